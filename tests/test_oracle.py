@@ -1,0 +1,303 @@
+"""Pins for the CPU oracle (no GPU).
+
+Each check ties the oracle to something other than itself: the discrete
+equation written in its original upwind max-form (eq. Eik_discr), exact
+solutions, brute-force value iteration, the convergence theorem's
+order-independence, FMM's monotone acceptance, Euclidean distance under grid
+refinement, and numbers printed in the paper (worked example, table).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1110_6220_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def upwind_equation_residual(U, F, h, src, mask=None):
+    """|LHS F^2 - 1| of eq. Eik_discr written with the one-sided difference
+    quotients D^{+-x}, D^{+-y} as defined in Section 2 (not the quadrant
+    shortcut the oracle uses); +inf outside the grid and on obstacles."""
+    ny, nx = U.shape
+    P = np.full((ny + 2, nx + 2), np.inf)
+    P[1:-1, 1:-1] = U
+    if mask is not None:
+        P[1:-1, 1:-1][mask == 0] = np.inf
+    C = P[1:-1, 1:-1]
+    with np.errstate(invalid="ignore"):
+        Dmx = (C - P[1:-1, :-2]) / h   # D^{-x} U
+        Dpx = (P[1:-1, 2:] - C) / h    # D^{+x} U
+        Dmy = (C - P[:-2, 1:-1]) / h
+        Dpy = (P[2:, 1:-1] - C) / h
+        tx = np.maximum(np.maximum(Dmx, -Dpx), 0.0)
+        ty = np.maximum(np.maximum(Dmy, -Dpy), 0.0)
+        lhs = tx * tx + ty * ty
+        res = np.abs(lhs * F * F - 1.0)
+    ok = np.isfinite(U)
+    if mask is not None:
+        ok &= mask != 0
+    ok.ravel()[np.asarray(src)] = False
+    return res, ok
+
+
+def assert_solves_discrete_system(U, w):
+    F, h = w["F"], w["h"]
+    res, ok = upwind_equation_residual(U, F, h, w["src"], w.get("mask"))
+    # cancellation in (U - U_nbr)/h: relative rounding ~ eps * U / (h / F)
+    delta = h / F
+    tol = 16 * np.finfo(float).eps * (np.where(np.isfinite(U), U, 0) + 1.0) / delta + 1e-12
+    bad = ok & ~(res <= tol)
+    assert not bad.any(), f"{bad.sum()} nodes violate eq. Eik_discr, worst {res[ok].max()}"
+
+
+def rel_diff(A, B):
+    fin = np.isfinite(B)
+    assert np.array_equal(fin, np.isfinite(A)), "different reachable sets"
+    d = np.abs(A[fin] - B[fin]) / np.maximum(np.abs(B[fin]), 1e-300)
+    return d.max() if d.size else 0.0
+
+
+# --------------------------------------------------------------------------
+# local update and closed forms
+# --------------------------------------------------------------------------
+
+def test_update_branches_and_infinities():
+    inf = math.inf
+    assert O.update(inf, inf, 0.3) == inf
+    assert O.update(2.0, inf, 0.3) == 2.3 and O.update(inf, 2.0, 0.3) == 2.3
+    assert O.update(1.0, 2.0, 0.5) == 1.5          # |a-b| >= delta: one-sided
+    assert O.update(1.0, 1.5, 0.5) == 1.5          # equality: the branches agree
+    for a, b, d in [(0.0, 0.0, 1.0), (0.3, 0.5, 0.7), (1.0, 1.2, 0.25)]:
+        U = O.update(a, b, d)
+        assert U >= max(a, b)
+        # quadratic of the two-sided update (eq. two_sided_update), h = F = ...
+        assert abs((U - a) ** 2 + (U - b) ** 2 - d * d) <= 8e-16 * max(U * U, 1.0)
+
+
+def test_point_source_first_nodes_solve_equation():
+    """Values next to a point source (F = 1, h = 1) satisfy eq. Eik_discr and
+    the first ones are the exact one-sided values 1 and 2."""
+    w = W._pack("t1", np.ones((7, 7)), 1.0, [3 * 7 + 3])
+    U = O.fmm(O.Problem.from_workload(w))
+    assert U[3, 4] == 1.0 and U[3, 5] == 2.0 and U[4, 3] == 1.0
+    assert_solves_discrete_system(U, w)
+    # survey-computed regression values (T1), checked here for stability only
+    assert U[4, 4] == pytest.approx(1.7071067811865475, abs=1e-15)
+    assert U[4, 5] == pytest.approx(2.545328925426122, abs=1e-15)
+    assert U[5, 5] == pytest.approx(3.25243570661267, abs=1e-14)
+
+
+def test_plane_front_and_strip_are_exact():
+    """Q = a full grid column, F = 1 => U = distance to the column exactly
+    (only one-sided updates occur); a 1-D strip gives U = k h."""
+    n, h = 12, 0.25
+    F = np.ones((9, n))
+    src = [j * n for j in range(9)]
+    w = W._pack("plane", F, h, src)
+    for solve in (O.fmm, lambda p: O.fsm(p)[0], lambda p: O.hcm(p, 4)[0]):
+        U = solve(O.Problem.from_workload(w))
+        assert np.array_equal(U, np.tile(np.arange(n) * h, (9, 1)))
+    strip = W._pack("strip", np.ones((1, 20)), 0.5, [0])
+    U = O.fmm(O.Problem.from_workload(strip))
+    assert np.array_equal(U[0], np.arange(20) * 0.5)
+
+
+# --------------------------------------------------------------------------
+# brute force and order-independence (convergence theorem)
+# --------------------------------------------------------------------------
+
+def _random_problems(count, seed, nmax=24):
+    rng = np.random.default_rng(seed)
+    for _ in range(count):
+        nx, ny = rng.integers(3, nmax + 1, size=2)
+        yield W.random_small(rng, int(nx), int(ny), obst=rng.uniform(0, 0.3),
+                             nsrc=int(rng.integers(1, 4)), q_spread=float(rng.choice([0.0, 0.3])))
+
+
+def test_value_iteration_equals_fmm():
+    for w in _random_problems(40, seed=11):
+        p = O.Problem.from_workload(w)
+        Uf = O.fmm(p)
+        Uj, _ = O.jacobi(p)
+        assert rel_diff(Uj, Uf) <= 1e-15
+        assert_solves_discrete_system(Uf, w)
+
+
+def test_exact_methods_agree():
+    """FMM, FSM, LSM and HCM at several cell sizes reach the same discrete
+    solution (Theorem of Section 3.2.1)."""
+    for w in _random_problems(30, seed=12, nmax=40):
+        p = O.Problem.from_workload(w)
+        Uf = O.fmm(p)
+        assert rel_diff(O.fsm(p)[0], Uf) <= 1e-15
+        assert rel_diff(O.lsm(p)[0], Uf) <= 1e-15
+        for s in (2, 3, 5, 8, 64):
+            assert rel_diff(O.hcm(p, s)[0], Uf) <= 1e-15
+
+
+def test_fmm_acceptance_is_monotone():
+    for w in list(_random_problems(10, seed=13, nmax=40)) + [W.smooth_sine(129)]:
+        p = O.Problem.from_workload(w)
+        U, order = O.fmm(p, want_order=True)
+        vals = U.ravel()[order]
+        ns = len(np.unique(w["src"]))
+        assert np.all(np.diff(vals[ns:]) >= 0.0)
+        assert np.isfinite(vals).all()
+        assert len(order) == np.isfinite(U).sum()
+
+
+def test_fixed_point_residual():
+    w = W.smooth_sine(257)
+    p = O.Problem.from_workload(w)
+    U = O.fmm(p)
+    r, _ = O.residual(p, U)
+    assert r <= 1e-13
+    # a planted error is visible to the residual
+    U2 = U.copy()
+    U2[100, 100] *= 1 + 1e-9
+    assert O.residual(p, U2)[0] > 1e-10
+
+
+def test_unreachable_and_obstacles_stay_infinite():
+    F = np.ones((9, 9))
+    mask = np.ones((9, 9), np.uint8)
+    mask[:, 4] = 0                     # a wall cutting the grid in two
+    w = W._pack("wall", F, 0.1, [2 * 9 + 1], mask=mask)
+    for U in (O.fmm(O.Problem.from_workload(w)), O.hcm(O.Problem.from_workload(w), 3)[0]):
+        assert np.isinf(U[:, 4:]).all() and np.isfinite(U[:, :4]).all()
+
+
+# --------------------------------------------------------------------------
+# Euclidean distance under refinement (F = 1, point source)
+# --------------------------------------------------------------------------
+
+def test_point_source_converges_to_distance():
+    errs = []
+    for n in (65, 129, 257, 513):
+        w = W.point_source_unit(n)
+        U = O.fmm(O.Problem.from_workload(w))
+        x = -1.0 + np.arange(n) * w["h"]
+        X, Y = np.meshgrid(x, x)
+        errs.append(np.abs(U - np.sqrt(X * X + Y * Y)).max())
+    orders = [math.log2(errs[k] / errs[k + 1]) for k in range(len(errs) - 1)]
+    assert all(0.7 <= o <= 1.1 for o in orders), orders
+    assert orders == sorted(orders)
+    assert errs[1] == pytest.approx(0.0218123, abs=5e-7)
+
+
+# --------------------------------------------------------------------------
+# two-scale methods
+# --------------------------------------------------------------------------
+
+def test_tiling_reading():
+    K, lo = O.tiling(129, 16)
+    assert K == 8 and lo[-1] == 129 and lo[-1] - lo[-2] == 17
+    assert O.tiling(1025, 64)[0] == 16 and O.tiling(1408, 64)[0] == 22
+    assert O.tiling(100, 16)[0] == 7 and O.tiling(5, 16)[0] == 1
+
+
+def test_approximate_methods_upper_bound_exact():
+    """FMSM and FHCM values never fall below the exact discrete solution."""
+    ws = list(_random_problems(15, seed=14, nmax=48)) + [W.smooth_sine(97)]
+    for w in ws:
+        p = O.Problem.from_workload(w)
+        U = O.fmm(p)
+        fin = np.isfinite(U)
+        for s in (4, 8, 16):
+            for V in (O.fmsm(p, s)[0], O.fhcm(p, s)[0]):
+                assert (V[fin] >= U[fin] * (1 - 1e-15)).all()
+                assert np.isinf(V[~fin]).all()
+
+
+def test_approximate_methods_exact_for_constant_speed():
+    """With F = 1 and a point source a causal cell order exists and FMSM and
+    FHCM add no error (Section 4.3, table tab:const: all ratios 1)."""
+    w = W.config(1)
+    p = O.Problem.from_workload(w)
+    U = O.fmm(p)
+    for s in (8, 16, 32):
+        assert rel_diff(O.fmsm(p, s)[0], U) <= 1e-15
+        assert rel_diff(O.fhcm(p, s)[0], U) <= 1e-15
+
+
+def _golden_grid(name):
+    rows = [list(map(int, ln.split())) for ln in open(os.path.join(GOLDEN, name))
+            if ln.strip() and not ln.startswith("#")]
+    return np.array(rows[::-1])  # row 0 = y = 1
+
+
+def test_coarse_checkerboard_acceptance_groups():
+    """Coarse FMM of the 5x5 checkerboard example: the sets of checkers
+    accepted at positions {0}, {1-4}, {5-8}, {9-12}, {13-20}, {21-24} of the
+    paper's numbering are the sets the oracle accepts at those positions
+    (order within a set of equal values is a heap tie-break)."""
+    num = _golden_grid("checkers5_coarse_order.txt")
+    jj, ii = np.mgrid[0:5, 0:5]
+    F = np.where((ii + jj) % 2 == 0, 1.0, 2.0)   # centre colour slow (F = 1)
+    w = W._pack("checkers5", F, 1.0, [2 * 5 + 2])
+    U, order = O.fmm(O.Problem.from_workload(w), want_order=True)
+    pos = np.empty(25, dtype=int)
+    pos[order] = np.arange(25)
+    pos = pos.reshape(5, 5)
+    for lo, hi in [(0, 0), (1, 4), (5, 8), (9, 12), (13, 20), (21, 24)]:
+        paper = (num >= lo) & (num <= hi)
+        mine = (pos >= lo) & (pos <= hi)
+        assert np.array_equal(paper, mine), (lo, hi)
+        assert np.ptp(U[paper]) == 0.0
+    assert sorted(set(np.round(U.ravel(), 7))) == [0.0, 0.5, 1.2071068, 1.5, 1.6753505, 2.3824573]
+
+
+def test_fmsm_sweep_directions_from_figure():
+    """Figure coarse_sweep_choice and the worked example: cell #1 sweeps from
+    NW and SW, cell #14 from NE only."""
+    SW, NW, NE, SE = 1, 2, 4, 8
+    Ws, Es, Ss, Ns = 1, 2, 4, 8
+    assert O.fmsm_dirs(Ws | Es | Ss | Ns) == SW | NW | NE | SE
+    assert O.fmsm_dirs(Ws | Ns | Es) == NW | NE
+    assert O.fmsm_dirs(Ws | Ns) == NW
+    assert O.fmsm_dirs(Ns) == NW | NE
+    num = _golden_grid("checkers5_coarse_order.txt")
+
+    def sides_earlier(label):
+        (j,), (i,) = np.nonzero(num == label)
+        s = 0
+        for bit, (di, dj) in ((Ws, (-1, 0)), (Es, (1, 0)), (Ss, (0, -1)), (Ns, (0, 1))):
+            a, b = i + di, j + dj
+            if 0 <= a < 5 and 0 <= b < 5 and num[b, a] < label:
+                s |= bit
+        return s
+
+    assert O.fmsm_dirs(sides_earlier(1)) == NW | SW
+    assert O.fmsm_dirs(sides_earlier(14)) == NE
+
+
+def test_fsm_sweep_count_constant_speed():
+    """F = 1 with a centre source: FSM needs 4 sweeps plus a confirming one
+    (Section 4.3, table tab:const, '# Sweeps' = 5)."""
+    for n in (9, 33, 129):
+        assert O.fsm(O.Problem.from_workload(W.point_source_unit(n)))[1] == 5
+
+
+@pytest.mark.slow
+def test_constant_speed_table_1408():
+    """F = 1 on 1408^2 with Q at the centre (the four nodes around it): FMSM's
+    AvS equals the printed table to the digits shown; HCM and FHCM remove
+    cells about once and every FHCM monotonicity check succeeds."""
+    n = 1408
+    src = [703 * n + 703, 703 * n + 704, 704 * n + 703, 704 * n + 704]
+    p = O.Problem(np.ones((n, n)), 1.0 / (n - 1), src)
+    rows = [ln.split() for ln in open(os.path.join(GOLDEN, "const_speed_1408_fmsm_avs.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    for cells, avs in rows:
+        s = n // int(cells)
+        _, st = O.fmsm(p, s)
+        assert round(st["AvS"], 3) == float(avs), (cells, st["AvS"])
+    for s in (64, 16):
+        _, sh = O.hcm(p, s)
+        _, sf = O.fhcm(p, s)
+        assert sh["AvHR"] <= 1.01 and sf["AvHR"] <= 1.01
+        assert sf["Mon%"] == 100.0
