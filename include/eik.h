@@ -1,0 +1,157 @@
+/*
+ * libeik -- two-scale Eikonal solvers on one AMD Instinct MI355X (gfx950).
+ *
+ * Solves the static Eikonal boundary-value problem |grad u(x)| F(x) = 1 on a
+ * uniform 2-D Cartesian grid with u = q on the exit set Q and a state
+ * constraint (q = +inf) on the rest of the boundary, discretised by the
+ * first-order upwind scheme (Chacon & Vladimirsky, "Fast two-scale methods for
+ * Eikonal equations", Section 2, eq. Eik_discr).  The grid is split into
+ * cells; each cell is swept by Gauss-Seidel sweeps (Algorithms FSM_order,
+ * FSM) and the cells are ordered at the coarse scale:
+ *   EIK_EXACT  label-correcting on cells (Algorithm generic_LC_cells, Heap-Cell
+ *              Method of Section 3.2.2): converges to the exact solution of the
+ *              discrete system regardless of processing order (the Theorem of
+ *              Section 3.2.1), so cells are processed concurrently;
+ *   EIK_FMSM   Fast Marching-Sweeping (Algorithm FMSM, Section 3.1): approximate;
+ *   EIK_FHCM   Fast Heap-Cell Method (Algorithm FHCM, Section 3.2.3): approximate.
+ *
+ * Layout: row-major with x fastest; node (i, j) <-> index j*nx + i and
+ * x_i = x0 + i*h.  All entry points return EIK_OK (0) or a negative
+ * eik_status; eik_last_error() returns a thread-local message for the last
+ * failure on the calling thread.  Inputs are validated before any output is
+ * written: on EIK_EINVAL the caller's u_out is untouched.
+ *
+ * Ownership: the caller owns every buffer passed in; the library never frees
+ * caller memory.  With device_ptrs = 1 every pointer (F, mask, src, q, u_out)
+ * is device memory of the current HIP device and the work is ordered on
+ * `stream`; the call returns once that work has completed.  With
+ * device_ptrs = 0 they are host memory and the library stages them through
+ * device buffers of its own.  Library workspace (per device) is allocated on
+ * first use, grows when a larger problem arrives and is kept until the
+ * process ends; calls on one device are serialised by a lock.
+ */
+#ifndef EIK_H
+#define EIK_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  EIK_OK = 0,
+  EIK_EINVAL = -1,   /* invalid argument (see eik_solve)                        */
+  EIK_ENOMEM = -2,   /* device or host allocation failed                        */
+  EIK_EDEVICE = -3,  /* a HIP runtime call failed                               */
+  EIK_EBUDGET = -4,  /* a request is larger than the whole serving budget       */
+  EIK_ENOTCONV = -5, /* the cell-visit guard tripped (max_cell_visits)          */
+  EIK_EBUSY = -6     /* serving: the request is still pending                   */
+} eik_status;
+
+typedef enum { EIK_F64 = 0, EIK_F32 = 1 } eik_dtype;
+typedef enum { EIK_EXACT = 0, EIK_FMSM = 1, EIK_FHCM = 2 } eik_method;
+
+typedef struct {
+  eik_dtype dtype;          /* storage and sweep precision of u and F          */
+  eik_method method;
+  int32_t cell;             /* cell side s in nodes, 4..64; 0 = tuned choice    */
+  double band;              /* band width of the cell queue, in units of u;
+                               0 = tuned choice                                 */
+  int32_t device_ptrs;      /* 1: all pointers are device memory                */
+  void* stream;             /* hipStream_t, or NULL for the null stream         */
+  uint64_t max_cell_visits; /* guard on total cell visits; 0 = 64 * cells + 1024 */
+  int32_t residual_check;   /* F32: recheck the fixed-point residual in FP64 and
+                               re-solve in FP64 when it exceeds 4 * 2^-24       */
+  int32_t workers;          /* persistent waves; 0 = chosen from the problem    */
+} eik_opts;
+
+typedef struct {
+  double seconds;           /* wall time of the call                            */
+  double kernel_seconds;    /* device time of the cell-processing kernel(s)     */
+  uint64_t cells;           /* number of cells J                                */
+  uint64_t cell_visits;     /* cell removals (AvHR = cell_visits / cells)       */
+  uint64_t sweeps;          /* productive sweeps (that changed a value)         */
+  uint64_t checks;          /* sweeps that changed nothing (AvS = (sweeps +
+                               checks) / cells)                                 */
+  uint64_t band_steps;      /* advances of the queue's lowest band              */
+  uint64_t mon_checks;      /* FHCM monotonicity checks                         */
+  uint64_t mon_ok;          /* ... that found a monotone side                   */
+  double max_residual;      /* max fixed-point residual |T(u)-u|/u (FP64), or -1
+                               when not computed                                */
+  int32_t cell_used;        /* cell side used                                   */
+  double band_used;         /* band width used                                  */
+  int32_t fell_back_to_f64; /* F32 residual check failed and FP64 re-solved     */
+} eik_stats;
+
+/* Solve one problem.
+ *   nx, ny  >= 1 grid nodes per axis; h > 0 finite grid spacing.
+ *   F       nx*ny values of `dtype`, > 0 and finite wherever mask == 1.
+ *   mask    nx*ny bytes, 1 = accessible, 0 = obstacle; NULL = all accessible.
+ *   src     nsrc >= 1 linear node indices of Q, each in range and accessible;
+ *           duplicates take the smallest q.
+ *   q       nsrc finite exit costs (FP64), NULL = all 0.
+ *   u_out   nx*ny values of `dtype`: the solution, +inf on obstacles and on
+ *           nodes with no accessible path to Q.
+ *   opts    NULL = defaults (F64, EXACT, tuned cell and band, host pointers).
+ *   stats   may be NULL.
+ * Errors: EINVAL (bad sizes, spacing, speeds, sources, enums, cell side
+ * outside [4, 64], an approximate method whose cell tiling has a cell wider
+ * than 64 nodes), ENOMEM, EDEVICE, ENOTCONV. */
+int eik_solve(int32_t nx, int32_t ny, double h, const void* F, const uint8_t* mask,
+              int32_t nsrc, const int64_t* src, const double* q, void* u_out,
+              const eik_opts* opts, eik_stats* stats);
+
+/* One problem of a batch (same meaning as the eik_solve arguments). */
+typedef struct {
+  int32_t nx, ny;
+  double h;
+  const void* F;
+  const uint8_t* mask;
+  int32_t nsrc;
+  const int64_t* src;
+  const double* q;
+  void* u_out;
+} eik_problem;
+
+/* Solve n independent problems in one persistent launch; all share `opts`
+   (dtype, method, cell, band, pointer kind, stream).  stats: n entries or
+   NULL; per-problem counters, with seconds/kernel_seconds of the whole batch.
+   Validation covers every problem before any work starts. */
+int eik_solve_batched(int32_t n, const eik_problem* probs, const eik_opts* opts,
+                      eik_stats* stats);
+
+/* Continuous-batching server.  Requests are copied to device memory owned by
+   the server and charged against hbm_budget_bytes; requests that do not fit
+   wait until earlier ones finish; a single request larger than the budget is
+   refused with EBUDGET.  Admitted requests join the running persistent work
+   at the next time slice and their cells are processed together with those
+   of requests already in flight.  opts.device_ptrs applies to the request's
+   input pointers; u_out is always host memory and must stay valid until
+   poll/wait reports completion. */
+typedef struct {
+  uint64_t hbm_budget_bytes;  /* device bytes for admitted requests; 0 = 64 GiB */
+  int32_t max_slots;          /* requests in flight at once; 0 = 1024          */
+  eik_opts opts;
+} eik_serve_cfg;
+
+typedef struct eik_server eik_server;
+
+int eik_serve_create(const eik_serve_cfg* cfg, eik_server** out);
+/* Copies the request's inputs and returns at once with a ticket. */
+int eik_serve_submit(eik_server* s, const eik_problem* p, uint64_t* ticket);
+/* EIK_OK when done (stats filled if non-NULL), EIK_EBUSY while pending. */
+int eik_serve_poll(eik_server* s, uint64_t ticket, eik_stats* stats);
+/* Blocks until the request is done. */
+int eik_serve_wait(eik_server* s, uint64_t ticket, eik_stats* stats);
+/* Cancels a request that has not been admitted yet; EBUSY if it already runs. */
+int eik_serve_cancel(eik_server* s, uint64_t ticket);
+/* Waits for requests in flight, then frees the server. */
+int eik_serve_destroy(eik_server* s);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char* eik_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EIK_H */

@@ -1,0 +1,186 @@
+"""Python binding of libeik (argument marshalling only).
+
+Every entry point forwards to the C ABI of ``include/eik.h`` in ``libeik.so``;
+all computation happens in the library's HIP kernels.  numpy arrays are passed
+as host pointers (the library stages them); torch tensors on a ROCm device are
+passed as device pointers and the work is ordered on torch's current stream.
+There is no fallback: if the library is not built, importing fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libeik.so")
+
+EIK_OK, EIK_EINVAL, EIK_ENOMEM, EIK_EDEVICE, EIK_EBUDGET, EIK_ENOTCONV, EIK_EBUSY = 0, -1, -2, -3, -4, -5, -6
+F64, F32 = 0, 1
+METHODS = {"exact": 0, "hcm": 0, "fmsm": 1, "fhcm": 2}
+
+# Every function include/eik.h declares.
+EXPORTS = ("eik_solve", "eik_solve_batched", "eik_serve_create", "eik_serve_submit",
+           "eik_serve_poll", "eik_serve_wait", "eik_serve_cancel", "eik_serve_destroy",
+           "eik_last_error")
+
+
+class EikError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libeik error {code}: {msg}")
+        self.code = code
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int), ("method", ctypes.c_int), ("cell", ctypes.c_int32),
+                ("band", ctypes.c_double), ("device_ptrs", ctypes.c_int32),
+                ("stream", ctypes.c_void_p), ("max_cell_visits", ctypes.c_uint64),
+                ("residual_check", ctypes.c_int32), ("workers", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("seconds", ctypes.c_double), ("kernel_seconds", ctypes.c_double),
+                ("cells", ctypes.c_uint64), ("cell_visits", ctypes.c_uint64),
+                ("sweeps", ctypes.c_uint64), ("checks", ctypes.c_uint64),
+                ("band_steps", ctypes.c_uint64), ("mon_checks", ctypes.c_uint64),
+                ("mon_ok", ctypes.c_uint64), ("max_residual", ctypes.c_double),
+                ("cell_used", ctypes.c_int32), ("band_used", ctypes.c_double),
+                ("fell_back_to_f64", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        cells = max(int(self.cells), 1)
+        d["AvHR"] = self.cell_visits / cells
+        d["AvS"] = (self.sweeps + self.checks) / cells
+        return d
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("h", ctypes.c_double),
+                ("F", ctypes.c_void_p), ("mask", ctypes.c_void_p), ("nsrc", ctypes.c_int32),
+                ("src", ctypes.c_void_p), ("q", ctypes.c_void_p), ("u_out", ctypes.c_void_p)]
+
+
+class ServeCfg(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int32),
+                ("opts", Opts)]
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(paper_1110_6220_amd/build.py) first")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32 = ctypes.c_void_p, ctypes.c_int32
+    L.eik_solve.argtypes = [i32, i32, ctypes.c_double, vp, vp, i32, vp, vp, vp,
+                            ctypes.POINTER(Opts), ctypes.POINTER(Stats)]
+    L.eik_solve_batched.argtypes = [i32, ctypes.POINTER(Problem), ctypes.POINTER(Opts),
+                                    ctypes.POINTER(Stats)]
+    L.eik_serve_create.argtypes = [ctypes.POINTER(ServeCfg), ctypes.POINTER(vp)]
+    L.eik_serve_submit.argtypes = [vp, ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_uint64)]
+    L.eik_serve_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(Stats)]
+    L.eik_serve_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(Stats)]
+    L.eik_serve_cancel.argtypes = [vp, ctypes.c_uint64]
+    L.eik_serve_destroy.argtypes = [vp]
+    L.eik_last_error.restype = ctypes.c_char_p
+    return L
+
+
+lib = _load()
+
+
+def last_error() -> str:
+    return lib.eik_last_error().decode()
+
+
+def _check(rc: int) -> None:
+    if rc != EIK_OK:
+        raise EikError(rc, last_error())
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _opts(dtype, method, cell, band, device, stream, residual_check, workers, max_cell_visits):
+    return Opts(dtype, METHODS[method], int(cell), float(band), int(device),
+                stream, int(max_cell_visits), int(bool(residual_check)), int(workers))
+
+
+def _marshal(F, h, src, q, mask, u_out, dtype):
+    """Returns (Problem, keepalive, u_out, device, dtype code)."""
+    if _is_torch(F):
+        import torch
+        dev = F.device
+        tdt = torch.float64 if dtype == "f64" else torch.float32
+        F = F.to(tdt).contiguous()
+        srct = torch.as_tensor(np.asarray(src, dtype=np.int64).ravel() if not _is_torch(src) else src,
+                               device=dev).to(torch.int64).contiguous()
+        qt = None if q is None else torch.as_tensor(q, device=dev).to(torch.float64).contiguous()
+        mt = None if mask is None else torch.as_tensor(mask, device=dev).to(torch.uint8).contiguous()
+        if u_out is None:
+            u_out = torch.empty_like(F)
+        ny, nx = F.shape
+        p = Problem(nx, ny, float(h), F.data_ptr(), None if mt is None else mt.data_ptr(),
+                    srct.numel(), srct.data_ptr(), None if qt is None else qt.data_ptr(),
+                    u_out.data_ptr())
+        return p, (F, srct, qt, mt, u_out), u_out, True
+    ndt = np.float64 if dtype == "f64" else np.float32
+    F = np.ascontiguousarray(F, dtype=ndt)
+    srca = np.ascontiguousarray(np.atleast_1d(src), dtype=np.int64)
+    qa = None if q is None else np.ascontiguousarray(np.atleast_1d(q), dtype=np.float64)
+    ma = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    if u_out is None:
+        u_out = np.empty_like(F)
+    ny, nx = F.shape
+    p = Problem(nx, ny, float(h), F.ctypes.data, None if ma is None else ma.ctypes.data,
+                len(srca), srca.ctypes.data, None if qa is None else qa.ctypes.data,
+                u_out.ctypes.data)
+    return p, (F, srca, qa, ma, u_out), u_out, False
+
+
+def _stream_of(device: bool):
+    if not device:
+        return None
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def eik_solve(F, h, src, q=None, mask=None, u_out=None, *, dtype="f64", method="exact",
+              cell=0, band=0.0, workers=0, residual_check=False, max_cell_visits=0):
+    """Solves |grad u| F = 1 with u = q on src (see include/eik.h).
+    Returns (u, stats dict)."""
+    p, keep, u_out, device = _marshal(F, h, src, q, mask, u_out, dtype)
+    o = _opts(F64 if dtype == "f64" else F32, method, cell, band, device, _stream_of(device),
+              residual_check, workers, max_cell_visits)
+    st = Stats()
+    _check(lib.eik_solve(p.nx, p.ny, p.h, p.F, p.mask, p.nsrc, p.src, p.q, p.u_out,
+                         ctypes.byref(o), ctypes.byref(st)))
+    del keep
+    return u_out, st.as_dict()
+
+
+def eik_solve_batched(problems, *, dtype="f64", method="exact", cell=0, band=0.0, workers=0,
+                      residual_check=False, max_cell_visits=0):
+    """problems: list of dicts with F, h, src and optional q, mask, u_out.
+    Returns (list of u, list of stats dicts)."""
+    ps, keeps, outs = [], [], []
+    device = None
+    for w in problems:
+        p, keep, u, dev = _marshal(w["F"], w["h"], w["src"], w.get("q"), w.get("mask"),
+                                   w.get("u_out"), dtype)
+        if device is None:
+            device = dev
+        elif device != dev:
+            raise ValueError("all problems of a batch must be host or all device arrays")
+        ps.append(p)
+        keeps.append(keep)
+        outs.append(u)
+    arr = (Problem * len(ps))(*ps)
+    o = _opts(F64 if dtype == "f64" else F32, method, cell, band, device, _stream_of(device),
+              residual_check, workers, max_cell_visits)
+    st = (Stats * len(ps))()
+    _check(lib.eik_solve_batched(len(ps), arr, ctypes.byref(o), st))
+    del keeps
+    return outs, [s.as_dict() for s in st]

@@ -1,0 +1,60 @@
+"""The C-ABI library loads and exports every entry point include/eik.h
+declares (no compute calls: this runs without a GPU)."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "eik.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(eik_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_api():
+    names = declared_functions()
+    assert "eik_solve" in names and "eik_solve_batched" in names and "eik_last_error" in names
+    assert {"eik_serve_create", "eik_serve_submit", "eik_serve_poll", "eik_serve_wait",
+            "eik_serve_cancel", "eik_serve_destroy"} <= set(names)
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1110_6220_amd import eik
+    lib = ctypes.CDLL(eik.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(declared_functions()) == set(eik.EXPORTS)
+
+
+def test_invalid_arguments_are_rejected_before_device_work():
+    """Argument checks that need no device: sizes, spacing, enums, cell side."""
+    import numpy as np
+    from paper_1110_6220_amd import eik
+    F = np.ones((4, 4))
+    u = np.full((4, 4), 7.0)
+    for kw in [dict(cell=3), dict(cell=65), dict(method="nope")]:
+        try:
+            eik.eik_solve(F, 0.1, [0], u_out=u, **kw)
+        except (eik.EikError, KeyError):
+            pass
+        else:
+            raise AssertionError(kw)
+    for h in (0.0, -1.0, float("inf"), float("nan")):
+        try:
+            eik.eik_solve(F, h, [0], u_out=u)
+        except eik.EikError as e:
+            assert e.code == eik.EIK_EINVAL
+        else:
+            raise AssertionError(h)
+    bad = F.copy()
+    bad[1, 1] = 0.0
+    for args in [(bad, 0.1, [0]), (F, 0.1, [16]), (F, 0.1, [-1])]:
+        try:
+            eik.eik_solve(*args, u_out=u)
+        except eik.EikError as e:
+            assert e.code == eik.EIK_EINVAL
+        else:
+            raise AssertionError(args)
+    assert (u == 7.0).all()  # untouched
