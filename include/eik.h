@@ -51,18 +51,42 @@ typedef enum {
 typedef enum { EIK_F64 = 0, EIK_F32 = 1 } eik_dtype;
 typedef enum { EIK_EXACT = 0, EIK_FMSM = 1, EIK_FHCM = 2 } eik_method;
 
+/* Order in which cells are processed.
+ *   COARSE  a cell starts once its neighbours that precede it in the
+ *           acceptance order of Fast Marching on the grid of cell centres
+ *           (FMSM Part I, Section 3.1) have been processed once; afterwards
+ *           cells are re-queued by the label-correcting add criterion.  The
+ *           only order FMSM uses, and the default for EXACT.
+ *   BANDS   cells are taken from the lowest open bands of their cell values
+ *           (eq. cell_value; the Heap-Cell Methods' heap with ties widened to
+ *           a band of width `band`).  The default for FHCM.
+ *   FIFO    cells are taken in the order they were queued.
+ * EXACT gives the same result under every order. */
+typedef enum {
+  EIK_SCHED_AUTO = 0,
+  EIK_SCHED_COARSE = 1,
+  EIK_SCHED_BANDS = 2,
+  EIK_SCHED_FIFO = 3
+} eik_schedule;
+
 typedef struct {
   eik_dtype dtype;          /* storage and sweep precision of u and F          */
   eik_method method;
   int32_t cell;             /* cell side s in nodes, 4..64; 0 = tuned choice    */
-  double band;              /* band width of the cell queue, in units of u;
-                               0 = tuned choice                                 */
+  double band;              /* BANDS: band width in units of u; 0 = one cell
+                               crossing at unit speed (s * h)                   */
   int32_t device_ptrs;      /* 1: all pointers are device memory                */
   void* stream;             /* hipStream_t, or NULL for the null stream         */
   uint64_t max_cell_visits; /* guard on total cell visits; 0 = 64 * cells + 1024 */
   int32_t residual_check;   /* F32: recheck the fixed-point residual in FP64 and
                                re-solve in FP64 when it exceeds 4 * 2^-24       */
   int32_t workers;          /* persistent waves; 0 = chosen from the problem    */
+  int32_t band_window;      /* bands above the lowest unfinished band whose
+                               cells may start, 0..63 (band <= 0: unused)       */
+  int32_t eager_publish;    /* 1: re-queue neighbours after every sweep that
+                               changed a value; 0: once per removal, after the
+                               cell converged (the paper's order)              */
+  int32_t schedule;         /* eik_schedule                                     */
 } eik_opts;
 
 typedef struct {
@@ -81,6 +105,8 @@ typedef struct {
   int32_t cell_used;        /* cell side used                                   */
   double band_used;         /* band width used                                  */
   int32_t fell_back_to_f64; /* F32 residual check failed and FP64 re-solved     */
+  uint64_t cells_total;     /* cells of the whole launch (batches: all problems;
+                               visit and sweep counters are launch totals)      */
 } eik_stats;
 
 /* Solve one problem.

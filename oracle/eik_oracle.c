@@ -860,24 +860,28 @@ int orc_fmsm(const orc_problem* p, int32_t s, double* V, int64_t* order_out,
   }
   /* Part I.  Coarse grid of cell centres, h^c = s h.  READING: coarse speed is
      the mean of F over the cell's accessible nodes (an all-obstacle cell is a
-     coarse obstacle); a cell holding sources is a coarse source with the
-     smallest of their q. */
+     coarse obstacle), summed column by column (each column bottom to top,
+     then the column sums left to right); a cell holding sources is a coarse
+     source with the smallest of their q. */
   long nsc = 0;
   for (long c = 0; c < J; ++c) {
     int x0, x1, y0, y1, cnt = 0, has = 0;
     double sum = 0.0, qmin = INF;
     cell_box(&C, c, &x0, &x1, &y0, &y1);
-    for (int j = y0; j < y1; ++j)
-      for (int i = x0; i < x1; ++i) {
+    for (int i = x0; i < x1; ++i) {
+      double col = 0.0;
+      for (int j = y0; j < y1; ++j) {
         long k = (long)j * g.nx + i;
         if (!g.acc[k]) continue;
-        sum += g.F[k];
+        col += g.F[k];
         cnt++;
         if (g.src[k]) {
           has = 1;
           if (g.qv[k] < qmin) qmin = g.qv[k];
         }
       }
+      sum += col;
+    }
     mc[c] = cnt > 0;
     Fc[c] = cnt > 0 ? sum / cnt : 1.0;
     if (has) {

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -16,8 +17,9 @@
 
 #include "../../include/eik.h"
 #include "engine.h"
+#include "internal.h"
 
-namespace {
+namespace eik {
 
 thread_local std::string g_err;
 
@@ -31,54 +33,35 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
-#define HIP_TRY(expr)                                                              \
-  do {                                                                             \
-    hipError_t e_ = (expr);                                                        \
-    if (e_ != hipSuccess)                                                          \
-      return fail(EIK_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));     \
-  } while (0)
-
 double now_s() {
   using namespace std::chrono;
   return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
-// ---------------------------------------------------------------------------
-// device buffers
-// ---------------------------------------------------------------------------
+// EIK_PROFILE=1 makes the solver accumulate per-phase wall-clock ticks,
+// reported on stderr after each call (a diagnostic, off by default).
+static const bool g_profile = [] {
+  const char* v = std::getenv("EIK_PROFILE");
+  return v && v[0] == '1';
+}();
+// EIK_TRACE=<file> records one line per cell visit of the main solve
+// (cell, sweeps, checks, ready, popped, loaded, swept, done in wall-clock
+// ticks, hardware id) into <file> after each call (a diagnostic).
+static const char* g_trace = std::getenv("EIK_TRACE");
 
-struct DevBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-  hipError_t ensure(size_t need) {
-    if (need <= bytes) return hipSuccess;
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    bytes = 0;
-    size_t b = std::max<size_t>(need, 256);
-    hipError_t e = hipMalloc(&p, b);
-    if (e == hipSuccess) bytes = b;
-    return e;
-  }
-  template <typename T>
-  T* as() const { return static_cast<T*>(p); }
-};
+hipError_t DevBuf::ensure(size_t need) {
+  if (need <= bytes) return hipSuccess;
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+  const size_t b = std::max<size_t>(need, 256);
+  hipError_t e = hipMalloc(&p, b);
+  if (e == hipSuccess) bytes = b;
+  return e;
+}
 
-// Workspace of one device: reused by every call on that device.
-struct Workspace {
-  std::mutex mu;
-  DevBuf delta, st, visits, cell_inst, key, slot, head, tail, cursor, ctl, inst;
-  // staging for host pointers
-  DevBuf F, u, mask, src, q;
-  eik::Ctl* ctl_host = nullptr;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  int cus = 0;
-  int wall_khz = 0;
-  bool ready = false;
-};
-
-std::mutex g_ws_mu;
-std::vector<std::unique_ptr<Workspace>> g_ws;
+static std::mutex g_ws_mu;
+static std::vector<std::unique_ptr<Workspace>> g_ws;
 
 int workspace(Workspace** out) {
   int dev = 0;
@@ -88,7 +71,7 @@ int workspace(Workspace** out) {
   if (!g_ws[dev]) g_ws[dev].reset(new Workspace());
   Workspace* w = g_ws[dev].get();
   if (!w->ready) {
-    HIP_TRY(hipHostMalloc((void**)&w->ctl_host, sizeof(eik::Ctl), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void**)&w->ctl_host, 2 * sizeof(Ctl), hipHostMallocDefault));
     HIP_TRY(hipEventCreate(&w->ev0));
     HIP_TRY(hipEventCreate(&w->ev1));
     HIP_TRY(hipDeviceGetAttribute(&w->cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -120,18 +103,15 @@ int check_opts(const eik_opts& o) {
     return fail(EIK_EINVAL, "cell side %d outside [4, 64]", (int)o.cell);
   if (!(o.band == o.band) || std::isinf(o.band)) return fail(EIK_EINVAL, "band must be finite");
   if (o.workers < 0) return fail(EIK_EINVAL, "workers must be >= 0");
-  if (o.method != EIK_EXACT)
-    return fail(EIK_EINVAL, "method %d is not available in this build", (int)o.method);
+  if (o.band_window < 0 || o.band_window > 63) return fail(EIK_EINVAL, "band_window outside [0, 63]");
+  if (o.schedule < EIK_SCHED_AUTO || o.schedule > EIK_SCHED_FIFO)
+    return fail(EIK_EINVAL, "unknown schedule %d", (int)o.schedule);
+  if (o.method == EIK_FMSM && o.schedule != EIK_SCHED_AUTO && o.schedule != EIK_SCHED_COARSE)
+    return fail(EIK_EINVAL, "FMSM processes cells in the coarse order only");
+  if (o.method == EIK_FHCM && o.schedule == EIK_SCHED_COARSE)
+    return fail(EIK_EINVAL, "FHCM orders cells by their cell values");
   return EIK_OK;
 }
-
-// Standard tiling: K = ceil(n/s) cells of s nodes, a last cell of one node
-// merged into its predecessor.  If that leaves a cell wider than 64 nodes the
-// exact method uses the balanced tiling (K = ceil(n/s) cells of floor/ceil
-// n/K nodes); its result does not depend on the tiling.
-struct Tiling {
-  int s, kx, ky, balanced, extent;
-};
 
 int std_cells(int n, int s) {
   int K = (n + s - 1) / s;
@@ -139,6 +119,10 @@ int std_cells(int n, int s) {
   return K;
 }
 
+// Standard tiling: K = ceil(n/s) cells of s nodes, a last cell of one node
+// merged into its predecessor.  If that leaves a cell wider than 64 nodes the
+// exact method uses the balanced tiling (K = ceil(n/s) cells of floor/ceil
+// n/K nodes); its result does not depend on the tiling.
 int make_tiling(int nx, int ny, int s, int method, Tiling* t) {
   t->s = s;
   t->kx = std_cells(nx, s);
@@ -157,14 +141,19 @@ int make_tiling(int nx, int ny, int s, int method, Tiling* t) {
   return EIK_OK;
 }
 
-int tile_for(int extent) { return extent <= 16 ? 16 : extent <= 32 ? 32 : 64; }
+static int tile_for(int extent) { return extent <= 16 ? 16 : extent <= 32 ? 32 : 64; }
 
-int default_cell(int nx, int ny) {
+int default_cell(int nx, int ny, int method) {
   const int n = std::max(nx, ny);
+  if (method != EIK_EXACT) {
+    // approximate methods need the standard tiling within 64 nodes
+    if (n >= 512 && (nx % 64 != 1) && (ny % 64 != 1)) return 64;
+    return n >= 160 ? 32 : 16;
+  }
   return n >= 512 ? 64 : n >= 160 ? 32 : 16;
 }
 
-uint32_t pow2_at_least(uint64_t v) {
+static uint32_t pow2_at_least(uint64_t v) {
   uint32_t p = 1;
   while (p < v) p <<= 1;
   return p;
@@ -201,35 +190,111 @@ int validate_shape(const eik_problem& p) {
 }
 
 // ---------------------------------------------------------------------------
-// the solve driver shared by eik_solve and eik_solve_batched
+// engine set-up
 // ---------------------------------------------------------------------------
 
-int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats) {
+// Sizes the solver's buffers for the instances in `inst` (cell0 filled in
+// here) and fills the engine arguments.
+static int setup_engine(Solver& sv, std::vector<Inst>& inst, int dtype, int method, int dag,
+                        double band, int window, int eager, uint64_t guard, uint64_t timeout,
+                        hipStream_t stream, Engine* out) {
+  int64_t J = 0;
+  for (auto& I : inst) {
+    I.cell0 = (int32_t)J;
+    J += (int64_t)I.kx * I.ky;
+  }
+  if (J > (1ll << 30)) return fail(EIK_EINVAL, "too many cells");
+  const uint32_t nb = band > 0.0 ? 64u : 1u;
+  const uint32_t cap = pow2_at_least((uint64_t)J + 1);
+  const int n = (int)inst.size();
+  HIP_TRY(sv.st.ensure(J * sizeof(uint32_t)));
+  HIP_TRY(sv.visits.ensure(J * sizeof(uint32_t)));
+  HIP_TRY(sv.key.ensure(J * sizeof(uint32_t)));
+  HIP_TRY(sv.cell_inst.ensure(n > 1 ? J * sizeof(int32_t) : 4));
+  HIP_TRY(sv.deps.ensure(dag ? J * sizeof(int32_t) : 4));
+  HIP_TRY(sv.ord.ensure(dag ? J : 4));
+  HIP_TRY(sv.slot.ensure((size_t)cap * nb * sizeof(unsigned long long)));
+  HIP_TRY(sv.head.ensure((size_t)nb * kCtrStride * sizeof(unsigned long long)));
+  HIP_TRY(sv.tail.ensure((size_t)nb * kCtrStride * sizeof(unsigned long long)));
+  HIP_TRY(sv.inflight.ensure((size_t)nb * kCtrStride * sizeof(unsigned long long)));
+  HIP_TRY(sv.cursor.ensure(128));
+  HIP_TRY(sv.ctl.ensure(sizeof(Ctl)));
+  HIP_TRY(sv.inst.ensure(n * sizeof(Inst)));
+  HIP_TRY(hipMemcpyAsync(sv.inst.p, inst.data(), n * sizeof(Inst), hipMemcpyHostToDevice, stream));
+  Engine& e = *out;
+  std::memset(&e, 0, sizeof e);
+  e.inst = sv.inst.as<Inst>();
+  e.one = inst[0];
+  e.args_inst = n == 1;
+  e.ninst = n;
+  e.ncells = (int32_t)J;
+  e.method = method;
+  e.dtype = dtype;
+  e.dag = dag;
+  e.st = sv.st.as<uint32_t>();
+  e.visits = sv.visits.as<uint32_t>();
+  e.cell_inst = sv.cell_inst.as<int32_t>();
+  e.key = sv.key.as<unsigned int>();
+  e.deps = sv.deps.as<int32_t>();
+  e.ord = sv.ord.as<uint8_t>();
+  e.q.slot = sv.slot.as<unsigned long long>();
+  e.q.head = sv.head.as<unsigned long long>();
+  e.q.tail = sv.tail.as<unsigned long long>();
+  e.q.inflight = sv.inflight.as<unsigned long long>();
+  e.q.cursor = sv.cursor.as<unsigned long long>();
+  e.q.cap = cap;
+  e.q.nb = nb;
+  e.q.window = (uint32_t)window;
+  e.q.inv_width = band > 0.0 ? 1.0 / band : 0.0;
+  e.ctl = sv.ctl.as<Ctl>();
+  e.eager = eager;
+  e.profile = g_profile;
+  e.guard = guard ? guard : 64ull * (uint64_t)J + 1024ull;
+  e.timeout_ticks = timeout;
+  return EIK_OK;
+}
+
+static int default_workers(const Workspace* ws, int64_t J, int tile, int dtype, int n) {
+  const int per_cu = tile == 64 ? (dtype == EIK_F64 ? 2 : 4) : tile == 32 ? 8 : 16;
+  int64_t w = std::min<int64_t>(J, (int64_t)ws->cus * per_cu);
+  if (n == 1) w = std::min<int64_t>(w, 128);
+  return (int)std::max<int64_t>(w, 1);
+}
+
+// ---------------------------------------------------------------------------
+// the solve driver shared by eik_solve, eik_solve_batched and the server
+// ---------------------------------------------------------------------------
+
+int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, RunInfo* info) {
   const double t0 = now_s();
   Workspace* ws = nullptr;
   int rc = workspace(&ws);
   if (rc) return rc;
-  std::lock_guard<std::mutex> lk(ws->mu);
+  std::unique_lock<std::mutex> lk(ws->mu);
   hipStream_t stream = static_cast<hipStream_t>(o.stream);
   const int dt = o.dtype;
   const size_t es = dsize(dt);
+  const int method = o.method;
+  int sched = o.schedule;
+  if (sched == EIK_SCHED_AUTO) sched = method == EIK_FHCM ? EIK_SCHED_BANDS : EIK_SCHED_COARSE;
+  const bool dag = sched == EIK_SCHED_COARSE;
 
   // tiling and sizes per instance
-  std::vector<eik::Inst> inst(n);
+  std::vector<Inst> inst(n);
   std::vector<Tiling> til(n);
-  int64_t total_nodes = 0, max_nodes = 0, total_cells = 0, max_src = 0;
+  int64_t total_nodes = 0, max_nodes = 0, max_src = 0;
   int extent = 0;
+  double hs_max = 0.0;
   for (int k = 0; k < n; ++k) {
     const eik_problem& p = probs[k];
-    const int s = o.cell ? o.cell : default_cell(p.nx, p.ny);
-    if ((rc = make_tiling(p.nx, p.ny, s, o.method, &til[k]))) return rc;
+    const int s = o.cell ? o.cell : default_cell(p.nx, p.ny, method);
+    if ((rc = make_tiling(p.nx, p.ny, s, method, &til[k]))) return rc;
     extent = std::max(extent, til[k].extent);
     total_nodes += (int64_t)p.nx * p.ny;
     max_nodes = std::max<int64_t>(max_nodes, (int64_t)p.nx * p.ny);
-    total_cells += (int64_t)til[k].kx * til[k].ky;
     max_src = std::max<int64_t>(max_src, p.nsrc);
+    hs_max = std::max(hs_max, p.h * til[k].s);
   }
-  if (total_cells > (1ll << 30)) return fail(EIK_EINVAL, "too many cells");
 
   // staging of host inputs
   const bool dev = o.device_ptrs != 0;
@@ -245,13 +310,12 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats) {
     HIP_TRY(ws->src.ensure(nsrc * sizeof(int64_t)));
     HIP_TRY(ws->q.ensure(nsrc * sizeof(double)));
   }
-  HIP_TRY(ws->delta.ensure(total_nodes * es));
+  HIP_TRY(ws->fine.delta.ensure(total_nodes * es));
   int64_t off = 0, moff = 0, soff = 0;
-  int64_t cell0 = 0;
   for (int k = 0; k < n; ++k) {
     const eik_problem& p = probs[k];
     const int64_t nn = (int64_t)p.nx * p.ny;
-    eik::Inst& I = inst[k];
+    Inst& I = inst[k];
     std::memset(&I, 0, sizeof I);
     I.h = p.h;
     I.nx = p.nx;
@@ -260,9 +324,8 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats) {
     I.kx = til[k].kx;
     I.ky = til[k].ky;
     I.balanced = til[k].balanced;
-    I.cell0 = (int32_t)cell0;
     I.nsrc = p.nsrc;
-    I.delta = ws->delta.as<char>() + off * es;
+    I.delta = ws->fine.delta.as<char>() + off * es;
     if (dev) {
       I.u = p.u_out;
       I.F = p.F;
@@ -287,90 +350,147 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats) {
       soff += p.nsrc;
     }
     off += nn;
-    cell0 += (int64_t)I.kx * I.ky;
   }
 
-  // cell state, queue, control block
-  const uint32_t J = (uint32_t)total_cells;
-  double band = o.band;
-  if (band == 0.0) {
-    // default band: one cell crossing at unit speed
-    double hs = 0.0;
-    for (int k = 0; k < n; ++k) hs = std::max(hs, probs[k].h * til[k].s);
-    band = hs;
-  }
-  const uint32_t nb = band > 0.0 ? 64u : 1u;
-  const uint32_t cap = pow2_at_least((uint64_t)J + 1);
-  HIP_TRY(ws->st.ensure(J * sizeof(uint32_t)));
-  HIP_TRY(ws->visits.ensure(J * sizeof(uint32_t)));
-  HIP_TRY(ws->key.ensure(J * sizeof(uint32_t)));
-  HIP_TRY(ws->cell_inst.ensure(n > 1 ? J * sizeof(int32_t) : 4));
-  HIP_TRY(ws->slot.ensure((size_t)cap * nb * sizeof(unsigned long long)));
-  HIP_TRY(ws->head.ensure((size_t)nb * eik::kCtrStride * sizeof(unsigned long long)));
-  HIP_TRY(ws->tail.ensure((size_t)nb * eik::kCtrStride * sizeof(unsigned long long)));
-  HIP_TRY(ws->cursor.ensure(128));
-  HIP_TRY(ws->ctl.ensure(sizeof(eik::Ctl)));
-  if (n > 1) {
-    HIP_TRY(ws->inst.ensure(n * sizeof(eik::Inst)));
-    HIP_TRY(hipMemcpyAsync(ws->inst.p, inst.data(), n * sizeof(eik::Inst), hipMemcpyHostToDevice, stream));
-  }
-
-  eik::Engine e;
-  std::memset(&e, 0, sizeof e);
-  e.inst = n > 1 ? ws->inst.as<eik::Inst>() : nullptr;
-  e.one = inst[0];
-  e.ninst = n;
-  e.ncells = (int32_t)J;
-  e.method = o.method;
-  e.dtype = dt;
-  e.st = ws->st.as<uint32_t>();
-  e.visits = ws->visits.as<uint32_t>();
-  e.cell_inst = ws->cell_inst.as<int32_t>();
-  e.key = ws->key.as<unsigned int>();
-  e.q.slot = ws->slot.as<unsigned long long>();
-  e.q.head = ws->head.as<unsigned long long>();
-  e.q.tail = ws->tail.as<unsigned long long>();
-  e.q.cursor = ws->cursor.as<unsigned long long>();
-  e.q.cap = cap;
-  e.q.nb = nb;
-  e.q.inv_width = band > 0.0 ? 1.0 / band : 0.0;
-  e.ctl = ws->ctl.as<eik::Ctl>();
-  e.guard = o.max_cell_visits ? o.max_cell_visits : 64ull * J + 1024ull;
-  e.timeout_ticks = (unsigned long long)ws->wall_khz * 1000ull * 10ull;  // 10 s
-
+  double band = -1.0;
+  if (sched == EIK_SCHED_BANDS) band = o.band > 0.0 ? o.band : hs_max;  // one cell crossing at unit speed
+  const uint64_t timeout = (uint64_t)ws->wall_khz * 1000ull * 10ull;  // 10 s
+  Engine e;
+  if ((rc = setup_engine(ws->fine, inst, dt, method, dag, band, o.band_window, o.eager_publish,
+                         o.max_cell_visits, timeout, stream, &e)))
+    return rc;
+  const int64_t J = e.ncells;
   const int tile = tile_for(extent);
-  int workers = o.workers;
-  if (workers == 0) {
-    const int per_cu = tile == 64 ? (dt == EIK_F64 ? 2 : 4) : tile == 32 ? 8 : 16;
-    workers = (int)std::min<int64_t>(J, (int64_t)ws->cus * per_cu);
-    if (n == 1) workers = std::min(workers, 256);
-  }
-  workers = std::max(workers, 1);
+  const int workers = o.workers ? o.workers : default_workers(ws, J, tile, dt, n);
 
-  HIP_TRY(eik::launch_prepare(e, max_nodes, stream));
+  const unsigned trace_cap = 1u << 20;
+  if (g_trace) {
+    HIP_TRY(ws->ready_at.ensure(J * 8));
+    HIP_TRY(ws->trace.ensure((size_t)trace_cap * 64));
+    HIP_TRY(ws->trace_n.ensure(4));
+    HIP_TRY(hipMemsetAsync(ws->trace_n.p, 0, 4, stream));
+    HIP_TRY(hipMemsetAsync(ws->ready_at.p, 0, J * 8, stream));
+    e.ready_at = ws->ready_at.as<unsigned long long>();
+    e.trace = ws->trace.as<unsigned long long>();
+    e.trace_n = ws->trace_n.as<unsigned int>();
+    e.trace_cap = trace_cap;
+  }
+  HIP_TRY(launch_prepare(e, max_nodes, stream));
+  Engine ce;
+  bool have_coarse = false;
+  if (dag) {
+    // FMSM Part I on every instance: coarse speeds, exit cells, and an exact
+    // solve on the grid of cell centres with spacing h^c = s h
+    HIP_TRY(ws->cF.ensure(J * sizeof(double)));
+    HIP_TRY(ws->cmask.ensure(J));
+    HIP_TRY(ws->cq.ensure(J * sizeof(double)));
+    HIP_TRY(ws->cu.ensure(J * sizeof(double)));
+    HIP_TRY(ws->coarse.delta.ensure(J * sizeof(double)));
+    HIP_TRY(ws->cout.ensure(n * sizeof(CoarseOut)));
+    std::vector<CoarseOut> co(n);
+    std::vector<Inst> cinst(n);
+    int cext = 0;
+    for (int k = 0; k < n; ++k) {
+      const int64_t c0 = inst[k].cell0;
+      co[k].F = ws->cF.as<double>() + c0;
+      co[k].mask = ws->cmask.as<uint8_t>() + c0;
+      co[k].q = ws->cq.as<double>() + c0;
+      co[k].u = ws->cu.as<double>() + c0;
+      Inst& C = cinst[k];
+      std::memset(&C, 0, sizeof C);
+      C.u = co[k].u;
+      C.F = co[k].F;
+      C.mask = co[k].mask;
+      C.qdense = co[k].q;
+      C.delta = ws->coarse.delta.as<double>() + c0;
+      C.h = (double)inst[k].s * inst[k].h;
+      C.nx = inst[k].kx;
+      C.ny = inst[k].ky;
+      Tiling ct;
+      make_tiling(C.nx, C.ny, 64, EIK_EXACT, &ct);
+      C.s = ct.s;
+      C.kx = ct.kx;
+      C.ky = ct.ky;
+      C.balanced = ct.balanced;
+      cext = std::max(cext, ct.extent);
+    }
+    HIP_TRY(hipMemcpyAsync(ws->cout.p, co.data(), n * sizeof(CoarseOut), hipMemcpyHostToDevice, stream));
+    HIP_TRY(launch_coarse_inputs(e, ws->cout.as<CoarseOut>(), (int)max_src, stream));
+    if ((rc = setup_engine(ws->coarse, cinst, EIK_F64, EIK_EXACT, 0, -1.0, 0, 0, 0, timeout, stream, &ce)))
+      return rc;
+    HIP_TRY(launch_prepare(ce, J, stream));
+    const int cw = default_workers(ws, ce.ncells, tile_for(cext), EIK_F64, n);
+    HIP_TRY(launch_solve(ce, cw, tile_for(cext), stream));
+    HIP_TRY(launch_dag(e, ws->cout.as<CoarseOut>(), (int)J, stream));
+    have_coarse = true;
+  }
   HIP_TRY(hipEventRecord(ws->ev0, stream));
-  HIP_TRY(eik::launch_solve(e, workers, tile, stream));
+  HIP_TRY(launch_solve(e, workers, tile, stream));
   HIP_TRY(hipEventRecord(ws->ev1, stream));
   const bool want_resid = o.residual_check != 0;
-  if (want_resid) HIP_TRY(eik::launch_residual(e, max_nodes, stream));
-  HIP_TRY(hipMemcpyAsync(ws->ctl_host, e.ctl, sizeof(eik::Ctl), hipMemcpyDeviceToHost, stream));
+  if (want_resid) HIP_TRY(launch_residual(e, max_nodes, stream));
+  HIP_TRY(hipMemcpyAsync(ws->ctl_host, e.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+  if (have_coarse)
+    HIP_TRY(hipMemcpyAsync(ws->ctl_host + 1, ce.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  const Ctl c = ws->ctl_host[0];
+  const unsigned err = c.err | (have_coarse ? ws->ctl_host[1].err : 0u);
+  if (err & (kErrSpeed | kErrSource))
+    return fail(EIK_EINVAL, "%s", (err & kErrSpeed) ? "a speed value is not positive and finite"
+                                                   : "a source is out of range, on an obstacle or has non-finite q");
+  if (err & kErrGuard)
+    return fail(EIK_ENOTCONV, "cell-visit guard tripped after %llu visits", (unsigned long long)c.visits);
+  if (err & kErrDeadline) return fail(EIK_EDEVICE, "solver exceeded its time limit");
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, ws->ev0, ws->ev1));
+  double resid = -1.0;
+  if (want_resid) std::memcpy(&resid, &c.resid_bits, sizeof resid);
+
+  // FP32: certify the result with the FP64 residual, else re-solve in FP64
+  int fell_back = 0;
+  if (dt == EIK_F32 && want_resid && !(resid <= 4.0 * std::ldexp(1.0, -24))) {
+    lk.unlock();  // the FP64 solve takes the workspace lock itself
+    rc = refine_fp64(n, probs, inst, o, stream);
+    lk.lock();
+    if (rc) return rc;
+    fell_back = 1;
+  }
   if (!dev) {
     for (int k = 0; k < n; ++k)
       HIP_TRY(hipMemcpyAsync(probs[k].u_out, inst[k].u, (size_t)probs[k].nx * probs[k].ny * es,
                              hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
   }
-  HIP_TRY(hipStreamSynchronize(stream));
-  const eik::Ctl& c = *ws->ctl_host;
-  if (c.err & (eik::kErrSpeed | eik::kErrSource))
-    return fail(EIK_EINVAL, "%s", (c.err & eik::kErrSpeed) ? "a speed value is not positive and finite"
-                                                          : "a source is out of range, on an obstacle or has non-finite q");
-  if (c.err & eik::kErrGuard)
-    return fail(EIK_ENOTCONV, "cell-visit guard tripped after %llu visits", (unsigned long long)c.visits);
-  if (c.err & eik::kErrDeadline) return fail(EIK_EDEVICE, "solver exceeded its time limit");
-  float ms = 0.f;
-  HIP_TRY(hipEventElapsedTime(&ms, ws->ev0, ws->ev1));
+  if (g_profile) {
+    const double us = 1e3 / ws->wall_khz;  // microseconds per tick
+    std::fprintf(stderr,
+                 "[eik profile] kernel %.1f us; wave-us idle %.0f claim %.0f load %.0f sweep %.0f "
+                 "publish %.0f finish %.0f; visits %llu sweeps %llu checks %llu\n",
+                 ms * 1e3, c.t_idle * us, c.t_claim * us, c.t_load * us, c.t_sweep * us,
+                 c.t_publish * us, c.t_finish * us, (unsigned long long)c.visits,
+                 (unsigned long long)c.sweeps, (unsigned long long)c.checks);
+  }
+  if (g_trace) {
+    unsigned cnt = 0;
+    HIP_TRY(hipMemcpy(&cnt, ws->trace_n.p, 4, hipMemcpyDeviceToHost));
+    cnt = std::min(cnt, trace_cap);
+    std::vector<unsigned long long> t((size_t)cnt * 8);
+    HIP_TRY(hipMemcpy(t.data(), ws->trace.p, t.size() * 8, hipMemcpyDeviceToHost));
+    if (FILE* f = std::fopen(g_trace, "w")) {
+      for (unsigned k = 0; k < cnt; ++k) {
+        const unsigned long long* r = &t[(size_t)k * 8];
+        std::fprintf(f, "%llu %llu %llu %llu %llu %llu %llu %llu %llu\n", r[0] & 0xffffffffull,
+                     (r[0] >> 32) & 0xffff, r[0] >> 48, r[1], r[2], r[3], r[4], r[5], r[6]);
+      }
+      std::fclose(f);
+    }
+  }
+  if (info) {
+    info->kernel_ms = ms;
+    info->cells = J;
+  }
   if (stats) {
-    for (int k = 0; k < (stats ? n : 0); ++k) {
+    for (int k = 0; k < n; ++k) {
       eik_stats& S = stats[k];
       std::memset(&S, 0, sizeof S);
       S.seconds = now_s() - t0;
@@ -382,18 +502,61 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats) {
       S.band_steps = c.band_steps;
       S.mon_checks = c.mon_checks;
       S.mon_ok = c.mon_ok;
-      double r;
-      std::memcpy(&r, &c.resid_bits, sizeof r);
-      S.max_residual = want_resid ? r : -1.0;
+      S.max_residual = resid;
       S.cell_used = inst[k].s;
       S.band_used = band;
-      S.fell_back_to_f64 = 0;
+      S.fell_back_to_f64 = fell_back;
+      S.cells_total = (uint64_t)J;
     }
   }
   return EIK_OK;
 }
 
-}  // namespace
+// Re-solves FP32 problems in FP64 (speeds widened on the device) and rounds
+// the result into the FP32 outputs (inst[k].u: device memory).
+int refine_fp64(int n, const eik_problem* probs, const std::vector<Inst>& inst, const eik_opts& o,
+                hipStream_t stream) {
+  Workspace* ws = nullptr;
+  int rc = workspace(&ws);
+  if (rc) return rc;
+  int64_t total = 0;
+  for (int k = 0; k < n; ++k) total += (int64_t)probs[k].nx * probs[k].ny;
+  {
+    std::lock_guard<std::mutex> lk(ws->mu);
+    HIP_TRY(ws->F64.ensure(total * sizeof(double)));
+    HIP_TRY(ws->u64.ensure(total * sizeof(double)));
+  }
+  std::vector<eik_problem> p64(probs, probs + n);
+  int64_t off = 0;
+  for (int k = 0; k < n; ++k) {
+    const int64_t nn = (int64_t)probs[k].nx * probs[k].ny;
+    double* F = ws->F64.as<double>() + off;
+    HIP_TRY(launch_convert(inst[k].F, EIK_F32, F, EIK_F64, nn, stream));
+    p64[k].F = F;
+    p64[k].u_out = ws->u64.as<double>() + off;
+    p64[k].mask = inst[k].mask;
+    p64[k].src = inst[k].src;
+    p64[k].q = inst[k].q;
+    off += nn;
+  }
+  eik_opts o64 = o;
+  o64.dtype = EIK_F64;
+  o64.device_ptrs = 1;
+  o64.residual_check = 0;
+  if ((rc = run(n, p64.data(), o64, nullptr, nullptr))) return rc;
+  off = 0;
+  for (int k = 0; k < n; ++k) {
+    const int64_t nn = (int64_t)probs[k].nx * probs[k].ny;
+    HIP_TRY(launch_convert(ws->u64.as<double>() + off, EIK_F64, inst[k].u, EIK_F32, nn, stream));
+    off += nn;
+  }
+  HIP_TRY(hipStreamSynchronize(stream));
+  return EIK_OK;
+}
+
+}  // namespace eik
+
+using namespace eik;
 
 extern "C" {
 
@@ -407,7 +570,7 @@ int eik_solve(int32_t nx, int32_t ny, double h, const void* F, const uint8_t* ma
   eik_problem p{nx, ny, h, F, mask, nsrc, src, q, u_out};
   if ((rc = validate_shape(p))) return rc;
   if (!o.device_ptrs && (rc = validate_host(p, o.dtype))) return rc;
-  return run(1, &p, o, stats);
+  return run(1, &p, o, stats, nullptr);
 }
 
 int eik_solve_batched(int32_t n, const eik_problem* probs, const eik_opts* opts, eik_stats* stats) {
@@ -421,7 +584,7 @@ int eik_solve_batched(int32_t n, const eik_problem* probs, const eik_opts* opts,
     if (!o.device_ptrs && (rc = validate_host(probs[k], o.dtype)))
       return fail(rc, "problem %d: %s", k, g_err.c_str());
   }
-  return run(n, probs, o, stats);
+  return run(n, probs, o, stats, nullptr);
 }
 
 const char* eik_last_error(void) { return g_err.c_str(); }

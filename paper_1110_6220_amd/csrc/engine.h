@@ -6,13 +6,24 @@
 
 namespace eik {
 
-// Per-cell state word: bit 0 = queued (pending), bit 1 = being processed;
-// bits 8..11 = preferred sweep directions raised by neighbours (0 SW, 1 NW,
+// Per-cell state word.  kPending: queued or to be processed again; kRunning:
+// a wave is processing the cell; kDone1: its first processing has finished
+// (cells that are not ordered by dependency counts start with kDone1 set).
+// Bits 8..11: preferred sweep directions raised by neighbours (0 SW, 1 NW,
 // 2 NE, 3 SE).
 constexpr uint32_t kPending = 1u;
 constexpr uint32_t kRunning = 2u;
+constexpr uint32_t kDone1 = 4u;
 constexpr int kFlagShift = 8;
 constexpr uint32_t kFlagMask = 0xFu << kFlagShift;
+
+// Per-cell order bits (DAG ordering): bits 0..3 = sides (0 W, 1 E, 2 S, 3 N)
+// whose neighbour comes earlier in the coarse order; kOrdConverge = the cell
+// holds exit nodes or the coarse front never reaches it (FMSM sweeps it to
+// convergence); kOrdEmpty = the cell has no accessible node.
+constexpr uint8_t kOrdConverge = 0x10;
+constexpr uint8_t kOrdEmpty = 0x20;
+constexpr uint8_t kOrdSource = 0x40;  // the cell holds exit nodes
 
 enum Method : int32_t { kExact = 0, kFmsm = 1, kFhcm = 2 };
 
@@ -21,11 +32,12 @@ enum Method : int32_t { kExact = 0, kFmsm = 1, kFhcm = 2 };
 // or floor(k*n/K) for the balanced one.
 struct Inst {
   void* u;               // solution / working values (dtype)
-  const void* F;         // speed (dtype)
+  const void* F;         // speed (dtype; coarse problems: double)
   const uint8_t* mask;   // 1 accessible, 0 obstacle; nullptr = all accessible
-  void* delta;           // workspace: h/F; +inf on obstacles and sources (dtype)
-  const int64_t* src;    // exit-set nodes
-  const double* q;       // exit costs, nullptr = 0
+  void* delta;           // workspace: h/F; +inf on obstacles and exit nodes (dtype)
+  const int64_t* src;    // exit nodes (nsrc entries) ...
+  const double* q;       // ... and their costs (nullptr = 0)
+  const double* qdense;  // or: exit cost per node, +inf elsewhere (coarse problems)
   double h;
   int32_t nx, ny;
   int32_t s;             // nominal cell side
@@ -33,64 +45,109 @@ struct Inst {
   int32_t balanced;      // tiling kind
   int32_t cell0;         // global id of the instance's first cell
   int32_t nsrc;
-  int32_t pad;
 };
 
-// Multi-producer multi-consumer bucketed cell queue.  Bucket b holds a ring of
-// `cap` slots; a slot is (sequence << 32 | cell).  Keys map to absolute band
-// index floor(key / width); the ring is that index modulo nb.  `cursor` is the
-// lowest absolute band that may hold work.
+// Multi-producer multi-consumer cell queue.  Band b holds a ring of `cap`
+// slots; a slot is (sequence << 32 | cell).  Keys map to absolute band index
+// floor(key / width); the ring is that index modulo nb.  inflight[b] counts
+// the cells of band b that are queued or running; the cursor moves past a
+// band only once its count is zero (the band is closed with kClosed while the
+// cursor moves, then reopened for band + nb).  Cells are popped only from the
+// `window` + 1 bands starting at the cursor.  nb = 1 is a plain FIFO.
 struct Queue {
-  unsigned long long* slot;    // nb * cap
-  unsigned long long* head;    // nb entries, stride kCtrStride
-  unsigned long long* tail;    // nb entries, stride kCtrStride
-  unsigned long long* cursor;  // 1
-  uint32_t cap;                // power of two > number of cells
-  uint32_t nb;                 // power of two
-  double inv_width;            // 1 / band width (0: single band)
+  unsigned long long* slot;      // nb * cap
+  unsigned long long* head;      // nb entries, stride kCtrStride
+  unsigned long long* tail;      // nb entries, stride kCtrStride
+  unsigned long long* inflight;  // nb entries, stride kCtrStride
+  unsigned long long* cursor;    // 1
+  uint32_t cap;                  // power of two > number of cells
+  uint32_t nb;                   // power of two
+  uint32_t window;
+  uint32_t pad;
+  double inv_width;              // 1 / band width
 };
 constexpr int kCtrStride = 16;  // 128 bytes between hot counters
+constexpr unsigned long long kClosed = 1ull << 62;
 
-// Device control block.
+// Device control block.  Counters that many waves update while cells are
+// processed sit on cache lines of their own.
 struct Ctl {
-  unsigned long long active;      // cells pending or running
-  unsigned long long visits;      // cell removals
+  unsigned long long active;      // cells waiting, queued or running
+  unsigned long long pad_a[15];
+  unsigned long long visits;      // cell removals (checked against guard)
+  unsigned long long pad_v[15];
+  unsigned long long guard;       // limit on total visits
+  unsigned long long deadline;    // wall_clock64() value after which workers stop
+  unsigned int err;               // kErr* bits
+  unsigned int pad0;
+  unsigned long long pad_g[13];
+  // statistics, flushed once per wave when it exits
   unsigned long long sweeps;      // productive sweeps
-  unsigned long long checks;      // no-change sweeps
+  unsigned long long checks;      // convergence tests (no-change sweeps, tile checks)
   unsigned long long band_steps;  // cursor advances
   unsigned long long mon_checks;
   unsigned long long mon_ok;
   unsigned long long resid_bits;  // max residual (bits of a non-negative double)
-  unsigned long long guard;       // limit on total visits
-  unsigned long long deadline;    // wall_clock64() value after which workers stop
-  unsigned int err;               // bit 0 bad speed, 1 bad source, 2 guard, 3 deadline
-  unsigned int done_waves;
-  unsigned long long pad[4];
+  // phase timers (wall-clock ticks summed over waves), when profiling
+  unsigned long long t_idle, t_claim, t_load, t_sweep, t_publish, t_finish;
+  unsigned long long pad_s[4];
 };
 constexpr unsigned kErrSpeed = 1u, kErrSource = 2u, kErrGuard = 4u, kErrDeadline = 8u;
 
 // Arguments of the engine kernels.
 struct Engine {
-  Inst* inst;            // device array (batched) -- may be null when ninst == 1
-  Inst one;              // the instance when ninst == 1
+  Inst* inst;            // device array of ninst descriptors
+  Inst one;              // copy of inst[0], used when args_inst is set
+  int32_t args_inst;     // the single descriptor is known on the host
   int32_t ninst;
   int32_t ncells;        // total cells J
   int32_t method;
   int32_t dtype;         // 0 f64, 1 f32
+  int32_t dag;           // cells start when their earlier neighbours are done
   uint32_t* st;          // J state words
   uint32_t* visits;      // J removal counts
-  int32_t* cell_inst;    // J instance ids (batched only)
+  int32_t* cell_inst;    // J instance ids (ninst > 1)
   unsigned int* key;     // J orderable bits of the float cell value
+  int32_t* deps;         // J unfinished earlier neighbours (dag)
+  uint8_t* ord;          // J order bits (dag)
   Queue q;
   Ctl* ctl;
+  int32_t eager;         // publish after every productive sweep
+  int32_t profile;       // accumulate phase timers in Ctl
+  // diagnostic trace (null when off): per cell the wall clock when it was
+  // last made ready; per visit {cell, ready, popped, loaded, swept, done}
+  unsigned long long* ready_at;
+  unsigned long long* trace;
+  unsigned int* trace_n;
+  unsigned int trace_cap;
   unsigned long long guard;          // limit on total cell visits
   unsigned long long timeout_ticks;  // wall_clock64 ticks before workers give up
 };
 
+// Coarse grid of one fine instance (FMSM Part I): one node per cell.
+struct CoarseOut {
+  double* F;        // J mean speed over accessible nodes
+  uint8_t* mask;    // J 1 = the cell has an accessible node
+  double* q;        // J min exit cost over the cell's exit nodes, +inf if none
+  double* u;        // J coarse solution (filled by the coarse solve)
+};
+
 // Host-side launchers (engine.hip).  All work is enqueued on `stream`.
-hipError_t launch_prepare(const Engine& e, int64_t total_nodes, hipStream_t stream);
+// prepare: cell states, queue, delta, validation, u = +inf / exit costs, and
+// (unless dag) the exit cells queued.
+hipError_t launch_prepare(const Engine& e, int64_t max_nodes, hipStream_t stream);
 hipError_t launch_solve(const Engine& e, int workers, int tile, hipStream_t stream);
-hipError_t launch_residual(const Engine& e, int64_t total_nodes, hipStream_t stream);
-size_t solve_lds_bytes(int dtype, int tile);
+hipError_t launch_residual(const Engine& e, int64_t max_nodes, hipStream_t stream);
+// coarse speeds, masks and exit costs of every fine cell (cells of instance k
+// at co[k].*[cell - cell0])
+hipError_t launch_coarse_inputs(const Engine& fine, const CoarseOut* co_dev, int max_cells,
+                                hipStream_t stream);
+// dependency counts and order bits from the coarse solutions; queues the
+// cells that have no earlier neighbour
+hipError_t launch_dag(const Engine& fine, const CoarseOut* co_dev, int max_cells,
+                      hipStream_t stream);
+// element-wise copies between precisions (FP32 results re-solved in FP64)
+hipError_t launch_convert(const void* src, int src_dtype, void* dst, int dst_dtype, int64_t n,
+                          hipStream_t stream);
 
 }  // namespace eik

@@ -3,29 +3,34 @@
 // Method (Chacon & Vladimirsky, "Fast two-scale methods for Eikonal
 // equations"): the grid is split into cells; a cell is processed by
 // Gauss-Seidel sweeps over the cell with its one-node halo held fixed
-// (Algorithm FSM restricted to c~ = c u N^f(c)); after processing, each
+// (Algorithm FSM restricted to c~ = c u N^f(c)); after processing, a
 // neighbour cell is re-queued when a node on the shared side decreased during
 // this processing (or is an exit node and the cell is removed for the first
 // time) and is smaller than the node across (Algorithm generic_LC_cells).  The
-// Theorem of Section 3.2.1 makes the result independent of the order in which
-// cells are removed, which is what lets many cells run at once here.
+// Theorem of Section 3.2.1 makes the exact method's result independent of the
+// order in which cells are removed, which is what lets many cells run at once.
 //
 // Mapping onto CDNA4:
-//  * one wave64 per cell, cells up to 64 x 64 nodes; the tile plus its halo
-//    and the per-node step delta = h/F live in LDS;
+//  * one wave64 per cell, cells up to 64 x 64 nodes; the tile, its halo and
+//    the per-node step delta = h/F live in LDS;
 //  * a sweep walks the anti-diagonals of the tile: lane l owns column l and
 //    at step d updates row d - l, so the upwind x-neighbour is the value lane
 //    l-1 produced one step earlier, carried by a DPP wave shift, and the
 //    upwind y-neighbour is the lane's own previous value -- the dependent
-//    chain stays in registers; the two downwind neighbours are old values in
-//    LDS.  This order is a topological order of the lexicographic sweep's
+//    chain stays in registers; downwind neighbours are old values in LDS.
+//    This order is a topological order of the lexicographic sweep's
 //    dependencies, so each sweep equals the serial sweep bit for bit;
-//  * a persistent grid of waves pulls cells from a bucketed device queue
-//    keyed by the cell values of eq. cell_value; state words per cell make
-//    "queued", "running" and "re-queued while running" atomic transitions;
-//  * values shared between waves (the solution array, cell states, queue)
-//    use agent-scope atomics so that waves on different XCDs see each other's
-//    writes; the read-only delta array uses ordinary cached loads.
+//  * a persistent grid of waves pulls cells from a device queue.  Cells are
+//    ordered either by the cell values of eq. cell_value in bands (the
+//    Heap-Cell Methods' heap, relaxed to "any cell of the lowest open bands")
+//    or, when a coarse solve is available (FMSM Part I), by dependency
+//    counts: a cell starts once every neighbour that precedes it in the
+//    coarse order has finished its first processing.  State words make
+//    "queued", "running", "re-queued while running" and "first pass done"
+//    atomic transitions;
+//  * values shared between waves (solution, cell states, queue, counters)
+//    use agent-scope atomics, coherent across XCDs; the read-only delta and
+//    speed arrays use ordinary cached loads.
 #include <math.h>
 #include <stdint.h>
 
@@ -33,7 +38,6 @@
 
 namespace eik {
 namespace {
-
 
 // ----------------------------------------------------------------------------
 // scalar helpers
@@ -46,31 +50,65 @@ __device__ __forceinline__ double inf_v<double>() { return __builtin_huge_val();
 template <>
 __device__ __forceinline__ float inf_v<float>() { return __builtin_huge_valf(); }
 
+// Pointers into device global memory (address space 1): loads through them
+// are global_load rather than flat_load.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> to_global(T* p) {
+  return (gptr<T>)(p);
+}
+
 template <typename T>
 __device__ __forceinline__ T ld_coh(const T* p) {
   return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 template <typename T>
+__device__ __forceinline__ T ld_coh(gptr<const T> p) {
+  return __hip_atomic_load((gptr<T>)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
 __device__ __forceinline__ void st_coh(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-
 __device__ __forceinline__ unsigned long long ld64(const unsigned long long* p) {
   return ld_coh(p);
 }
 
-// Local update of Section 2 with the quadrant shortcut: a = min(U_W, U_E),
-// b = min(U_S, U_N).  One-sided value min(a,b) + delta when |a - b| >= delta,
-// otherwise the root >= max(a,b) of ((U-a)^2 + (U-b)^2) = delta^2.  The
+template <typename T>
+__device__ __forceinline__ T atomic_add_relaxed(T* p, T v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Square root of x >= 2^-767 by the reciprocal-square-root estimate and two
+// Newton corrections (the sequence LLVM emits for a correctly rounded sqrt,
+// without its rescaling of tiny inputs, which never occur here: the argument
+// 2 delta^2 - d^2 is either >= delta^2 or the result is discarded).
+__device__ __forceinline__ double sqrt_pos(double x) {
+  const double r = __builtin_amdgcn_rsq(x);
+  double g = x * r;
+  double h = r * 0.5;
+  const double e = fma(-h, g, 0.5);
+  g = fma(g, e, g);
+  h = fma(h, e, h);
+  double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  d = fma(-g, g, x);
+  return fma(d, h, g);
+}
+
+// Local update of Section 2 from a (x-neighbour value) and b (y-neighbour
+// value): the one-sided value min(a,b) + delta when |a - b| >= delta,
+// otherwise the root >= max(a,b) of (U-a)^2 + (U-b)^2 = delta^2.  The
 // expression order matches the CPU oracle and the build disables contraction,
-// so both round identically.
+// so both round identically.  a = b = +inf gives NaN, which the caller's
+// minimum with the old value turns into "no update".
 __device__ __forceinline__ double local_update(double a, double b, double dl) {
   const double lo = a < b ? a : b;
   const double d = a - b;
   const double one = lo + dl;
-  const double two = 0.5 * (a + b + sqrt(2.0 * dl * dl - d * d));
-  const double r = (fabs(d) >= dl) ? one : two;
-  return (lo == __builtin_huge_val()) ? lo : r;
+  const double two = 0.5 * (a + b + sqrt_pos(2.0 * dl * dl - d * d));
+  return (fabs(d) >= dl) ? one : two;
 }
 
 // FP32 storage: the branch test and the two-sided root are evaluated in FP64
@@ -79,25 +117,40 @@ __device__ __forceinline__ float local_update(float a, float b, float dl) {
   const float lo = a < b ? a : b;
   const double da = a, db = b, dd = da - db, ddl = dl;
   const float one = lo + dl;
-  const float two = (float)(0.5 * (da + db + sqrt(2.0 * ddl * ddl - dd * dd)));
-  const float r = (fabs(dd) >= ddl) ? one : two;
-  return (lo == __builtin_huge_valf()) ? lo : r;
+  const float two = (float)(0.5 * (da + db + sqrt_pos(2.0 * ddl * ddl - dd * dd)));
+  return (fabs(dd) >= ddl) ? one : two;
 }
 
-// Lane l receives lane l-1's value (DPP wave_shr:1; lane 0 receives 0).
-__device__ __forceinline__ float wave_shr1(float v) {
-  return __builtin_bit_cast(
-      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, false));
+// IEEE minNum without the compiler's NaN canonicalisation of the operands
+// (operands here are never signalling NaNs); a quiet NaN operand yields the
+// other operand.  ALU-only inline assembly.
+__device__ __forceinline__ double vmin(double a, double b) {
+  double r;
+  asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
 }
-__device__ __forceinline__ double wave_shr1(double v) {
+__device__ __forceinline__ float vmin(float a, float b) {
+  float r;
+  asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
+// Lane l receives lane l-1's value; lane 0 receives `edge` (DPP wave_shr:1
+// with the out-of-range source replaced by the old value).
+__device__ __forceinline__ float shr1_or(float v, float edge) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, edge),
+                                                               __builtin_bit_cast(int, v), 0x138,
+                                                               0xf, 0xf, false));
+}
+__device__ __forceinline__ double shr1_or(double v, double edge) {
   const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x138, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xf, 0xf, false);
+  const long long o = __builtin_bit_cast(long long, edge);
+  const int lo = __builtin_amdgcn_update_dpp((int)o, (int)b, 0x138, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(b >> 32), 0x138, 0xf, 0xf, false);
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
 __device__ __forceinline__ int bcast(int v, int src_lane) { return __shfl(v, src_lane, 64); }
-
 __device__ __forceinline__ unsigned long long ballot(bool p) { return __ballot(p); }
 
 // orderable encoding of a float as an unsigned int (monotone)
@@ -115,8 +168,11 @@ __device__ __forceinline__ int cell_lo(int k, int n, int K, int s, int bal) {
   return bal ? (int)(((long long)k * n) / K) : k * s;
 }
 
-__device__ __forceinline__ const Inst& inst_of(const Engine& e, int g) {
-  return e.ninst == 1 ? e.one : e.inst[e.cell_inst[g]];
+__device__ __forceinline__ int inst_index(const Engine& e, int g) {
+  return e.ninst == 1 ? 0 : e.cell_inst[g];
+}
+__device__ __forceinline__ Inst inst_of(const Engine& e, int g) {
+  return e.args_inst ? e.one : e.inst[inst_index(e, g)];
 }
 
 __device__ __forceinline__ bool past_deadline(const Ctl* c) {
@@ -126,9 +182,54 @@ __device__ __forceinline__ bool past_deadline(const Ctl* c) {
 __device__ __forceinline__ void set_err(Ctl* c, unsigned bits) {
   __hip_atomic_fetch_or(&c->err, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ unsigned get_err(const Ctl* c) {
+  return __hip_atomic_load(const_cast<unsigned*>(&c->err), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Adds the ticks since *t0 to counter c (lane 0, when profiling) and
+// restarts the clock.
+__device__ __forceinline__ void tick(const Engine& e, unsigned long long* c,
+                                     unsigned long long* t0, int lane) {
+  if (!e.profile) return;
+  const unsigned long long t = wall_clock64();
+  if (lane == 0) atomic_add_relaxed(c, t - *t0);
+  *t0 = t;
+}
+
+// Ordering between waves.  Every value the waves share (solution values,
+// cell states, queue words, counters) is accessed only with agent-scope
+// atomic operations, which are coherent across XCDs on their own; what the
+// protocol needs on top is that a wave's earlier memory operations have
+// completed before it signals (release) and that its later operations start
+// after the signal it observed has returned (acquire).  Waiting on the
+// wave's memory counters gives exactly that.  EIK_FENCE_MODE=1 uses the
+// compiler's agent-scope fences instead, which in addition write back and
+// invalidate the L2 for non-atomic data this kernel does not share.
+#ifndef EIK_FENCE_MODE
+#define EIK_FENCE_MODE 0
+#endif
+__device__ __forceinline__ void order_release() {
+#if EIK_FENCE_MODE == 1
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+#else
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+#endif
+}
+__device__ __forceinline__ void order_acquire() {
+#if EIK_FENCE_MODE == 1
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+#else
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+#endif
+}
 
 // ----------------------------------------------------------------------------
-// bucketed cell queue (per-lane operations)
+// cell queue (per-lane operations except q_pop)
 // ----------------------------------------------------------------------------
 
 __device__ __forceinline__ unsigned long long band_of(const Queue& q, float key) {
@@ -137,52 +238,94 @@ __device__ __forceinline__ unsigned long long band_of(const Queue& q, float key)
   return b < 1e15 ? (unsigned long long)b : 1000000000000000ull;
 }
 
-// Appends `cell` to the ring of its band.  Every cell is in the queue at most
-// once (guarded by its state word) and cap > cells, so a producer only waits
-// for a consumer that has already claimed the slot's previous ticket.
-__device__ bool q_push(const Engine& e, uint32_t cell, float key) {
+__device__ __forceinline__ unsigned long long* ctr(unsigned long long* base, uint32_t r) {
+  return base + (size_t)r * kCtrStride;
+}
+
+// Appends `cell` to the ring of its band (clamped to the open bands
+// [cursor, cursor + nb)).  Every cell is in the queue at most once (guarded by
+// its state word) and cap > cells, so a producer only waits for a consumer
+// that has already claimed the slot's previous ticket.
+__device__ void q_push(const Engine& e, uint32_t cell, float key) {
   const Queue& q = e.q;
   uint32_t r = 0;
   if (q.nb > 1) {
-    unsigned long long b = band_of(q, key);
-    const unsigned long long cur = ld64(q.cursor);
-    if (b < cur) b = cur;
-    r = (uint32_t)(b & (q.nb - 1));
+    const unsigned long long kb = band_of(q, key);
+    for (;;) {
+      const unsigned long long c = ld64(q.cursor);
+      unsigned long long b = kb < c ? c : kb;
+      if (b > c + q.nb - 1) b = c + q.nb - 1;
+      r = (uint32_t)(b & (q.nb - 1));
+      const unsigned long long old = atomic_add_relaxed(ctr(q.inflight, r), 1ull);
+      order_acquire();
+      // band b still open and not yet passed by the cursor: the count now
+      // held keeps the cursor from passing it
+      if (!(old & kClosed) && ld64(q.cursor) <= b) break;
+      atomic_add_relaxed(ctr(q.inflight, r), ~0ull);
+      if (past_deadline(e.ctl)) {
+        set_err(e.ctl, kErrDeadline);
+        return;
+      }
+    }
   }
-  const unsigned long long t = __hip_atomic_fetch_add(
-      &q.tail[r * kCtrStride], 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  order_release();
+  const unsigned long long t = atomic_add_relaxed(ctr(q.tail, r), 1ull);
   unsigned long long* s = q.slot + (size_t)r * q.cap + (t & (q.cap - 1));
   while ((uint32_t)(ld64(s) >> 32) != (uint32_t)t) {
     if (past_deadline(e.ctl)) {
       set_err(e.ctl, kErrDeadline);
-      return false;
+      return;
     }
     __builtin_amdgcn_s_sleep(1);
   }
-  __hip_atomic_store(s, ((t + 1ull) << 32) | cell, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-  return true;
+  order_release();
+  st_coh(s, ((t + 1ull) << 32) | cell);
 }
 
-// Wave-cooperative pop from the lowest non-empty band; -1 if none was found.
-__device__ int q_pop(const Engine& e, int lane) {
+// Moves the cursor past its band when no cell of that band is queued or
+// running.  One lane.
+__device__ void q_try_advance(const Engine& e) {
+  const Queue& q = e.q;
+  const unsigned long long c = ld64(q.cursor);
+  unsigned long long* fl = ctr(q.inflight, (uint32_t)(c & (q.nb - 1)));
+  unsigned long long z = 0ull;
+  if (!__hip_atomic_compare_exchange_strong(fl, &z, kClosed, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT))
+    return;
+  order_acquire();
+  unsigned long long cc = c;
+  const bool moved = __hip_atomic_compare_exchange_strong(q.cursor, &cc, c + 1ull, __ATOMIC_RELAXED,
+                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  order_release();
+  __hip_atomic_fetch_and(fl, ~kClosed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (moved) atomic_add_relaxed(&e.ctl->band_steps, 1ull);
+}
+
+// Wave-cooperative pop from the lowest non-empty band within the window;
+// returns the cell (or -1) and its ring in *ring.
+__device__ int q_pop(const Engine& e, int lane, int* ring) {
   const Queue& q = e.q;
   unsigned long long cur = 0;
   if (q.nb > 1) cur = ld64(q.cursor);
+  const uint32_t span = q.nb > 1 ? q.window + 1u : 1u;
   unsigned long long h = 0, t = 0;
   bool has = false;
-  if ((uint32_t)lane < q.nb) {
+  if ((uint32_t)lane < span) {
     const uint32_t r = (uint32_t)((cur + lane) & (q.nb - 1));
-    h = ld64(&q.head[r * kCtrStride]);
-    t = ld64(&q.tail[r * kCtrStride]);
+    h = ld64(ctr(q.head, r));
+    t = ld64(ctr(q.tail, r));
     has = h < t;
   }
   const unsigned long long m = ballot(has);
-  if (!m) return -1;
+  if (!m) {
+    if (q.nb > 1 && lane == 0) q_try_advance(e);
+    return -1;
+  }
   const int k = __builtin_ctzll(m);
   int cell = -1;
+  const uint32_t r = (uint32_t)((cur + k) & (q.nb - 1));
   if (lane == k) {
-    const uint32_t r = (uint32_t)((cur + k) & (q.nb - 1));
-    unsigned long long* hp = &q.head[r * kCtrStride];
+    unsigned long long* hp = ctr(q.head, r);
     bool got = false;
     for (int tries = 0; tries < 8 && h < t; ++tries) {
       unsigned long long exp = h;
@@ -192,13 +335,13 @@ __device__ int q_pop(const Engine& e, int lane) {
         break;
       }
       h = exp;
-      t = ld64(&q.tail[r * kCtrStride]);
+      t = ld64(ctr(q.tail, r));
     }
     if (got) {
       unsigned long long* s = q.slot + (size_t)r * q.cap + (h & (q.cap - 1));
       unsigned long long v;
       for (;;) {
-        v = __hip_atomic_load(s, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        v = ld64(s);
         if ((uint32_t)(v >> 32) == (uint32_t)(h + 1ull)) break;
         if (past_deadline(e.ctl)) {
           set_err(e.ctl, kErrDeadline);
@@ -210,91 +353,219 @@ __device__ int q_pop(const Engine& e, int lane) {
       if (v != ~0ull) {
         cell = (int)(uint32_t)v;
         st_coh(s, (h + (unsigned long long)q.cap) << 32);
-        if (k > 0) {
-          unsigned long long c = cur;
-          if (__hip_atomic_compare_exchange_strong(q.cursor, &c, cur + (unsigned long long)k,
-                                                   __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT))
-            __hip_atomic_fetch_add(&e.ctl->band_steps, 1ull, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        }
       }
     }
   }
+  *ring = (int)r;
   return bcast(cell, k);
 }
 
-// Marks neighbour cell `g` as needing processing with direction flags `fl`;
-// enqueues it when it was idle.  Called by one lane.
+// Blocking pop from a single FIFO ring (nb = 1).  The wave takes the next
+// ticket and waits on that ticket's slot only, so idle waves poll distinct
+// addresses instead of competing for the head.  Returns the cell, or -1 once
+// no cell is waiting, queued or running (or on error/timeout).  A ticket is
+// given up only then: no cell will be queued any more.
+__device__ int q_pop_ticket(const Engine& e, int lane) {
+  const Queue& q = e.q;
+  int cell = -1;
+  if (lane == 0) {
+    const unsigned long long h = atomic_add_relaxed(q.head, 1ull);
+    unsigned long long* s = q.slot + (h & (q.cap - 1));
+    int spins = 0;
+    for (;;) {
+      const unsigned long long v = ld64(s);
+      if ((uint32_t)(v >> 32) == (uint32_t)(h + 1ull)) {
+        cell = (int)(uint32_t)v;
+        st_coh(s, (h + (unsigned long long)q.cap) << 32);
+        break;
+      }
+      if ((++spins & 15) == 0 &&
+          (ld64(&e.ctl->active) == 0ull || get_err(e.ctl) || past_deadline(e.ctl)))
+        break;
+      if (spins < 64) __builtin_amdgcn_s_sleep(1);
+      else __builtin_amdgcn_s_sleep(4);
+    }
+  }
+  return bcast(cell, 0);
+}
+
+// Releases the band count a processed cell held.  One lane.
+__device__ __forceinline__ void q_done(const Engine& e, int ring) {
+  if (e.q.nb > 1) {
+    order_release();
+    atomic_add_relaxed(ctr(e.q.inflight, (uint32_t)ring), ~0ull);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// cell state transitions (one lane)
+// ----------------------------------------------------------------------------
+
+// A neighbour found that cell g must be processed (again), with preferred
+// directions fl.  Enqueued when it is idle and its first processing is done;
+// a running cell takes the request itself when it finishes, and a cell still
+// waiting for its first processing reads the new values when it starts.
 __device__ void requeue(const Engine& e, int g, uint32_t fl, float key) {
+  order_release();
   const uint32_t old = __hip_atomic_fetch_or(&e.st[g], kPending | (fl << kFlagShift),
-                                             __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-  if (!(old & (kPending | kRunning))) {
-    __hip_atomic_fetch_add(&e.ctl->active, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (!(old & (kPending | kRunning)) && (old & kDone1)) {
+    atomic_add_relaxed(&e.ctl->active, 1ull);
+    if (e.ready_at) e.ready_at[g] = wall_clock64();
     q_push(e, (uint32_t)g, key);
   }
 }
 
+// The last earlier neighbour of cell g finished its first processing: g is
+// enqueued (only this path enqueues a cell before its first processing).
+__device__ void release_first(const Engine& e, int g) {
+  order_release();
+  __hip_atomic_fetch_or(&e.st[g], kPending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (e.ready_at) e.ready_at[g] = wall_clock64();
+  q_push(e, (uint32_t)g, 0.0f);
+}
+
+// Takes a popped (or re-requested) cell: state -> running, keeping kDone1.
+// Returns the previous state word.
+__device__ uint32_t claim(const Engine& e, int g) {
+  uint32_t old = ld_coh(&e.st[g]);
+  for (;;) {
+    const uint32_t want = (old & kDone1) | kRunning;
+    if (__hip_atomic_compare_exchange_strong(&e.st[g], &old, want, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      break;
+  }
+  return old;
+}
+
 // ----------------------------------------------------------------------------
-// the cell sweep
+// sweeps
 // ----------------------------------------------------------------------------
 
 // One Gauss-Seidel sweep in direction dir (0 SW, 1 NW, 2 NE, 3 SE: x and y
 // ascending for SW, x ascending / y descending for NW, ...) over the w x hgt
-// tile in LDS (pitch P, halo at row/column 0 and w+1/hgt+1).  Returns whether
-// any node decreased (wave-uniform).
-template <typename T, int P>
-__device__ bool sweep_tile(T* tu, const T* td, int w, int hgt, int dir, int lane) {
+// tile in LDS (pitch P, halo at row/column 0 and w+1/hgt+1; P*P + lane is a
+// per-lane dummy slot).  Returns (wave-uniform) bit 0: some node decreased;
+// bit 1: some node that decreased is now below one of its upwind neighbours
+// inside the tile.  Without bit 1 the tile is converged: every node was
+// evaluated with its upwind neighbours' final values, and a node can only be
+// lowered further through a downwind neighbour that fell below it during the
+// sweep (a neighbour that stays at or above it cannot lower it, by the
+// causality of the update).  DIRECTIONAL uses only the two upwind neighbours
+// of the sweep (the sweep-directional update of FMSM) instead of the
+// quadrant shortcut.
+//
+// At step d lane l updates node (i, j) with i = column l in sweep order and j
+// = row t = d - l in sweep order.  The upwind x-neighbour is lane l-1's result
+// of step d-1 (for lane 0 the halo value, supplied as the DPP's out-of-range
+// operand); the upwind y-neighbour is the lane's own previous result, which
+// before the lane's first row holds the halo value below it.  The step is
+// branch-free: lanes without a node at this step store into their dummy slot
+// and keep their previous result.  The old values a step needs are read one
+// step ahead (none is a location the current step writes); the node's own old
+// value is the north value read for the step before.  min is v_min_f64, which
+// also maps the NaN that a = b = +inf produces to "no update", as the
+// oracle's explicit test does.
+template <typename T, int P, bool DIRECTIONAL>
+__device__ uint32_t sweep_tile(T* tu, const T* td, int w, int hgt, int dir, int lane) {
   const int sx = (dir == 0 || dir == 1) ? 1 : -1;
   const int sy = (dir == 0 || dir == 3) ? 1 : -1;
-  const int i = sx > 0 ? lane : w - 1 - lane;
+  const int rowstep = sy * P;
   const bool col_ok = lane < w;
-  const int xoff = sx;        // step to the downwind x-neighbour in LDS
-  const int yoff = sy * P;    // step to the downwind y-neighbour in LDS
-  T prev = inf_v<T>();
-  bool changed = false;
+  const int i = col_ok ? (sx > 0 ? lane : w - 1 - lane) : 0;
+  const int j0 = sy > 0 ? 0 : hgt - 1;
+  const int dummy = P * P + lane;
   const int nsteps = w + hgt - 1;
+  // LDS index of the lane's node at sweep-order row t, clamped to the halo rows
+  auto idx_t = [&](int t) {
+    const int tc = t < -1 ? -1 : (t > hgt ? hgt : t);
+    return (j0 + sy * tc + 1) * P + i + 1;
+  };
+  int c = idx_t(-lane);
+  T prev = tu[idx_t(-1)];
+  T ev = tu[c + sx], nv = tu[c + rowstep], uo = tu[c], dl = td[c], hw = tu[c - sx];
+  bool changed = false, backflow = false;
+
   for (int d = 0; d < nsteps; ++d) {
-    const T from_left = wave_shr1(prev);
     const int t = d - lane;
-    if (col_ok && t >= 0 && t < hgt) {
-      const int j = sy > 0 ? t : hgt - 1 - t;
-      const int idx = (j + 1) * P + (i + 1);
-      const T wv = lane == 0 ? tu[idx - xoff] : from_left;
-      const T sv = t == 0 ? tu[idx - yoff] : prev;
-      const T ev = tu[idx + xoff];
-      const T nv = tu[idx + yoff];
-      const T uo = tu[idx];
-      const T a = wv < ev ? wv : ev;
-      const T b = sv < nv ? sv : nv;
-      const T U = local_update(a, b, td[idx]);
-      T r = uo;
-      if (U < uo) {
-        r = U;
-        tu[idx] = U;
-        changed = true;
-      }
-      prev = r;
-    }
+    const bool valid = col_ok && (unsigned)t < (unsigned)hgt;
+    const int c1 = idx_t(t + 1);
+    const T ev1 = tu[c1 + sx], nv1 = tu[c1 + rowstep], dl1 = td[c1], hw1 = tu[c1 - sx];
+    const T wv = shr1_or(prev, hw);
+    const T a = DIRECTIONAL ? wv : vmin(wv, ev);
+    const T b = DIRECTIONAL ? prev : vmin(prev, nv);
+    const T U = local_update(a, b, dl);
+    const T r = vmin(uo, U);
+    const bool dec = valid && (r < uo);
+    changed |= dec;
+    backflow |= dec && ((lane > 0 && r < wv) || (t > 0 && r < prev));
+    tu[valid ? c : dummy] = r;
+    prev = valid ? r : prev;
+    c = c1;
+    ev = ev1;
+    uo = nv;
+    nv = nv1;
+    dl = dl1;
+    hw = hw1;
   }
-  return ballot(changed) != 0ull;
+  return (ballot(changed) ? 1u : 0u) | (ballot(backflow) ? 2u : 0u);
 }
 
-// wave-wide max of x with the lowest lane attaining it (x = -inf: none)
-__device__ __forceinline__ float wave_max(float x, int lane, int* arg) {
-  float m = x;
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    const float y = __shfl_xor(m, o, 64);
-    m = y > m ? y : m;
+// Convergence test of the tile against its halo: true when no node would
+// decrease, T(V) >= V everywhere.  A Gauss-Seidel sweep that changes nothing
+// is exactly this test, but the test has no dependency chain between nodes:
+// each lane walks its column.
+template <typename T, int P>
+__device__ bool tile_converged(const T* tu, const T* td, int w, int hgt, int lane) {
+  bool bad = false;
+  if (lane < w) {
+#pragma unroll 4
+    for (int j = 0; j < hgt; ++j) {
+      const int k = (j + 1) * P + lane + 1;
+      const T a = vmin(tu[k - 1], tu[k + 1]);
+      const T b = vmin(tu[k - P], tu[k + P]);
+      const T U = local_update(a, b, td[k]);
+      bad |= U < tu[k];
+    }
   }
-  const unsigned long long at = ballot(x == m && m > -__builtin_huge_valf());
-  *arg = at ? __builtin_ctzll(at) : -1;
-  return m;
+  return ballot(bad) == 0ull;
+}
+
+// FMSM sweep directions (bit d = direction d: 0 SW, 1 NW, 2 NE, 3 SE) from
+// the sides (bit 0 W, 1 E, 2 S, 3 N) whose neighbour was accepted earlier,
+// following the figure on coarse sweep choice: sweeps start from the corners
+// formed by an earlier vertical and an earlier horizontal side; with earlier
+// sides on one axis only, both corners of each such side.
+__device__ __forceinline__ uint32_t fmsm_dirs(uint32_t sides) {
+  const bool W = sides & 1u, E = sides & 2u, S = sides & 4u, N = sides & 8u;
+  uint32_t d = 0;
+  if ((W || E) && (S || N)) {
+    if (S && W) d |= 1u;
+    if (N && W) d |= 2u;
+    if (N && E) d |= 4u;
+    if (S && E) d |= 8u;
+  } else {
+    if (W) d |= 1u | 2u;
+    if (E) d |= 4u | 8u;
+    if (S) d |= 1u | 8u;
+    if (N) d |= 2u | 4u;
+  }
+  return d;
+}
+
+// Directions raised in a receiving cell by a neighbour on its side s
+// (0 W, 1 E, 2 S, 3 N): the two sweeps that start on that side.
+__device__ __forceinline__ uint32_t side_dirs(int recv_side) {
+  switch (recv_side) {
+    case 0: return 0x1u | 0x2u;  // SW, NW
+    case 1: return 0x4u | 0x8u;  // NE, SE
+    case 2: return 0x1u | 0x8u;  // SW, SE
+    default: return 0x2u | 0x4u; // NW, NE
+  }
 }
 
 // ----------------------------------------------------------------------------
-// persistent solver kernel
+// tiles in LDS
 // ----------------------------------------------------------------------------
 
 struct CellBox {
@@ -315,43 +586,71 @@ __device__ __forceinline__ CellBox cell_box(const Inst& I, int local) {
 }
 
 // Loads the tile (rows -1..hgt, columns -1..w without corners) from u and
-// delta into LDS.  Outside the grid: +inf.
+// delta into LDS; outside the grid: +inf.  Every lane loads from a clamped,
+// in-bounds address and substitutes +inf afterwards, so the loads of a chunk
+// of kChunk rows issue back to back without branches and a tile costs a few
+// memory latencies rather than one per row.
+// fresh: the cell has never been processed and holds no exit node, so its
+// interior values are all +inf and only delta and the halo are read.
 template <typename T, int P>
 __device__ void load_tile(T* tu, T* td, const Inst& I, const CellBox& B, int lane,
-                          bool with_interior) {
-  const T* u = static_cast<const T*>(I.u);
-  const T* dl = static_cast<const T*>(I.delta);
+                          bool with_interior, bool fresh = false) {
+  constexpr int kChunk = 16;
+  const gptr<const T> u = to_global(static_cast<const T*>(I.u));
+  const gptr<const T> dl = to_global(static_cast<const T*>(I.delta));
   const T INF = inf_v<T>();
-  for (int r = -1; r <= B.hgt; ++r) {
-    if (!with_interior && r >= 0 && r < B.hgt) continue;
-    const int j = B.y0 + r;
-    if (lane < B.w) {
-      T v = INF, dv = INF;
-      if (j >= 0 && j < I.ny) {
-        const size_t k = (size_t)j * I.nx + B.x0 + lane;
-        v = ld_coh(u + k);
-        dv = dl[k];
+  const int nx = I.nx, ny = I.ny;
+  const int rows = B.hgt + 2;
+  const bool col = lane < B.w;
+  const int ci = B.x0 + (col ? lane : 0);
+  for (int r0 = 0; r0 < rows; r0 += kChunk) {
+    if (!with_interior && r0 > 0 && r0 + kChunk < rows) continue;
+    T v[kChunk], dv[kChunk];
+#pragma unroll
+    for (int c = 0; c < kChunk; ++c) {
+      const int r = r0 + c - 1;
+      const int j = B.y0 + r;
+      const int jc = j < 0 ? 0 : (j >= ny ? ny - 1 : j);
+      const size_t k = (size_t)jc * nx + ci;
+      const bool halo_row = r < 0 || r >= B.hgt;
+      v[c] = (fresh && !halo_row) ? INF : ld_coh(u + k);
+      dv[c] = dl[k];
+    }
+#pragma unroll
+    for (int c = 0; c < kChunk; ++c) {
+      const int r = r0 + c - 1;  // tile row, -1 .. hgt
+      const int j = B.y0 + r;
+      const bool need = r0 + c < rows && (with_interior || r < 0 || r >= B.hgt);
+      const bool in = j >= 0 && j < ny;
+      if (col && need) {
+        tu[(r + 1) * P + lane + 1] = in ? v[c] : INF;
+        td[(r + 1) * P + lane + 1] = in ? dv[c] : INF;
       }
-      tu[(r + 1) * P + lane + 1] = v;
-      td[(r + 1) * P + lane + 1] = dv;
     }
   }
-  if (lane < B.hgt) {
-    const size_t row = (size_t)(B.y0 + lane) * I.nx;
-    T vw = INF, dw = INF, ve = INF, de = INF;
-    if (B.x0 > 0) {
-      vw = ld_coh(u + row + B.x0 - 1);
-      dw = dl[row + B.x0 - 1];
+  {
+    const int jr = B.y0 + (lane < B.hgt ? lane : 0);
+    const size_t row = (size_t)jr * nx;
+    const int iw = B.x0 > 0 ? B.x0 - 1 : 0;
+    const int ie = B.x1 < nx ? B.x1 : nx - 1;
+    const T vw = ld_coh(u + row + iw), dw = dl[row + iw];
+    const T ve = ld_coh(u + row + ie), de = dl[row + ie];
+    if (lane < B.hgt) {
+      tu[(lane + 1) * P] = B.x0 > 0 ? vw : INF;
+      td[(lane + 1) * P] = B.x0 > 0 ? dw : INF;
+      tu[(lane + 1) * P + B.w + 1] = B.x1 < nx ? ve : INF;
+      td[(lane + 1) * P + B.w + 1] = B.x1 < nx ? de : INF;
     }
-    if (B.x1 < I.nx) {
-      ve = ld_coh(u + row + B.x1);
-      de = dl[row + B.x1];
-    }
-    tu[(lane + 1) * P] = vw;
-    td[(lane + 1) * P] = dw;
-    tu[(lane + 1) * P + B.w + 1] = ve;
-    td[(lane + 1) * P + B.w + 1] = de;
   }
+}
+
+// Writes the whole tile back to u.
+template <typename T, int P>
+__device__ void store_tile(const T* tu, const Inst& I, const CellBox& B, int lane) {
+  T* u = static_cast<T*>(I.u);
+  if (lane < B.w)
+    for (int r = 0; r < B.hgt; ++r)
+      st_coh(u + (size_t)(B.y0 + r) * I.nx + B.x0 + lane, tu[(r + 1) * P + lane + 1]);
 }
 
 // Speed at y_i for eq. cell_value: at the node (integer offset) or the mean of
@@ -368,6 +667,7 @@ __device__ double speed_at(const Inst& I, int side, int along, int other, int wk
     p[np++] = (twice - 1) / 2 + 1;
   }
   const T* F = static_cast<const T*>(I.F);
+  const double* Fd = static_cast<const double*>(I.F);
   double sum = 0.0;
   int cnt = 0;
   for (int m = 0; m < np; ++m) {
@@ -376,26 +676,43 @@ __device__ double speed_at(const Inst& I, int side, int along, int other, int wk
     if (ii < 0 || jj < 0 || ii >= I.nx || jj >= I.ny) continue;
     const size_t k = (size_t)jj * I.nx + ii;
     if (I.mask && !I.mask[k]) continue;
-    sum += (double)F[k];
+    sum += I.qdense ? Fd[k] : (double)F[k];
     cnt++;
   }
   return cnt ? sum / cnt : 0.0;
 }
 
-// Directions raised in a receiving cell by a neighbour on its side s
-// (0 W, 1 E, 2 S, 3 N): the two sweeps that start on that side.
-__device__ __forceinline__ uint32_t side_dirs(int recv_side) {
-  switch (recv_side) {
-    case 0: return 0x1u | 0x2u;  // SW, NW
-    case 1: return 0x4u | 0x8u;  // NE, SE
-    case 2: return 0x1u | 0x8u;  // SW, SE
-    default: return 0x2u | 0x4u; // NW, NE
+// wave-wide max of x with the lowest lane attaining it (x = -inf: none)
+__device__ __forceinline__ float wave_max(float x, int* arg) {
+  float m = x;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const float y = __shfl_xor(m, o, 64);
+    m = y > m ? y : m;
   }
+  const unsigned long long at = ballot(x == m && m > -__builtin_huge_valf());
+  *arg = at ? __builtin_ctzll(at) : -1;
+  return m;
 }
 
-// After a sweep: writes the boundary nodes that decreased since they were
+// Monotonicity of the finite values v of the lanes in `fin`, in ascending
+// lane order: bit 0 non-decreasing, bit 1 non-increasing (wave-uniform).
+template <typename T>
+__device__ uint32_t line_monotone(T v, bool fin, int lane) {
+  const unsigned long long m = ballot(fin);
+  const unsigned long long below = m & ((1ull << lane) - 1ull);
+  const int pred = below ? 63 - __builtin_clzll(below) : lane;
+  const T pv = __shfl(v, pred, 64);
+  const bool has = fin && below;
+  const bool up_bad = has && pv > v;
+  const bool down_bad = has && pv < v;
+  return (ballot(up_bad) ? 0u : 1u) | (ballot(down_bad) ? 0u : 2u);
+}
+
+// After processing: writes the boundary nodes that decreased since they were
 // last published, re-queues neighbours by the add criterion of Algorithm
-// generic_LC_cells, and lowers their cell values (eq. cell_value).
+// generic_LC_cells (FHCM narrows the raised directions by the monotonicity
+// check of Algorithm FHCM), and lowers their cell values (eq. cell_value).
 template <typename T, int P>
 __device__ void publish(const Engine& e, const Inst& I, const CellBox& B, int g, T* tu,
                         const T* td, T pub[4], bool first, int lane) {
@@ -404,6 +721,7 @@ __device__ void publish(const Engine& e, const Inst& I, const CellBox& B, int g,
   bool crit[4];
   float kv[4];
   int karg[4];
+  uint32_t mono[4];
 #pragma unroll
   for (int side = 0; side < 4; ++side) {
     // side 0 W: column 0, 1 E: column w-1 (lane = row); 2 S: row 0, 3 N: row
@@ -416,10 +734,11 @@ __device__ void publish(const Engine& e, const Inst& I, const CellBox& B, int g,
     else if (side == 1) { idx_in = (lane + 1) * P + B.w; idx_out = idx_in + 1; }
     else if (side == 2) { idx_in = P + lane + 1; idx_out = idx_in - P; }
     else { idx_in = B.hgt * P + lane + 1; idx_out = idx_in + P; }
+    if (!ok) idx_in = idx_out = P + 1;
+    const T v = tu[idx_in];
     bool c = false;
     float vmax = -__builtin_huge_valf();
     if (ok) {
-      const T v = tu[idx_in];
       const bool is_src = td[idx_in] == INF && v != INF;
       const bool changed = v < pub[side] || (first && is_src);
       if (v < pub[side]) {
@@ -432,10 +751,11 @@ __device__ void publish(const Engine& e, const Inst& I, const CellBox& B, int g,
       if (v != INF) vmax = (float)v;
     }
     crit[side] = ballot(c) != 0ull;
-    kv[side] = wave_max(vmax, lane, &karg[side]);
+    kv[side] = wave_max(vmax, &karg[side]);
+    mono[side] = e.method == kFhcm ? line_monotone(v, ok && v != INF, lane) : 3u;
   }
   // make the boundary values visible before any neighbour is signalled
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  order_release();
   if (lane < 4) {
     const int side = lane;
     int nb = -1, wk = 0;
@@ -454,140 +774,244 @@ __device__ void publish(const Engine& e, const Inst& I, const CellBox& B, int g,
     }
     if (nb >= 0) {
       float key = __builtin_huge_valf();
-      if (karg[side] >= 0) {
+      if (!e.dag && karg[side] >= 0) {
         const int along = side == 0 ? B.x0 : side == 1 ? B.x1 - 1 : side == 2 ? B.y0 : B.y1 - 1;
         const int other = side <= 1 ? B.y0 + karg[side] : B.x0 + karg[side];
         const double fy = speed_at<T>(I, side, along, other, wk);
         if (fy > 0.0) {
           key = (float)((double)kv[side] + (0.5 * (1 + wk) * I.h) / fy);
-          const unsigned int old =
-              __hip_atomic_fetch_min(&e.key[nb], key_bits(key), __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_AGENT);
-          const float ok = key_float(old);
-          if (ok < key) key = ok;
+          const unsigned int old = __hip_atomic_fetch_min(&e.key[nb], key_bits(key),
+                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const float okey = key_float(old);
+          if (okey < key) key = okey;
         }
       }
       if (crit[side]) {
-        const int recv_side = side ^ 1;  // W<->E, S<->N
-        requeue(e, nb, side_dirs(recv_side), key);
+        const int recv = side ^ 1;  // the receiving cell sees us on the opposite side
+        uint32_t dirs = side_dirs(recv);
+        if (e.method == kFhcm) {
+          // line order N->S for W/E lines (descending lanes), W->E for S/N lines
+          const uint32_t m = mono[side];
+          const bool nondec = side <= 1 ? (m & 2u) : (m & 1u);
+          const bool noninc = side <= 1 ? (m & 1u) : (m & 2u);
+          atomic_add_relaxed(&e.ctl->mon_checks, 1ull);
+          if (nondec || noninc) atomic_add_relaxed(&e.ctl->mon_ok, 1ull);
+          if (nondec != noninc) {
+            // receiver's west side: NW / SW; east: NE / SE; north: NW / NE;
+            // south: SW / SE (first = line non-decreasing)
+            const uint32_t a = recv == 0 ? 0x2u : recv == 1 ? 0x4u : recv == 3 ? 0x2u : 0x1u;
+            const uint32_t b = recv == 0 ? 0x1u : recv == 1 ? 0x8u : recv == 3 ? 0x4u : 0x8u;
+            dirs = nondec ? a : b;
+          }
+        }
+        requeue(e, nb, dirs, key);
       }
     }
   }
 }
 
+// ----------------------------------------------------------------------------
+// persistent solver kernel
+// ----------------------------------------------------------------------------
+
 template <typename T, int S>
 __global__ __launch_bounds__(64) void k_solve(Engine e) {
   constexpr int P = S + 2;
-  __shared__ T tu[P * P];
+  __shared__ T tu[P * P + 64];  // tile + per-lane dummy slots
   __shared__ T td[P * P];
   const int lane = threadIdx.x;
   Ctl* ctl = e.ctl;
-  if (__hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  if (get_err(ctl)) return;
   int backoff = 0;
+  unsigned long long t0 = e.profile ? wall_clock64() : 0ull;
+  unsigned long long nsweeps = 0, nchecks = 0;  // this wave's totals
   for (;;) {
-    const int g = q_pop(e, lane);
+    int ring = 0;
+    const int g = e.q.nb == 1 ? q_pop_ticket(e, lane) : q_pop(e, lane, &ring);
     if (g < 0) {
-      const bool stop = ld64(&ctl->active) == 0ull ||
-                        __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+      const bool stop = e.q.nb == 1 || ld64(&ctl->active) == 0ull || get_err(ctl) ||
                         past_deadline(ctl);
       if (stop) break;
       if (backoff < 8) ++backoff;
       for (int z = 0; z < backoff; ++z) __builtin_amdgcn_s_sleep(2);
+      tick(e, &ctl->t_idle, &t0, lane);
       continue;
     }
     backoff = 0;
-    const Inst& I = inst_of(e, g);
+    unsigned long long tr[5] = {0, 0, 0, 0, 0};
+    const unsigned long long sw0 = nsweeps, ch0 = nchecks;
+    if (e.trace) tr[0] = wall_clock64();
+    const Inst I = inst_of(e, g);  // by value: fields stay in registers
     const CellBox B = cell_box(I, g - I.cell0);
-    // claim the cell (acquire: halo values published before it was queued
-    // are visible)
-    uint32_t fl = 0;
-    int first = 0;
+    uint32_t fl = 0, ordb = 0;
+    int first = 0, done1 = 0;
+    uint32_t run_state = kRunning;  // the state word written by claim (lane 0)
     if (lane == 0) {
-      const uint32_t old = __hip_atomic_exchange(&e.st[g], kRunning, __ATOMIC_ACQUIRE,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t old = claim(e, g);
+      run_state = (old & kDone1) | kRunning;
       fl = (old >> kFlagShift) & 0xFu;
+      done1 = (old & kDone1) != 0u;
       const uint32_t v = ld_coh(&e.visits[g]);
       st_coh(&e.visits[g], v + 1u);
       first = v == 0u;
-      const unsigned long long tot = __hip_atomic_fetch_add(&ctl->visits, 1ull, __ATOMIC_RELAXED,
-                                                            __HIP_MEMORY_SCOPE_AGENT);
+      if (e.dag) ordb = e.ord[g];
+      const unsigned long long tot = atomic_add_relaxed(&ctl->visits, 1ull);
       if (tot >= ctl->guard) set_err(ctl, kErrGuard);
     }
     fl = (uint32_t)bcast((int)fl, 0);
+    ordb = (uint32_t)bcast((int)ordb, 0);
+    done1 = bcast(done1, 0);
     bool is_first = bcast(first, 0) != 0;
-    load_tile<T, P>(tu, td, I, B, lane, true);
+    if (e.dag && !done1) fl |= fmsm_dirs(ordb & 0xFu);
+    order_acquire();
+    tick(e, &ctl->t_claim, &t0, lane);
+    // a cell's interior is written only by its own processing
+    load_tile<T, P>(tu, td, I, B, lane, true, e.dag && is_first && !(ordb & kOrdSource));
     T pub[4];
     pub[0] = lane < B.hgt ? tu[(lane + 1) * P + 1] : inf_v<T>();
     pub[1] = lane < B.hgt ? tu[(lane + 1) * P + B.w] : inf_v<T>();
     pub[2] = lane < B.w ? tu[P + lane + 1] : inf_v<T>();
     pub[3] = lane < B.w ? tu[B.hgt * P + lane + 1] : inf_v<T>();
-    unsigned long long nsweeps = 0, nchecks = 0;
-    int sched[4];
+    tick(e, &ctl->t_load, &t0, lane);
+    if (e.trace) tr[1] = wall_clock64();
+    bool aborted = false;
     for (;;) {
-      // preferred directions first, in canonical order, then the others;
-      // after four sweeps the canonical loop
-      {
-        int n = 0;
+      if (e.method == kFmsm) {
+        if (ordb & kOrdConverge) {
+          // cells holding exit nodes (or unreached by the coarse front): plain
+          // FSM to convergence
+          for (int k = 0;; ++k) {
+            const bool ch = sweep_tile<T, P, false>(tu, td, B.w, B.hgt, k & 3, lane) & 1u;
+            if (ch) nsweeps++; else nchecks++;
+            if (!ch || k > 4096) break;
+          }
+        } else {
+          // at most four sweeps in the coarse-upwind directions, with
+          // sweep-directional updates
+          const uint32_t dirs = fmsm_dirs(ordb & 0xFu);
+          for (int d = 0; d < 4; ++d)
+            if (dirs & (1u << d)) {
+              const bool ch = sweep_tile<T, P, true>(tu, td, B.w, B.hgt, d, lane) & 1u;
+              if (ch) nsweeps++; else nchecks++;
+            }
+        }
+        tick(e, &ctl->t_sweep, &t0, lane);
+      } else if (e.method == kFhcm) {
+        // one non-directional sweep per flagged direction, canonical order
+        for (int d = 0; d < 4; ++d)
+          if (fl & (1u << d)) {
+            const bool ch = sweep_tile<T, P, false>(tu, td, B.w, B.hgt, d, lane) & 1u;
+            if (ch) nsweeps++; else nchecks++;
+          }
+        tick(e, &ctl->t_sweep, &t0, lane);
+        publish<T, P>(e, I, B, g, tu, td, pub, is_first, lane);
+        is_first = false;
+        tick(e, &ctl->t_publish, &t0, lane);
+      } else {
+        // exact: preferred directions first, in canonical order, then the
+        // others; after four sweeps the canonical loop; until converged
+        int sched[4], n = 0;
         for (int d = 0; d < 4; ++d)
           if (fl & (1u << d)) sched[n++] = d;
         for (int d = 0; d < 4; ++d)
           if (!(fl & (1u << d))) sched[n++] = d;
-      }
-      bool aborted = false;
-      for (int k = 0;; ++k) {
-        const int dir = k < 4 ? sched[k] : (k & 3);
-        const bool ch = sweep_tile<T, P>(tu, td, B.w, B.hgt, dir, lane);
-        if (ch) nsweeps++; else nchecks++;
-        if (ch || is_first) {
+        for (int k = 0;; ++k) {
+          const int dir = k < 4 ? sched[k] : (k & 3);
+          const uint32_t res = sweep_tile<T, P, false>(tu, td, B.w, B.hgt, dir, lane);
+          const bool ch = res & 1u;
+          if (ch) nsweeps++; else nchecks++;
+          tick(e, &ctl->t_sweep, &t0, lane);
+          if (e.eager && (ch || is_first)) {
+            publish<T, P>(e, I, B, g, tu, td, pub, is_first, lane);
+            is_first = false;
+            tick(e, &ctl->t_publish, &t0, lane);
+          }
+          if (!(res & 2u)) break;  // no change, or no backflow: converged
+          if (k > 4096) {  // a cell solve always terminates; guard anyway
+            if (lane == 0) set_err(ctl, kErrGuard);
+            aborted = true;
+            break;
+          }
+        }
+        if (!e.eager) {
           publish<T, P>(e, I, B, g, tu, td, pub, is_first, lane);
           is_first = false;
-        }
-        if (!ch) break;
-        if (k > 4096) {  // a cell solve always terminates; guard anyway
-          if (lane == 0) set_err(ctl, kErrGuard);
-          aborted = true;
-          break;
+          tick(e, &ctl->t_publish, &t0, lane);
         }
       }
       if (aborted) break;
-      // write the interior back (boundary nodes are already published)
-      {
-        T* u = static_cast<T*>(I.u);
-        for (int r = 1; r + 1 < B.hgt; ++r)
-          if (lane >= 1 && lane + 1 < B.w)
-            st_coh(u + (size_t)(B.y0 + r) * I.nx + B.x0 + lane, tu[(r + 1) * P + lane + 1]);
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      if (e.trace && !tr[2]) tr[2] = wall_clock64();
+      store_tile<T, P>(tu, I, B, lane);
+      order_release();
       int again = 0;
       if (lane == 0) {
-        uint32_t exp = kRunning;
-        if (__hip_atomic_compare_exchange_strong(&e.st[g], &exp, 0u, __ATOMIC_RELEASE,
-                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-          __hip_atomic_fetch_add(&ctl->active, ~0ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (e.dag && !done1) {
+          // first processing done: a later neighbour starts once all its
+          // earlier neighbours are done
+          for (int side = 0; side < 4; ++side) {
+            int nb = -1;
+            if (side == 0 && B.cx > 0) nb = g - 1;
+            if (side == 1 && B.cx + 1 < I.kx) nb = g + 1;
+            if (side == 2 && B.cy > 0) nb = g - I.kx;
+            if (side == 3 && B.cy + 1 < I.ky) nb = g + I.kx;
+            if (nb < 0 || (ordb & (1u << side))) continue;  // none, or earlier
+            if (e.ord[nb] & kOrdEmpty) continue;
+            if (atomic_add_relaxed(&e.deps[nb], -1) == 1) release_first(e, nb);
+          }
+          done1 = 1;
+        }
+        uint32_t exp = run_state;
+        const bool idle =
+            e.method == kFmsm ||
+            __hip_atomic_compare_exchange_strong(&e.st[g], &exp, kDone1, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (idle) {
+          if (e.method == kFmsm) st_coh(&e.st[g], kDone1);
+          atomic_add_relaxed(&ctl->active, ~0ull);
+          q_done(e, ring);
         } else {
-          // re-queued while running: take it again at once
-          const uint32_t old = __hip_atomic_exchange(&e.st[g], kRunning, __ATOMIC_ACQUIRE,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
+          // re-requested while running: take it again at once
+          const uint32_t old = claim(e, g);
+          run_state = (old & kDone1) | kRunning;
           fl = (old >> kFlagShift) & 0xFu;
           const uint32_t v = ld_coh(&e.visits[g]);
           st_coh(&e.visits[g], v + 1u);
-          const unsigned long long tot = __hip_atomic_fetch_add(
-              &ctl->visits, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const unsigned long long tot = atomic_add_relaxed(&ctl->visits, 1ull);
           if (tot >= ctl->guard) set_err(ctl, kErrGuard);
           again = 1;
         }
       }
       again = bcast(again, 0);
+      tick(e, &ctl->t_finish, &t0, lane);
       if (!again) break;
-      if (__hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+      if (get_err(ctl)) break;
       fl = (uint32_t)bcast((int)fl, 0);
+      done1 = 1;
+      order_acquire();
       load_tile<T, P>(tu, td, I, B, lane, false);  // fresh halo only
     }
     if (lane == 0) {
-      __hip_atomic_fetch_add(&ctl->sweeps, nsweeps, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&ctl->checks, nchecks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (e.trace) {
+        const unsigned int slot = atomic_add_relaxed(e.trace_n, 1u);
+        if (slot < e.trace_cap) {
+          unsigned long long* t = e.trace + (size_t)slot * 8;
+          t[0] = (unsigned long long)g | (((nsweeps - sw0) & 0xffffull) << 32) |
+                 (((nchecks - ch0) & 0xffffull) << 48);
+          t[1] = e.ready_at[g];
+          t[2] = tr[0];
+          t[3] = tr[1];
+          t[4] = tr[2];
+          t[5] = wall_clock64();
+          t[6] = __builtin_amdgcn_s_getreg(4 | (0 << 6) | (31 << 11));  // HW_ID
+          t[7] = 0;
+        }
+      }
     }
-    if (__hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+    if (get_err(ctl)) break;
+  }
+  if (lane == 0) {
+    atomic_add_relaxed(&ctl->sweeps, nsweeps);
+    atomic_add_relaxed(&ctl->checks, nchecks);
   }
 }
 
@@ -595,15 +1019,25 @@ __global__ __launch_bounds__(64) void k_solve(Engine e) {
 // preparation kernels
 // ----------------------------------------------------------------------------
 
+__device__ __forceinline__ const Inst& inst_at(const Engine& e, int k) {
+  return e.args_inst ? e.one : e.inst[k];
+}
+
 // Cell states, queue rings and control block.
 __global__ void k_prep_cells(Engine e) {
   const int ninst = e.ninst;
   const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t c = tid; c < (size_t)e.ncells; c += stride) {
-    e.st[c] = 0u;
+    // dependency ordering: the state's kRunning bit of a cell whose first
+    // processing has not finished stays clear; kDone1 set means "idle"
+    e.st[c] = e.dag ? 0u : kDone1;
     e.visits[c] = 0u;
     e.key[c] = 0xFF800000u;  // key_bits(+inf)
+    if (e.dag) {
+      e.deps[c] = 0;
+      e.ord[c] = 0;
+    }
   }
   if (ninst > 1) {
     // instance of every cell (instances are laid out by increasing cell0)
@@ -622,12 +1056,11 @@ __global__ void k_prep_cells(Engine e) {
   for (size_t k = tid; k < (size_t)e.q.nb; k += stride) {
     e.q.head[k * kCtrStride] = 0ull;
     e.q.tail[k * kCtrStride] = 0ull;
+    e.q.inflight[k * kCtrStride] = 0ull;
   }
   if (tid == 0) {
     *e.q.cursor = 0ull;
     Ctl* c = e.ctl;
-    c->guard = e.guard;
-    c->deadline = wall_clock64() + e.timeout_ticks;
     c->active = 0ull;
     c->visits = 0ull;
     c->sweeps = 0ull;
@@ -637,24 +1070,28 @@ __global__ void k_prep_cells(Engine e) {
     c->mon_ok = 0ull;
     c->resid_bits = 0ull;
     c->err = 0u;
-    c->done_waves = 0u;
+    c->t_idle = c->t_claim = c->t_load = c->t_sweep = c->t_publish = c->t_finish = 0ull;
+    c->guard = e.guard;
+    c->deadline = wall_clock64() + e.timeout_ticks;
   }
 }
 
 // delta = h/F on accessible nodes (validating F), +inf on obstacles.
 template <typename T>
 __global__ void k_prep_nodes(Engine e) {
-  const Inst& I = e.ninst == 1 ? e.one : e.inst[blockIdx.y];
+  const Inst& I = inst_at(e, blockIdx.y);
   const size_t n = (size_t)I.nx * I.ny;
   const T* F = static_cast<const T*>(I.F);
+  const double* Fd = static_cast<const double*>(I.F);
   T* dl = static_cast<T*>(I.delta);
+  const bool f64_input = I.qdense != nullptr;  // coarse problems carry double speeds
   bool bad = false;
   for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
        k += (size_t)gridDim.x * blockDim.x) {
     const bool acc = I.mask ? I.mask[k] != 0 : true;
     T d = inf_v<T>();
     if (acc) {
-      const double f = (double)F[k];
+      const double f = f64_input ? Fd[k] : (double)F[k];
       if (!(f > 0.0) || !isfinite(f)) bad = true;
       d = (T)(I.h / f);
     }
@@ -665,7 +1102,7 @@ __global__ void k_prep_nodes(Engine e) {
 
 // Source validation (index range, accessibility, finite q).
 __global__ void k_check_sources(Engine e) {
-  const Inst& I = e.ninst == 1 ? e.one : e.inst[blockIdx.y];
+  const Inst& I = inst_at(e, blockIdx.y);
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < I.nsrc; s += gridDim.x * blockDim.x) {
     const long long k = I.src[s];
     const double q = I.q ? I.q[s] : 0.0;
@@ -674,20 +1111,47 @@ __global__ void k_check_sources(Engine e) {
   }
 }
 
+__device__ __forceinline__ int cell_of_node(const Inst& I, int i, int j) {
+  int cx = I.balanced ? (int)(((long long)i * I.kx) / I.nx) : i / I.s;
+  int cy = I.balanced ? (int)(((long long)j * I.ky) / I.ny) : j / I.s;
+  if (cx >= I.kx) cx = I.kx - 1;
+  if (cy >= I.ky) cy = I.ky - 1;
+  while (cx > 0 && cell_lo(cx, I.nx, I.kx, I.s, I.balanced) > i) cx--;
+  while (cx + 1 < I.kx && cell_lo(cx + 1, I.nx, I.kx, I.s, I.balanced) <= i) cx++;
+  while (cy > 0 && cell_lo(cy, I.ny, I.ky, I.s, I.balanced) > j) cy--;
+  while (cy + 1 < I.ky && cell_lo(cy + 1, I.ny, I.ky, I.s, I.balanced) <= j) cy++;
+  return I.cell0 + cy * I.kx + cx;
+}
+
+// u = +inf, or the dense exit costs (coarse problems: those nodes are frozen
+// and, without dependency ordering, their cells queued).
 template <typename T>
 __global__ void k_init_u(Engine e) {
-  if (__hip_atomic_load(&e.ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-  const Inst& I = e.ninst == 1 ? e.one : e.inst[blockIdx.y];
+  if (get_err(e.ctl)) return;
+  const Inst& I = inst_at(e, blockIdx.y);
   const size_t n = (size_t)I.nx * I.ny;
   T* u = static_cast<T*>(I.u);
+  T* dl = static_cast<T*>(I.delta);
   for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
-       k += (size_t)gridDim.x * blockDim.x)
-    u[k] = inf_v<T>();
+       k += (size_t)gridDim.x * blockDim.x) {
+    T v = inf_v<T>();
+    if (I.qdense && I.qdense[k] < __builtin_huge_val() && (!I.mask || I.mask[k])) {
+      v = (T)I.qdense[k];
+      dl[k] = inf_v<T>();
+      if (!e.dag) {
+        const int g = cell_of_node(I, (int)(k % I.nx), (int)(k / I.nx));
+        __hip_atomic_fetch_min(&e.key[g], key_bits((float)v), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        requeue(e, g, e.method == kFhcm ? 0xFu : 0u, (float)v);
+      }
+    }
+    u[k] = v;
+  }
 }
 
 __device__ __forceinline__ void atomic_min_val(double* p, double v) {
   unsigned long long* a = reinterpret_cast<unsigned long long*>(p);
-  unsigned long long old = *a;
+  unsigned long long old = ld_coh(a);
   while (__builtin_bit_cast(double, old) > v) {
     if (__hip_atomic_compare_exchange_strong(a, &old, __builtin_bit_cast(unsigned long long, v),
                                              __ATOMIC_RELAXED, __ATOMIC_RELAXED,
@@ -697,7 +1161,7 @@ __device__ __forceinline__ void atomic_min_val(double* p, double v) {
 }
 __device__ __forceinline__ void atomic_min_val(float* p, float v) {
   unsigned int* a = reinterpret_cast<unsigned int*>(p);
-  unsigned int old = *a;
+  unsigned int old = ld_coh(a);
   while (__builtin_bit_cast(float, old) > v) {
     if (__hip_atomic_compare_exchange_strong(a, &old, __builtin_bit_cast(unsigned int, v),
                                              __ATOMIC_RELAXED, __ATOMIC_RELAXED,
@@ -706,12 +1170,15 @@ __device__ __forceinline__ void atomic_min_val(float* p, float v) {
   }
 }
 
-// u = min q at sources, sources frozen (delta = +inf), their cells queued
-// (Algorithm generic_LC_cells, cell and fine-grid initialisation).
+// u = min q at sources, sources frozen (delta = +inf), and -- unless cells
+// are ordered by dependency counts -- their cells queued (Algorithm
+// generic_LC_cells, cell and fine-grid initialisation; Algorithm FHCM for the
+// key 0 and four raised directions).
 template <typename T>
 __global__ void k_apply_sources(Engine e) {
-  if (__hip_atomic_load(&e.ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-  const Inst& I = e.ninst == 1 ? e.one : e.inst[blockIdx.y];
+  if (get_err(e.ctl)) return;
+  const Inst& I = inst_at(e, blockIdx.y);
+  if (I.qdense) return;
   T* u = static_cast<T*>(I.u);
   T* dl = static_cast<T*>(I.delta);
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < I.nsrc; s += gridDim.x * blockDim.x) {
@@ -719,24 +1186,133 @@ __global__ void k_apply_sources(Engine e) {
     const double q = I.q ? I.q[s] : 0.0;
     atomic_min_val(u + k, (T)q);
     dl[k] = inf_v<T>();
-    const int i = (int)(k % I.nx), j = (int)(k / I.nx);
-    // cell containing (i, j)
-    int cx = 0, cy = 0;
-    while (cx + 1 < I.kx && cell_lo(cx + 1, I.nx, I.kx, I.s, I.balanced) <= i) cx++;
-    while (cy + 1 < I.ky && cell_lo(cy + 1, I.ny, I.ky, I.s, I.balanced) <= j) cy++;
-    const int g = I.cell0 + cy * I.kx + cx;
+    if (e.dag) continue;
+    const int g = cell_of_node(I, (int)(k % I.nx), (int)(k / I.nx));
     const float key = e.method == kFhcm ? 0.0f : (float)q;
     __hip_atomic_fetch_min(&e.key[g], key_bits(key), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t fl = e.method == kFhcm ? 0xFu : 0u;
-    requeue(e, g, fl, key);
+    requeue(e, g, e.method == kFhcm ? 0xFu : 0u, key);
+  }
+}
+
+// Coarse grid inputs (FMSM Part I): per cell the mean speed over its
+// accessible nodes, whether it has one, and (initially +inf) the smallest exit
+// cost of its exit nodes.  One wave per cell: lane l sums column l bottom to
+// top (loads of a row are contiguous), then lane 0 adds the column sums left
+// to right -- a fixed order the CPU oracle uses as well.
+template <typename T>
+__global__ __launch_bounds__(64) void k_coarse_cells(Engine e, const CoarseOut* co) {
+  __shared__ double csum[64];
+  __shared__ int ccnt[64];
+  const int lane = threadIdx.x;
+  for (int g = blockIdx.x; g < e.ncells; g += gridDim.x) {
+    const int k = inst_index(e, g);
+    const Inst& I = inst_at(e, k);
+    const CellBox B = cell_box(I, g - I.cell0);
+    const T* F = static_cast<const T*>(I.F);
+    double col = 0.0;
+    int cnt = 0;
+    if (lane < B.w) {
+#pragma unroll 8
+      for (int j = B.y0; j < B.y1; ++j) {
+        const size_t n = (size_t)j * I.nx + B.x0 + lane;
+        const bool acc = !I.mask || I.mask[n];
+        const double f = (double)F[n];
+        if (acc) {
+          col += f;
+          cnt++;
+        }
+      }
+    }
+    csum[lane] = col;
+    ccnt[lane] = cnt;
+    __syncthreads();
+    if (lane == 0) {
+      double sum = 0.0;
+      int c = 0;
+      for (int l = 0; l < B.w; ++l) {
+        sum += csum[l];
+        c += ccnt[l];
+      }
+      const int cl = g - I.cell0;
+      co[k].F[cl] = c ? sum / c : 1.0;
+      co[k].mask[cl] = c > 0;
+      co[k].q[cl] = __builtin_huge_val();
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_coarse_sources(Engine e, const CoarseOut* co) {
+  const int k = blockIdx.y;
+  const Inst& I = inst_at(e, k);
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < I.nsrc; s += gridDim.x * blockDim.x) {
+    const long long n = I.src[s];
+    const double q = I.q ? I.q[s] : 0.0;
+    const int g = cell_of_node(I, (int)(n % I.nx), (int)(n / I.nx));
+    atomic_min_val(co[k].q + (g - I.cell0), q);
+  }
+}
+
+// Order of the cells: exit cells first by (q, index), then by (coarse value,
+// index) -- the acceptance order of Fast Marching on the coarse grid -- and
+// cells the coarse front does not reach last, by index.  Each cell counts
+// the accessible neighbours that precede it.
+__global__ void k_dag(Engine e, const CoarseOut* co) {
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < e.ncells; g += gridDim.x * blockDim.x) {
+    const int k = inst_index(e, g);
+    const Inst& I = inst_at(e, k);
+    const CoarseOut C = co[k];
+    const int c = g - I.cell0;
+    if (!C.mask[c]) {
+      e.ord[g] = kOrdEmpty;
+      e.st[g] = kDone1;
+      continue;
+    }
+    auto cls = [&](int x) { return C.q[x] < __builtin_huge_val() ? 0 : 1; };
+    auto val = [&](int x) { return C.q[x] < __builtin_huge_val() ? C.q[x] : C.u[x]; };
+    auto before = [&](int x, int y) {  // does cell x precede cell y?
+      const int cxx = cls(x), cyy = cls(y);
+      if (cxx != cyy) return cxx < cyy;
+      const double vx = val(x), vy = val(y);
+      if (vx != vy) return vx < vy;
+      return x < y;
+    };
+    const int cx = c % I.kx, cy = c / I.kx;
+    uint8_t o = (cls(c) == 0 || !(val(c) < __builtin_huge_val())) ? kOrdConverge : 0;
+    if (cls(c) == 0) o |= kOrdSource;
+    int n = 0;
+    for (int side = 0; side < 4; ++side) {
+      int nb = -1;
+      if (side == 0 && cx > 0) nb = c - 1;
+      if (side == 1 && cx + 1 < I.kx) nb = c + 1;
+      if (side == 2 && cy > 0) nb = c - I.kx;
+      if (side == 3 && cy + 1 < I.ky) nb = c + I.kx;
+      if (nb < 0 || !C.mask[nb]) continue;
+      if (before(nb, c)) {
+        o |= (uint8_t)(1u << side);
+        n++;
+      }
+    }
+    e.ord[g] = o;
+    e.deps[g] = n;
+    atomic_add_relaxed(&e.ctl->active, 1ull);
+  }
+}
+
+// Queues the cells without earlier neighbours (after every count is set).
+__global__ void k_dag_roots(Engine e) {
+  if (get_err(e.ctl)) return;
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < e.ncells; g += gridDim.x * blockDim.x) {
+    if (e.ord[g] & kOrdEmpty) continue;
+    if (e.deps[g] == 0) release_first(e, g);
   }
 }
 
 // Fixed-point residual max |T(u)_k - u_k| / u_k in FP64 over accessible,
-// non-source nodes with finite u (inf where u is inf but T(u) is finite).
+// non-exit nodes with finite u (inf where u is inf but T(u) is finite).
 template <typename T>
 __global__ void k_residual(Engine e) {
-  const Inst& I = e.ninst == 1 ? e.one : e.inst[blockIdx.y];
+  const Inst& I = inst_at(e, blockIdx.y);
   const T* u = static_cast<const T*>(I.u);
   const T* F = static_cast<const T*>(I.F);
   const T* dl = static_cast<const T*>(I.delta);
@@ -744,7 +1320,7 @@ __global__ void k_residual(Engine e) {
   double mx = 0.0;
   for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
        k += (size_t)gridDim.x * blockDim.x) {
-    if (dl[k] == inf_v<T>()) continue;  // obstacle or source
+    if (dl[k] == inf_v<T>()) continue;  // obstacle or exit node
     const int i = (int)(k % I.nx), j = (int)(k / I.nx);
     const double INF = __builtin_huge_val();
     const double uW = i > 0 ? (double)u[k - 1] : INF;
@@ -752,7 +1328,8 @@ __global__ void k_residual(Engine e) {
     const double uS = j > 0 ? (double)u[k - I.nx] : INF;
     const double uN = j + 1 < I.ny ? (double)u[k + I.nx] : INF;
     const double a = uW < uE ? uW : uE, b = uS < uN ? uS : uN;
-    const double t = local_update(a, b, I.h / (double)F[k]);
+    double t = local_update(a, b, I.h / (double)F[k]);
+    if (t != t) t = INF;
     const double v = (double)u[k];
     double r;
     if (v == INF) r = (t == INF) ? 0.0 : INF;
@@ -766,6 +1343,13 @@ __global__ void k_residual(Engine e) {
   if ((threadIdx.x & 63) == 0 && mx > 0.0)
     __hip_atomic_fetch_max(&e.ctl->resid_bits, __builtin_bit_cast(unsigned long long, mx),
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename S, typename D>
+__global__ void k_convert(const S* src, D* dst, int64_t n) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x)
+    dst[k] = (D)src[k];
 }
 
 }  // namespace
@@ -797,11 +1381,6 @@ hipError_t launch_prepare(const Engine& e, int64_t max_nodes, hipStream_t stream
   return hipGetLastError();
 }
 
-size_t solve_lds_bytes(int dtype, int tile) {
-  const size_t P = (size_t)tile + 2;
-  return 2 * P * P * (dtype == 0 ? sizeof(double) : sizeof(float));
-}
-
 hipError_t launch_solve(const Engine& e, int workers, int tile, hipStream_t stream) {
   const dim3 g(workers), b(64);
   if (e.dtype == 0) {
@@ -820,6 +1399,35 @@ hipError_t launch_residual(const Engine& e, int64_t max_nodes, hipStream_t strea
   const dim3 gn(grid_for(max_nodes, 256, e.ninst > 1 ? 256 : 4096), e.ninst);
   if (e.dtype == 0) hipLaunchKernelGGL(k_residual<double>, gn, dim3(256), 0, stream, e);
   else hipLaunchKernelGGL(k_residual<float>, gn, dim3(256), 0, stream, e);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse_inputs(const Engine& fine, const CoarseOut* co_dev, int max_src,
+                                hipStream_t stream) {
+  const dim3 gc(fine.ncells < 65535 ? fine.ncells : 65535);
+  if (fine.dtype == 0) hipLaunchKernelGGL(k_coarse_cells<double>, gc, dim3(64), 0, stream, fine, co_dev);
+  else hipLaunchKernelGGL(k_coarse_cells<float>, gc, dim3(64), 0, stream, fine, co_dev);
+  hipLaunchKernelGGL(k_coarse_sources, dim3(grid_for(max_src, 64, 1024), fine.ninst), dim3(64), 0,
+                     stream, fine, co_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_dag(const Engine& fine, const CoarseOut* co_dev, int, hipStream_t stream) {
+  const dim3 gc(grid_for(fine.ncells, 256, 4096));
+  hipLaunchKernelGGL(k_dag, gc, dim3(256), 0, stream, fine, co_dev);
+  hipLaunchKernelGGL(k_dag_roots, gc, dim3(256), 0, stream, fine);
+  return hipGetLastError();
+}
+
+hipError_t launch_convert(const void* src, int src_dtype, void* dst, int dst_dtype, int64_t n,
+                          hipStream_t stream) {
+  const dim3 g(grid_for(n, 256, 8192)), b(256);
+  if (src_dtype == 0 && dst_dtype == 1)
+    hipLaunchKernelGGL((k_convert<double, float>), g, b, 0, stream, (const double*)src, (float*)dst, n);
+  else if (src_dtype == 1 && dst_dtype == 0)
+    hipLaunchKernelGGL((k_convert<float, double>), g, b, 0, stream, (const float*)src, (double*)dst, n);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -1,0 +1,78 @@
+// Host-side internals shared by the C-ABI translation units (api.cpp,
+// serve.cpp).  Not installed.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/eik.h"
+#include "engine.h"
+
+namespace eik {
+
+extern thread_local std::string g_err;
+int fail(int code, const char* fmt, ...);
+double now_s();
+
+#define HIP_TRY(expr)                                                                 \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return ::eik::fail(EIK_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// A device allocation that only grows.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipError_t ensure(size_t need);
+  template <typename T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+// Buffers of one engine run.
+struct Solver {
+  DevBuf delta, st, visits, cell_inst, key, deps, ord, slot, head, tail, inflight, cursor, ctl, inst;
+};
+
+// Per-device workspace, reused by every call on that device.
+struct Workspace {
+  std::mutex mu;
+  Solver fine, coarse;
+  DevBuf F, u, mask, src, q;          // staging of host inputs
+  DevBuf cF, cmask, cq, cu, cout;     // coarse problems
+  DevBuf F64, u64;                    // FP64 re-solve of FP32 problems
+  DevBuf ready_at, trace, trace_n;    // diagnostic trace (EIK_TRACE)
+  Ctl* ctl_host = nullptr;            // pinned: fine and coarse control blocks
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  int cus = 0;
+  int wall_khz = 0;
+  bool ready = false;
+};
+
+struct Tiling {
+  int s, kx, ky, balanced, extent;
+};
+
+struct RunInfo {
+  float kernel_ms;
+  int64_t cells;
+};
+
+int workspace(Workspace** out);
+eik_opts default_opts();
+int check_opts(const eik_opts& o);
+int std_cells(int n, int s);
+int make_tiling(int nx, int ny, int s, int method, Tiling* t);
+int default_cell(int nx, int ny, int method);
+size_t dsize(int dtype);
+int validate_host(const eik_problem& p, int dtype);
+int validate_shape(const eik_problem& p);
+// Solves n problems (validated) with one persistent launch.
+int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, RunInfo* info);
+int refine_fp64(int n, const eik_problem* probs, const std::vector<Inst>& inst, const eik_opts& o,
+                hipStream_t stream);
+
+}  // namespace eik

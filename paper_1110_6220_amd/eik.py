@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libeik.so")
 EIK_OK, EIK_EINVAL, EIK_ENOMEM, EIK_EDEVICE, EIK_EBUDGET, EIK_ENOTCONV, EIK_EBUSY = 0, -1, -2, -3, -4, -5, -6
 F64, F32 = 0, 1
 METHODS = {"exact": 0, "hcm": 0, "fmsm": 1, "fhcm": 2}
+SCHEDULES = {"auto": 0, "coarse": 1, "bands": 2, "fifo": 3}
 
 # Every function include/eik.h declares.
 EXPORTS = ("eik_solve", "eik_solve_batched", "eik_serve_create", "eik_serve_submit",
@@ -36,7 +37,9 @@ class Opts(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int), ("method", ctypes.c_int), ("cell", ctypes.c_int32),
                 ("band", ctypes.c_double), ("device_ptrs", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("max_cell_visits", ctypes.c_uint64),
-                ("residual_check", ctypes.c_int32), ("workers", ctypes.c_int32)]
+                ("residual_check", ctypes.c_int32), ("workers", ctypes.c_int32),
+                ("band_window", ctypes.c_int32), ("eager_publish", ctypes.c_int32),
+                ("schedule", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -46,11 +49,11 @@ class Stats(ctypes.Structure):
                 ("band_steps", ctypes.c_uint64), ("mon_checks", ctypes.c_uint64),
                 ("mon_ok", ctypes.c_uint64), ("max_residual", ctypes.c_double),
                 ("cell_used", ctypes.c_int32), ("band_used", ctypes.c_double),
-                ("fell_back_to_f64", ctypes.c_int32)]
+                ("fell_back_to_f64", ctypes.c_int32), ("cells_total", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}
-        cells = max(int(self.cells), 1)
+        cells = max(int(self.cells_total or self.cells), 1)
         d["AvHR"] = self.cell_visits / cells
         d["AvS"] = (self.sweeps + self.checks) / cells
         return d
@@ -103,9 +106,11 @@ def _is_torch(x) -> bool:
     return type(x).__module__.startswith("torch")
 
 
-def _opts(dtype, method, cell, band, device, stream, residual_check, workers, max_cell_visits):
+def _opts(dtype, method, cell, band, device, stream, residual_check, workers, max_cell_visits,
+          band_window=0, eager_publish=False, schedule="auto"):
     return Opts(dtype, METHODS[method], int(cell), float(band), int(device),
-                stream, int(max_cell_visits), int(bool(residual_check)), int(workers))
+                stream, int(max_cell_visits), int(bool(residual_check)), int(workers),
+                int(band_window), int(bool(eager_publish)), SCHEDULES[schedule])
 
 
 def _marshal(F, h, src, q, mask, u_out, dtype):
@@ -148,12 +153,13 @@ def _stream_of(device: bool):
 
 
 def eik_solve(F, h, src, q=None, mask=None, u_out=None, *, dtype="f64", method="exact",
-              cell=0, band=0.0, workers=0, residual_check=False, max_cell_visits=0):
+              cell=0, band=0.0, workers=0, residual_check=False, max_cell_visits=0,
+              band_window=0, eager_publish=False, schedule="auto"):
     """Solves |grad u| F = 1 with u = q on src (see include/eik.h).
     Returns (u, stats dict)."""
     p, keep, u_out, device = _marshal(F, h, src, q, mask, u_out, dtype)
     o = _opts(F64 if dtype == "f64" else F32, method, cell, band, device, _stream_of(device),
-              residual_check, workers, max_cell_visits)
+              residual_check, workers, max_cell_visits, band_window, eager_publish, schedule)
     st = Stats()
     _check(lib.eik_solve(p.nx, p.ny, p.h, p.F, p.mask, p.nsrc, p.src, p.q, p.u_out,
                          ctypes.byref(o), ctypes.byref(st)))
@@ -162,7 +168,8 @@ def eik_solve(F, h, src, q=None, mask=None, u_out=None, *, dtype="f64", method="
 
 
 def eik_solve_batched(problems, *, dtype="f64", method="exact", cell=0, band=0.0, workers=0,
-                      residual_check=False, max_cell_visits=0):
+                      residual_check=False, max_cell_visits=0, band_window=0,
+                      eager_publish=False, schedule="auto"):
     """problems: list of dicts with F, h, src and optional q, mask, u_out.
     Returns (list of u, list of stats dicts)."""
     ps, keeps, outs = [], [], []
@@ -179,7 +186,7 @@ def eik_solve_batched(problems, *, dtype="f64", method="exact", cell=0, band=0.0
         outs.append(u)
     arr = (Problem * len(ps))(*ps)
     o = _opts(F64 if dtype == "f64" else F32, method, cell, band, device, _stream_of(device),
-              residual_check, workers, max_cell_visits)
+              residual_check, workers, max_cell_visits, band_window, eager_publish, schedule)
     st = (Stats * len(ps))()
     _check(lib.eik_solve_batched(len(ps), arr, ctypes.byref(o), st))
     del keeps
