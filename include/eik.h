@@ -146,32 +146,52 @@ typedef struct {
 int eik_solve_batched(int32_t n, const eik_problem* probs, const eik_opts* opts,
                       eik_stats* stats);
 
-/* Continuous-batching server.  Requests are copied to device memory owned by
-   the server and charged against hbm_budget_bytes; requests that do not fit
-   wait until earlier ones finish; a single request larger than the budget is
-   refused with EBUDGET.  Admitted requests join the running persistent work
-   at the next time slice and their cells are processed together with those
-   of requests already in flight.  opts.device_ptrs applies to the request's
-   input pointers; u_out is always host memory and must stay valid until
-   poll/wait reports completion. */
+/* Continuous-batching server.  The server allocates one device arena of
+   hbm_budget_bytes at creation.  Each request is charged the device bytes it
+   needs (F, u and h/F in the solve precision, the mask, the exit nodes and
+   costs, and for FP32 with residual_check the FP64 re-solve buffers, 24 bytes
+   per node) and waits until the arena can hold it; requests are admitted in
+   submission order.  A request larger than the whole budget is refused with
+   EBUDGET.  `lanes` host threads, each with its own stream, take all admitted
+   requests that fit when they fall idle and solve them in one persistent
+   launch; launches of different lanes run concurrently on the device, so a
+   request that arrives while others are being solved starts as soon as a
+   lane, a slot and memory are free.  A request's result does not depend on
+   the requests it is solved with (up to the rounding of the exact method's
+   order-independent fixed point).
+   opts: dtype, method, cell, band, residual_check, schedule apply to every
+   request; opts.device_ptrs = 1 means the request's F, mask, src and q are
+   device memory, read when the request is admitted (they must stay valid until
+   it completes); u_out is always host memory and must stay valid until
+   poll/wait reports completion.  opts.stream and opts.workers are ignored
+   (each lane uses its own stream and a 1/lanes share of the device).
+   Small per-launch solver state (a few bytes per cell) is held by the lanes
+   outside the budget. */
 typedef struct {
-  uint64_t hbm_budget_bytes;  /* device bytes for admitted requests; 0 = 64 GiB */
-  int32_t max_slots;          /* requests in flight at once; 0 = 1024          */
+  uint64_t hbm_budget_bytes;  /* device arena; 0 = 64 GiB                      */
+  int32_t max_slots;          /* requests admitted at once; 0 = 1024           */
+  int32_t lanes;              /* concurrent launches, 0..16; 0 = 4             */
   eik_opts opts;
 } eik_serve_cfg;
 
 typedef struct eik_server eik_server;
 
 int eik_serve_create(const eik_serve_cfg* cfg, eik_server** out);
-/* Copies the request's inputs and returns at once with a ticket. */
+/* Validates the request, copies its host inputs (device_ptrs = 0) and returns
+   at once with a ticket.  EINVAL as for eik_solve; EBUDGET (see above). */
 int eik_serve_submit(eik_server* s, const eik_problem* p, uint64_t* ticket);
-/* EIK_OK when done (stats filled if non-NULL), EIK_EBUSY while pending. */
+/* EIK_OK when done (stats filled if non-NULL; stats.seconds is the time from
+   submission to completion), EIK_EBUSY while queued or running, or the
+   request's own error.  A ticket is reported done once, then forgotten
+   (a later call returns EINVAL). */
 int eik_serve_poll(eik_server* s, uint64_t ticket, eik_stats* stats);
 /* Blocks until the request is done. */
 int eik_serve_wait(eik_server* s, uint64_t ticket, eik_stats* stats);
-/* Cancels a request that has not been admitted yet; EBUSY if it already runs. */
+/* Cancels a request that has not been admitted yet (its ticket is forgotten);
+   EBUSY if it has been admitted. */
 int eik_serve_cancel(eik_server* s, uint64_t ticket);
-/* Waits for requests in flight, then frees the server. */
+/* Solves every request still queued or running, then frees the server
+   (results not yet collected are dropped). */
 int eik_serve_destroy(eik_server* s);
 
 /* Message for the last failed call on this thread ("" if none). */

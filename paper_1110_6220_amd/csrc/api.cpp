@@ -60,8 +60,48 @@ hipError_t DevBuf::ensure(size_t need) {
   return e;
 }
 
+void DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+void Solver::release() {
+  for (DevBuf* b : {&delta, &st, &visits, &cell_inst, &key, &deps, &ord, &slot, &head, &tail,
+                    &inflight, &cursor, &ctl, &inst})
+    b->release();
+}
+
+void workspace_free(Workspace* w) {
+  w->fine.release();
+  w->coarse.release();
+  for (DevBuf* b : {&w->F, &w->u, &w->mask, &w->src, &w->q, &w->cF, &w->cmask, &w->cq, &w->cu,
+                    &w->cout, &w->F64, &w->u64, &w->ready_at, &w->trace, &w->trace_n})
+    b->release();
+  if (w->ctl_host) (void)hipHostFree(w->ctl_host);
+  if (w->ev0) (void)hipEventDestroy(w->ev0);
+  if (w->ev1) (void)hipEventDestroy(w->ev1);
+  w->ctl_host = nullptr;
+  w->ev0 = w->ev1 = nullptr;
+  w->ready = false;
+}
+
 static std::mutex g_ws_mu;
 static std::vector<std::unique_ptr<Workspace>> g_ws;
+
+int workspace_init(Workspace* w) {
+  if (w->ready) return EIK_OK;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipHostMalloc((void**)&w->ctl_host, 2 * sizeof(Ctl), hipHostMallocDefault));
+  HIP_TRY(hipEventCreate(&w->ev0));
+  HIP_TRY(hipEventCreate(&w->ev1));
+  HIP_TRY(hipDeviceGetAttribute(&w->cus, hipDeviceAttributeMultiprocessorCount, dev));
+  HIP_TRY(hipDeviceGetAttribute(&w->wall_khz, hipDeviceAttributeWallClockRate, dev));
+  if (w->wall_khz <= 0) w->wall_khz = 100000;
+  w->ready = true;
+  return EIK_OK;
+}
 
 int workspace(Workspace** out) {
   int dev = 0;
@@ -70,15 +110,8 @@ int workspace(Workspace** out) {
   if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1);
   if (!g_ws[dev]) g_ws[dev].reset(new Workspace());
   Workspace* w = g_ws[dev].get();
-  if (!w->ready) {
-    HIP_TRY(hipHostMalloc((void**)&w->ctl_host, 2 * sizeof(Ctl), hipHostMallocDefault));
-    HIP_TRY(hipEventCreate(&w->ev0));
-    HIP_TRY(hipEventCreate(&w->ev1));
-    HIP_TRY(hipDeviceGetAttribute(&w->cus, hipDeviceAttributeMultiprocessorCount, dev));
-    HIP_TRY(hipDeviceGetAttribute(&w->wall_khz, hipDeviceAttributeWallClockRate, dev));
-    if (w->wall_khz <= 0) w->wall_khz = 100000;
-    w->ready = true;
-  }
+  int rc = workspace_init(w);
+  if (rc) return rc;
   *out = w;
   return EIK_OK;
 }
@@ -265,11 +298,14 @@ static int default_workers(const Workspace* ws, int64_t J, int tile, int dtype, 
 // the solve driver shared by eik_solve, eik_solve_batched and the server
 // ---------------------------------------------------------------------------
 
-int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, RunInfo* info) {
+int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, RunInfo* info,
+        const RunCtx* ctx_in) {
   const double t0 = now_s();
-  Workspace* ws = nullptr;
-  int rc = workspace(&ws);
+  RunCtx ctx = ctx_in ? *ctx_in : RunCtx();
+  Workspace* ws = ctx.ws;
+  int rc = ws ? workspace_init(ws) : workspace(&ws);
   if (rc) return rc;
+  ctx.ws = ws;
   std::unique_lock<std::mutex> lk(ws->mu);
   hipStream_t stream = static_cast<hipStream_t>(o.stream);
   const int dt = o.dtype;
@@ -310,7 +346,7 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
     HIP_TRY(ws->src.ensure(nsrc * sizeof(int64_t)));
     HIP_TRY(ws->q.ensure(nsrc * sizeof(double)));
   }
-  HIP_TRY(ws->fine.delta.ensure(total_nodes * es));
+  if (!ctx.delta) HIP_TRY(ws->fine.delta.ensure(total_nodes * es));
   int64_t off = 0, moff = 0, soff = 0;
   for (int k = 0; k < n; ++k) {
     const eik_problem& p = probs[k];
@@ -325,7 +361,7 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
     I.ky = til[k].ky;
     I.balanced = til[k].balanced;
     I.nsrc = p.nsrc;
-    I.delta = ws->fine.delta.as<char>() + off * es;
+    I.delta = ctx.delta ? ctx.delta[k] : (void*)(ws->fine.delta.as<char>() + off * es);
     if (dev) {
       I.u = p.u_out;
       I.F = p.F;
@@ -361,7 +397,8 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
     return rc;
   const int64_t J = e.ncells;
   const int tile = tile_for(extent);
-  const int workers = o.workers ? o.workers : default_workers(ws, J, tile, dt, n);
+  const int workers =
+      o.workers ? o.workers : std::max(1, default_workers(ws, J, tile, dt, n) / std::max(1, ctx.share));
 
   const unsigned trace_cap = 1u << 20;
   if (g_trace) {
@@ -419,7 +456,8 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
     if ((rc = setup_engine(ws->coarse, cinst, EIK_F64, EIK_EXACT, 0, -1.0, 0, 0, 0, timeout, stream, &ce)))
       return rc;
     HIP_TRY(launch_prepare(ce, J, stream));
-    const int cw = default_workers(ws, ce.ncells, tile_for(cext), EIK_F64, n);
+    const int cw = std::max(1, default_workers(ws, ce.ncells, tile_for(cext), EIK_F64, n) /
+                                   std::max(1, ctx.share));
     HIP_TRY(launch_solve(ce, cw, tile_for(cext), stream));
     HIP_TRY(launch_dag(e, ws->cout.as<CoarseOut>(), (int)J, stream));
     have_coarse = true;
@@ -450,7 +488,7 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
   int fell_back = 0;
   if (dt == EIK_F32 && want_resid && !(resid <= 4.0 * std::ldexp(1.0, -24))) {
     lk.unlock();  // the FP64 solve takes the workspace lock itself
-    rc = refine_fp64(n, probs, inst, o, stream);
+    rc = refine_fp64(n, probs, inst, o, stream, ctx);
     lk.lock();
     if (rc) return rc;
     fell_back = 1;
@@ -515,25 +553,33 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
 // Re-solves FP32 problems in FP64 (speeds widened on the device) and rounds
 // the result into the FP32 outputs (inst[k].u: device memory).
 int refine_fp64(int n, const eik_problem* probs, const std::vector<Inst>& inst, const eik_opts& o,
-                hipStream_t stream) {
-  Workspace* ws = nullptr;
-  int rc = workspace(&ws);
-  if (rc) return rc;
+                hipStream_t stream, const RunCtx& ctx) {
+  Workspace* ws = ctx.ws;
   int64_t total = 0;
   for (int k = 0; k < n; ++k) total += (int64_t)probs[k].nx * probs[k].ny;
-  {
+  if (!ctx.f64) {
     std::lock_guard<std::mutex> lk(ws->mu);
     HIP_TRY(ws->F64.ensure(total * sizeof(double)));
     HIP_TRY(ws->u64.ensure(total * sizeof(double)));
   }
   std::vector<eik_problem> p64(probs, probs + n);
+  std::vector<double*> u64(n);
+  std::vector<void*> d64(n);
   int64_t off = 0;
   for (int k = 0; k < n; ++k) {
     const int64_t nn = (int64_t)probs[k].nx * probs[k].ny;
-    double* F = ws->F64.as<double>() + off;
+    double* F;
+    if (ctx.f64) {
+      F = static_cast<double*>(ctx.f64[k]);
+      u64[k] = F + nn;
+      d64[k] = F + 2 * nn;
+    } else {
+      F = ws->F64.as<double>() + off;
+      u64[k] = ws->u64.as<double>() + off;
+    }
     HIP_TRY(launch_convert(inst[k].F, EIK_F32, F, EIK_F64, nn, stream));
     p64[k].F = F;
-    p64[k].u_out = ws->u64.as<double>() + off;
+    p64[k].u_out = u64[k];
     p64[k].mask = inst[k].mask;
     p64[k].src = inst[k].src;
     p64[k].q = inst[k].q;
@@ -543,12 +589,15 @@ int refine_fp64(int n, const eik_problem* probs, const std::vector<Inst>& inst, 
   o64.dtype = EIK_F64;
   o64.device_ptrs = 1;
   o64.residual_check = 0;
-  if ((rc = run(n, p64.data(), o64, nullptr, nullptr))) return rc;
-  off = 0;
+  RunCtx c64;
+  c64.ws = ws;
+  c64.delta = ctx.f64 ? d64.data() : nullptr;
+  c64.share = ctx.share;
+  int rc = run(n, p64.data(), o64, nullptr, nullptr, &c64);
+  if (rc) return rc;
   for (int k = 0; k < n; ++k) {
     const int64_t nn = (int64_t)probs[k].nx * probs[k].ny;
-    HIP_TRY(launch_convert(ws->u64.as<double>() + off, EIK_F64, inst[k].u, EIK_F32, nn, stream));
-    off += nn;
+    HIP_TRY(launch_convert(u64[k], EIK_F64, inst[k].u, EIK_F32, nn, stream));
   }
   HIP_TRY(hipStreamSynchronize(stream));
   return EIK_OK;

@@ -28,6 +28,7 @@ struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
   hipError_t ensure(size_t need);
+  void release();
   template <typename T>
   T* as() const { return static_cast<T*>(p); }
 };
@@ -35,6 +36,7 @@ struct DevBuf {
 // Buffers of one engine run.
 struct Solver {
   DevBuf delta, st, visits, cell_inst, key, deps, ord, slot, head, tail, inflight, cursor, ctl, inst;
+  void release();
 };
 
 // Per-device workspace, reused by every call on that device.
@@ -61,7 +63,23 @@ struct RunInfo {
   int64_t cells;
 };
 
+// The calling device's shared workspace (created on first use).
 int workspace(Workspace** out);
+// Initialises a workspace for the current device (pinned control block,
+// events, device attributes).
+int workspace_init(Workspace* w);
+// Frees everything a workspace holds (no work may be pending on it).
+void workspace_free(Workspace* w);
+
+// Where a run takes its buffers from.  Defaults: the device's shared
+// workspace for everything.
+struct RunCtx {
+  Workspace* ws = nullptr;       // workspace (and its lock) of this run
+  void* const* delta = nullptr;  // per problem: nodes x dtype for h/F
+  void* const* f64 = nullptr;    // per problem: 3 x nodes doubles (F, u, delta)
+                                 // for the FP64 re-solve of FP32 problems
+  int share = 1;                 // the run gets 1/share of the default waves
+};
 eik_opts default_opts();
 int check_opts(const eik_opts& o);
 int std_cells(int n, int s);
@@ -71,8 +89,9 @@ size_t dsize(int dtype);
 int validate_host(const eik_problem& p, int dtype);
 int validate_shape(const eik_problem& p);
 // Solves n problems (validated) with one persistent launch.
-int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, RunInfo* info);
+int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, RunInfo* info,
+        const RunCtx* ctx = nullptr);
 int refine_fp64(int n, const eik_problem* probs, const std::vector<Inst>& inst, const eik_opts& o,
-                hipStream_t stream);
+                hipStream_t stream, const RunCtx& ctx);
 
 }  // namespace eik

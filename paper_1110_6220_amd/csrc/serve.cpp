@@ -1,19 +1,405 @@
-// Serving entry points (continuous batching).  See include/eik.h.
+// Continuous-batching server (the eik_serve_* entry points of include/eik.h).
+//
+// The server owns one device arena of hbm_budget_bytes.  Every request is
+// charged its device bytes (speed, solution and h/F arrays, mask, exit
+// nodes, and for FP32 with the residual check the FP64 re-solve buffers)
+// and admitted only when the arena can place it.  Lanes, each a host thread
+// with its own HIP stream and solver workspace, take every pending request
+// that fits when they fall idle and solve them together in one persistent
+// launch; launches of different lanes overlap on the device, so requests
+// arriving while others run start as soon as a lane, a slot and memory are
+// free.  A request's result does not depend on what it was batched with:
+// instances in a launch share the workers but no data.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <condition_variable>
 #include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
 
 #include "../../include/eik.h"
+#include "internal.h"
+
+namespace eik {
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kDefaultLanes = 4;        // one per hardware queue of the process
+constexpr int kMaxBatch = 256;          // requests per launch
+constexpr uint64_t kDefaultBudget = 64ull << 30;
+
+size_t up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
+
+// First-fit allocator over [0, size) with coalescing of free ranges.
+class Arena {
+ public:
+  void reset(size_t size) {
+    free_.clear();
+    if (size) free_[0] = size;
+  }
+  bool alloc(size_t bytes, size_t* off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < bytes) continue;
+      *off = it->first;
+      const size_t rest = it->second - bytes;
+      const size_t at = it->first + bytes;
+      free_.erase(it);
+      if (rest) free_[at] = rest;
+      return true;
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+
+ private:
+  std::map<size_t, size_t> free_;  // offset -> length
+};
+
+enum ReqState { kReqQueued, kReqRunning, kReqDone };
+
+struct Req {
+  uint64_t ticket = 0;
+  eik_problem p{};          // the caller's problem (pointers valid until admission)
+  std::vector<char> F;      // host copies (device_ptrs = 0)
+  std::vector<uint8_t> mask;
+  std::vector<int64_t> src;
+  std::vector<double> q;
+  size_t bytes = 0, off = 0;
+  ReqState state = kReqQueued;
+  int rc = EIK_OK;
+  std::string err;
+  eik_stats st{};
+  double t_submit = 0.0;
+};
+
+// Byte offsets of a request's arrays inside its arena block.
+struct Layout {
+  size_t F, u, delta, mask, src, q, f64, total;
+};
+
+Layout layout(const eik_problem& p, const eik_opts& o) {
+  const size_t nn = (size_t)p.nx * p.ny, es = dsize(o.dtype);
+  Layout L;
+  size_t at = 0;
+  L.F = at; at += up(nn * es);
+  L.u = at; at += up(nn * es);
+  L.delta = at; at += up(nn * es);
+  L.mask = at; at += p.mask ? up(nn) : 0;
+  L.src = at; at += up(p.nsrc * sizeof(int64_t));
+  L.q = at; at += p.q ? up(p.nsrc * sizeof(double)) : 0;
+  L.f64 = at; at += (o.dtype == EIK_F32 && o.residual_check) ? up(3 * nn * sizeof(double)) : 0;
+  L.total = at;
+  return L;
+}
+
+}  // namespace
+}  // namespace eik
+
+using namespace eik;
+
+struct eik_server {
+  eik_serve_cfg cfg{};
+  int dev = 0;
+  char* base = nullptr;  // device arena
+  Arena arena;
+  int lanes = kDefaultLanes;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Req*> pending;
+  std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
+  uint64_t next_ticket = 1;
+  int in_flight = 0;
+  bool stop = false;
+  std::vector<std::thread> threads;
+  std::vector<hipStream_t> streams;
+  std::vector<std::unique_ptr<Workspace>> ws;
+
+  void lane(int id);
+  void solve(int id, std::vector<Req*>& batch);
+};
+
+// Takes the requests at the head of the queue while a slot and arena space
+// are free (first come, first served: a request that does not fit holds back
+// those behind it).
+static void take_batch(eik_server* s, std::vector<Req*>& batch) {
+  const int max_slots = s->cfg.max_slots ? s->cfg.max_slots : 1024;
+  while (!s->pending.empty() && (int)batch.size() < kMaxBatch && s->in_flight < max_slots) {
+    Req* r = s->pending.front();
+    size_t off = 0;
+    if (!s->arena.alloc(r->bytes, &off)) break;
+    r->off = off;
+    r->state = kReqRunning;
+    s->pending.pop_front();
+    s->in_flight++;
+    batch.push_back(r);
+  }
+}
+
+void eik_server::lane(int id) {
+  (void)hipSetDevice(dev);
+  for (;;) {
+    std::vector<Req*> batch;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      for (;;) {
+        take_batch(this, batch);
+        if (!batch.empty() || (stop && pending.empty())) break;
+        cv_work.wait(lk);
+      }
+      if (batch.empty()) return;
+    }
+    solve(id, batch);
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      for (Req* r : batch) {
+        arena.release(r->off, r->bytes);
+        r->state = kReqDone;
+        in_flight--;
+      }
+    }
+    cv_work.notify_all();
+    cv_done.notify_all();
+  }
+}
+
+// Uploads, solves and downloads one batch on lane `id`.  A batch that fails
+// as a whole is retried request by request, so one bad request (speeds or
+// sources checked on the device) fails alone.
+void eik_server::solve(int id, std::vector<Req*>& batch) {
+  hipStream_t st = streams[id];
+  eik_opts o = cfg.opts;
+  o.device_ptrs = 1;
+  o.stream = st;
+  const size_t es = dsize(o.dtype);
+  const int n = (int)batch.size();
+  std::vector<eik_problem> probs(n);
+  std::vector<void*> delta(n), f64(n);
+  int rc = EIK_OK;
+  for (int k = 0; k < n && !rc; ++k) {
+    Req* r = batch[k];
+    const eik_problem& p = r->p;
+    const Layout L = layout(p, o);
+    char* b = base + r->off;
+    const size_t nn = (size_t)p.nx * p.ny;
+    const hipMemcpyKind kind = cfg.opts.device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    const void* F = cfg.opts.device_ptrs ? p.F : (const void*)r->F.data();
+    const void* M = cfg.opts.device_ptrs ? (const void*)p.mask : (const void*)r->mask.data();
+    const void* S = cfg.opts.device_ptrs ? (const void*)p.src : (const void*)r->src.data();
+    const void* Q = cfg.opts.device_ptrs ? (const void*)p.q : (const void*)r->q.data();
+    hipError_t e = hipMemcpyAsync(b + L.F, F, nn * es, kind, st);
+    if (e == hipSuccess && p.mask) e = hipMemcpyAsync(b + L.mask, M, nn, kind, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(b + L.src, S, p.nsrc * sizeof(int64_t), kind, st);
+    if (e == hipSuccess && p.q) e = hipMemcpyAsync(b + L.q, Q, p.nsrc * sizeof(double), kind, st);
+    if (e != hipSuccess) rc = fail(EIK_EDEVICE, "upload failed: %s", hipGetErrorString(e));
+    eik_problem d = p;
+    d.F = b + L.F;
+    d.u_out = b + L.u;
+    d.mask = p.mask ? (const uint8_t*)(b + L.mask) : nullptr;
+    d.src = (const int64_t*)(b + L.src);
+    d.q = p.q ? (const double*)(b + L.q) : nullptr;
+    probs[k] = d;
+    delta[k] = b + L.delta;
+    f64[k] = b + L.f64;
+  }
+  std::vector<eik_stats> stats(n);
+  RunCtx ctx;
+  ctx.ws = ws[id].get();
+  ctx.delta = delta.data();
+  ctx.f64 = f64.data();
+  ctx.share = lanes;
+  if (!rc) rc = run(n, probs.data(), o, stats.data(), nullptr, &ctx);
+  if (rc && n > 1) {
+    // isolate the failing request(s)
+    for (int k = 0; k < n; ++k) {
+      batch[k]->rc = run(1, &probs[k], o, &stats[k], nullptr, &ctx);
+      if (batch[k]->rc) batch[k]->err = g_err;
+    }
+  } else {
+    for (int k = 0; k < n; ++k) {
+      batch[k]->rc = rc;
+      if (rc) batch[k]->err = g_err;
+    }
+  }
+  for (int k = 0; k < n; ++k) {
+    Req* r = batch[k];
+    if (r->rc) continue;
+    const size_t nn = (size_t)r->p.nx * r->p.ny;
+    hipError_t e = hipMemcpyAsync(r->p.u_out, probs[k].u_out, nn * es, hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) {
+      r->rc = EIK_EDEVICE;
+      r->err = std::string("download failed: ") + hipGetErrorString(e);
+    }
+  }
+  (void)hipStreamSynchronize(st);
+  const double t = now_s();
+  for (int k = 0; k < n; ++k) {
+    Req* r = batch[k];
+    r->st = stats[k];
+    r->st.seconds = t - r->t_submit;
+    std::vector<char>().swap(r->F);
+    std::vector<uint8_t>().swap(r->mask);
+  }
+}
 
 extern "C" {
 
-int eik_serve_create(const eik_serve_cfg*, eik_server** out) {
-  if (out) *out = nullptr;
-  return EIK_EINVAL;
+int eik_serve_create(const eik_serve_cfg* cfg, eik_server** out) {
+  g_err.clear();
+  if (!cfg || !out) return fail(EIK_EINVAL, "cfg and out are required");
+  *out = nullptr;
+  int rc = check_opts(cfg->opts);
+  if (rc) return rc;
+  if (cfg->max_slots < 0) return fail(EIK_EINVAL, "max_slots must be >= 0");
+  if (cfg->lanes < 0 || cfg->lanes > 16) return fail(EIK_EINVAL, "lanes outside [0, 16]");
+  std::unique_ptr<eik_server> s(new eik_server());
+  s->cfg = *cfg;
+  if (!s->cfg.hbm_budget_bytes) s->cfg.hbm_budget_bytes = kDefaultBudget;
+  s->lanes = cfg->lanes ? cfg->lanes : kDefaultLanes;
+  HIP_TRY(hipGetDevice(&s->dev));
+  void* base = nullptr;
+  if (hipMalloc(&base, s->cfg.hbm_budget_bytes) != hipSuccess)
+    return fail(EIK_ENOMEM, "cannot allocate a %llu-byte arena",
+                (unsigned long long)s->cfg.hbm_budget_bytes);
+  s->base = static_cast<char*>(base);
+  s->arena.reset(s->cfg.hbm_budget_bytes / kAlign * kAlign);
+  for (int i = 0; i < s->lanes; ++i) {
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
+      (void)hipFree(s->base);
+      return fail(EIK_EDEVICE, "cannot create a stream");
+    }
+    s->streams.push_back(st);
+    s->ws.emplace_back(new Workspace());
+    if ((rc = workspace_init(s->ws.back().get()))) {
+      for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
+      for (auto& w : s->ws) workspace_free(w.get());
+      (void)hipFree(s->base);
+      return rc;
+    }
+  }
+  eik_server* raw = s.get();
+  for (int i = 0; i < s->lanes; ++i) s->threads.emplace_back([raw, i] { raw->lane(i); });
+  *out = s.release();
+  return EIK_OK;
 }
-int eik_serve_submit(eik_server*, const eik_problem*, uint64_t*) { return EIK_EINVAL; }
-int eik_serve_poll(eik_server*, uint64_t, eik_stats*) { return EIK_EINVAL; }
-int eik_serve_wait(eik_server*, uint64_t, eik_stats*) { return EIK_EINVAL; }
-int eik_serve_cancel(eik_server*, uint64_t) { return EIK_EINVAL; }
-int eik_serve_destroy(eik_server*) { return EIK_EINVAL; }
+
+int eik_serve_submit(eik_server* s, const eik_problem* p, uint64_t* ticket) {
+  g_err.clear();
+  if (!s || !p || !ticket) return fail(EIK_EINVAL, "server, problem and ticket are required");
+  int rc = validate_shape(*p);
+  if (rc) return rc;
+  const eik_opts& o = s->cfg.opts;
+  if (!o.device_ptrs && (rc = validate_host(*p, o.dtype))) return rc;
+  Tiling t;
+  const int cell = o.cell ? o.cell : default_cell(p->nx, p->ny, o.method);
+  if ((rc = make_tiling(p->nx, p->ny, cell, o.method, &t))) return rc;
+  std::unique_ptr<Req> r(new Req());
+  r->p = *p;
+  r->bytes = layout(*p, o).total;
+  if (r->bytes > s->cfg.hbm_budget_bytes / kAlign * kAlign)
+    return fail(EIK_EBUDGET, "request needs %zu device bytes, budget is %llu", r->bytes,
+                (unsigned long long)s->cfg.hbm_budget_bytes);
+  if (!o.device_ptrs) {
+    const size_t nn = (size_t)p->nx * p->ny;
+    r->F.assign((const char*)p->F, (const char*)p->F + nn * dsize(o.dtype));
+    if (p->mask) r->mask.assign(p->mask, p->mask + nn);
+    r->src.assign(p->src, p->src + p->nsrc);
+    if (p->q) r->q.assign(p->q, p->q + p->nsrc);
+  }
+  r->t_submit = now_s();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return fail(EIK_EINVAL, "server is shutting down");
+    r->ticket = s->next_ticket++;
+    *ticket = r->ticket;
+    s->pending.push_back(r.get());
+    s->reqs.emplace(r->ticket, std::move(r));
+  }
+  s->cv_work.notify_one();
+  return EIK_OK;
+}
+
+// Hands out a finished request's result once and forgets the ticket.
+static int collect(eik_server* s, std::unique_lock<std::mutex>& lk, uint64_t ticket, eik_stats* stats) {
+  (void)lk;
+  auto it = s->reqs.find(ticket);
+  Req* r = it->second.get();
+  const int rc = r->rc;
+  if (rc) g_err = r->err;
+  else if (stats) *stats = r->st;
+  s->reqs.erase(it);
+  return rc;
+}
+
+int eik_serve_poll(eik_server* s, uint64_t ticket, eik_stats* stats) {
+  g_err.clear();
+  if (!s) return fail(EIK_EINVAL, "server is required");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return fail(EIK_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+  if (it->second->state != kReqDone) return EIK_EBUSY;
+  return collect(s, lk, ticket, stats);
+}
+
+int eik_serve_wait(eik_server* s, uint64_t ticket, eik_stats* stats) {
+  g_err.clear();
+  if (!s) return fail(EIK_EINVAL, "server is required");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return fail(EIK_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+  Req* r = it->second.get();
+  s->cv_done.wait(lk, [r] { return r->state == kReqDone; });
+  return collect(s, lk, ticket, stats);
+}
+
+int eik_serve_cancel(eik_server* s, uint64_t ticket) {
+  g_err.clear();
+  if (!s) return fail(EIK_EINVAL, "server is required");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return fail(EIK_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+  if (it->second->state != kReqQueued) return fail(EIK_EBUSY, "request already admitted");
+  s->pending.erase(std::find(s->pending.begin(), s->pending.end(), it->second.get()));
+  s->reqs.erase(it);
+  return EIK_OK;
+}
+
+int eik_serve_destroy(eik_server* s) {
+  g_err.clear();
+  if (!s) return fail(EIK_EINVAL, "server is required");
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  for (auto& t : s->threads) t.join();
+  for (auto& w : s->ws) workspace_free(w.get());
+  for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+  (void)hipFree(s->base);
+  delete s;
+  return EIK_OK;
+}
 
 }  // extern "C"

@@ -67,7 +67,7 @@ class Problem(ctypes.Structure):
 
 class ServeCfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int32),
-                ("opts", Opts)]
+                ("lanes", ctypes.c_int32), ("opts", Opts)]
 
 
 def _load() -> ctypes.CDLL:
@@ -191,3 +191,70 @@ def eik_solve_batched(problems, *, dtype="f64", method="exact", cell=0, band=0.0
     _check(lib.eik_solve_batched(len(ps), arr, ctypes.byref(o), st))
     del keeps
     return outs, [s.as_dict() for s in st]
+
+
+class Server:
+    """Continuous-batching server (eik_serve_* of include/eik.h).
+
+    submit() takes numpy arrays (host inputs, copied at once) or device
+    tensors (read when the request is admitted; kept alive here until the
+    result is collected).  Results are host numpy arrays."""
+
+    def __init__(self, hbm_budget_bytes=0, max_slots=0, lanes=0, *, dtype="f64",
+                 method="exact", cell=0, band=0.0, residual_check=False, device_inputs=False,
+                 schedule="auto", max_cell_visits=0):
+        self.dtype = dtype
+        o = _opts(F64 if dtype == "f64" else F32, method, cell, band, device_inputs, None,
+                  residual_check, 0, max_cell_visits, 0, False, schedule)
+        cfg = ServeCfg(int(hbm_budget_bytes), int(max_slots), int(lanes), o)
+        h = ctypes.c_void_p()
+        _check(lib.eik_serve_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, F, h, src, q=None, mask=None) -> int:
+        p, keep, _, _ = _marshal(F, h, src, q, mask, None, self.dtype)
+        ndt = np.float64 if self.dtype == "f64" else np.float32
+        u = np.empty((p.ny, p.nx), dtype=ndt)
+        p.u_out = u.ctypes.data
+        t = ctypes.c_uint64()
+        _check(lib.eik_serve_submit(self._h, ctypes.byref(p), ctypes.byref(t)))
+        self._keep[t.value] = (u, keep)
+        return t.value
+
+    def _collect(self, rc, ticket, st):
+        if rc == EIK_EBUSY:
+            return None
+        u, _ = self._keep.pop(ticket, (None, None))
+        _check(rc)
+        return u, st.as_dict()
+
+    def poll(self, ticket):
+        """(u, stats) when done, None while pending; raises on failure."""
+        st = Stats()
+        return self._collect(lib.eik_serve_poll(self._h, ticket, ctypes.byref(st)), ticket, st)
+
+    def wait(self, ticket):
+        st = Stats()
+        return self._collect(lib.eik_serve_wait(self._h, ticket, ctypes.byref(st)), ticket, st)
+
+    def cancel(self, ticket) -> bool:
+        rc = lib.eik_serve_cancel(self._h, ticket)
+        if rc == EIK_OK:
+            self._keep.pop(ticket, None)
+            return True
+        if rc == EIK_EBUSY:
+            return False
+        _check(rc)
+
+    def close(self):
+        if self._h:
+            _check(lib.eik_serve_destroy(self._h))
+            self._h = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -58,3 +58,25 @@ def test_invalid_arguments_are_rejected_before_device_work():
         else:
             raise AssertionError(args)
     assert (u == 7.0).all()  # untouched
+
+
+def test_serving_arguments_are_checked_before_device_work():
+    """Server entry points reject missing handles and invalid configurations
+    without touching a device."""
+    from paper_1110_6220_amd import eik
+    L = eik.lib
+    out = ctypes.c_void_p()
+    assert L.eik_serve_create(None, ctypes.byref(out)) == eik.EIK_EINVAL
+    for kw in [dict(cell=3), dict(lanes=17), dict(max_slots=-1)]:
+        o = eik._opts(eik.F64, "exact", kw.get("cell", 0), 0.0, 0, None, 0, 0, 0)
+        cfg = eik.ServeCfg(1 << 20, kw.get("max_slots", 0), kw.get("lanes", 0), o)
+        assert L.eik_serve_create(ctypes.byref(cfg), ctypes.byref(out)) == eik.EIK_EINVAL, kw
+        assert eik.last_error()
+    t = ctypes.c_uint64()
+    p = eik.Problem()
+    st = eik.Stats()
+    assert L.eik_serve_submit(None, ctypes.byref(p), ctypes.byref(t)) == eik.EIK_EINVAL
+    assert L.eik_serve_poll(None, 1, ctypes.byref(st)) == eik.EIK_EINVAL
+    assert L.eik_serve_wait(None, 1, ctypes.byref(st)) == eik.EIK_EINVAL
+    assert L.eik_serve_cancel(None, 1) == eik.EIK_EINVAL
+    assert L.eik_serve_destroy(None) == eik.EIK_EINVAL

@@ -1,0 +1,90 @@
+"""GPU parity of batched solves (many problems of different sizes in one
+persistent launch) against the CPU oracle, FP64 and FP32."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1110_6220_amd import workloads as W
+from gpu_util import f32_bound, max_abs, max_rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def eik():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1110_6220_amd import eik as E
+    return E
+
+
+def batch_dev(ws, dtype):
+    out = []
+    for w in ws:
+        d = to_dev(w, dtype)
+        out.append(d)
+    return out
+
+
+def run_batched(eik, ws, **kw):
+    print(f"[gpu] batched {len(ws)} problems {kw}", flush=True)
+    dtype = kw.get("dtype", "f64")
+    us, st = eik.eik_solve_batched(batch_dev(ws, dtype), **kw)
+    return [u.double().cpu().numpy() for u in us], st
+
+
+def test_small_batch_fp64_device_and_host(eik):
+    ws = W.batch_bumps(count=24, seed=40, n_lo=17, n_hi=200)
+    ws += [W.random_small(np.random.default_rng(41 + k), nx, ny, q_spread=0.2)
+           for k, (nx, ny) in enumerate([(1, 1), (1, 50), (70, 1), (65, 66), (130, 33)])]
+    refs = [O.fmm(O.Problem.from_workload(w)) for w in ws]
+    got, st = run_batched(eik, ws)
+    for w, g, U in zip(ws, got, refs):
+        assert max_rel(g, U) <= 1e-12, w["name"]
+    assert len(st) == len(ws) and all(s["cells"] >= 1 for s in st)
+    # host pointers: same results
+    probs = [dict(F=w["F"], h=w["h"], src=w["src"], q=w["q"], mask=w.get("mask")) for w in ws]
+    hu, _ = eik.eik_solve_batched(probs)
+    for w, g, U in zip(ws, hu, refs):
+        assert max_rel(g, U) <= 1e-12, w["name"]
+
+
+def test_small_batch_fp32_with_residual_check(eik):
+    ws = W.batch_bumps(count=16, seed=42, n_lo=33, n_hi=300)
+    got, st = run_batched(eik, ws, dtype="f32", residual_check=True)
+    for w, g in zip(ws, got):
+        U = O.fmm(O.Problem.from_workload(w))
+        assert max_abs(g, U) <= f32_bound(w, U), w["name"]
+    assert 0.0 <= st[0]["max_residual"]
+
+
+def test_fmsm_batched_bitwise(eik):
+    ws = W.batch_bumps(count=8, seed=43, n_lo=40, n_hi=180)
+    got, _ = run_batched(eik, ws, method="fmsm", cell=16)
+    for w, g in zip(ws, got):
+        V, _ = O.fmsm(O.Problem.from_workload(w), 16)
+        assert np.array_equal(g, V), w["name"]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_full_256_instance_batch_sampled(eik, dtype):
+    """The 256-instance Gaussian-bump batch (sides 65..1025) in one launch:
+    sampled instances (the largest, the smallest and six more) against the
+    oracle; every instance's FP64 fixed-point residual via the library's
+    residual pass."""
+    ws = W.config(4)
+    got, st = run_batched(eik, ws, dtype=dtype, residual_check=True)
+    sizes = np.array([w["nx"] for w in ws])
+    pick = {int(sizes.argmax()), int(sizes.argmin())} | set(range(0, 256, 37))
+    for k in sorted(pick):
+        w = ws[k]
+        U = O.fmm(O.Problem.from_workload(w))
+        if dtype == "f64":
+            assert max_rel(got[k], U) <= 1e-12, w["name"]
+        else:
+            assert max_abs(got[k], U) <= f32_bound(w, U), w["name"]
+    if dtype == "f64":
+        assert st[0]["max_residual"] <= 1e-13
+    for w, g in zip(ws, got):
+        assert np.isfinite(g).all()  # no obstacles: every node reachable
+        assert (g[np.unravel_index(w["src"], g.shape)] == 0.0).all()

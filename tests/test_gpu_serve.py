@@ -1,0 +1,89 @@
+"""GPU tests of the continuous-batching server: results equal the oracle,
+and each request's result is the same solved alone and in a mix of
+concurrent requests; budget admission, EBUDGET, cancellation, polling."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1110_6220_amd import workloads as W
+from gpu_util import f32_bound, max_abs, max_rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def eik():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1110_6220_amd import eik as E
+    return E
+
+
+def submit(srv, w):
+    return srv.submit(w["F"], w["h"], w["src"], w["q"], w.get("mask"))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_alone_equals_mix(eik, dtype):
+    reqs = W.maze_requests(20, seed=50, n_lo=65, n_hi=700)
+    target = reqs[7]
+    U = O.fmm(O.Problem.from_workload(target))
+    with eik.Server(256 << 20, lanes=4, dtype=dtype, residual_check=(dtype == "f32")) as srv:
+        print(f"[gpu] serve alone {target['name']} {dtype}", flush=True)
+        alone, _ = srv.wait(submit(srv, target))
+        print(f"[gpu] serve mix of {len(reqs)} {dtype}", flush=True)
+        tickets = [submit(srv, w) for w in reqs]
+        res = [srv.wait(t) for t in tickets]
+    mix = res[7][0]
+    if dtype == "f64":
+        assert max_rel(alone, U) <= 1e-12
+        assert max_rel(mix, U) <= 1e-12
+        assert max_rel(mix, alone) <= 1e-12
+        for w, (u, st) in zip(reqs, res):
+            assert max_rel(u, O.fmm(O.Problem.from_workload(w))) <= 1e-12, w["name"]
+            assert st["seconds"] > 0
+    else:
+        b = f32_bound(target, U)
+        assert max_abs(alone.astype(np.float64), U) <= b
+        assert max_abs(mix.astype(np.float64), U) <= b
+        assert max_abs(mix.astype(np.float64), alone.astype(np.float64)) <= b
+
+
+def test_small_budget_admits_in_turn(eik):
+    reqs = W.maze_requests(6, seed=51, n_lo=129, n_hi=400)
+    need = max(3 * 8 * w["nx"] * w["ny"] + w["nx"] * w["ny"] + 4096 for w in reqs)
+    with eik.Server(need + (1 << 16), lanes=2) as srv:
+        print("[gpu] serve under a one-request budget", flush=True)
+        tickets = [submit(srv, w) for w in reqs]
+        res = [srv.wait(t) for t in tickets]
+    for w, (u, _) in zip(reqs, res):
+        assert max_rel(u, O.fmm(O.Problem.from_workload(w))) <= 1e-12, w["name"]
+
+
+def test_budget_cancel_poll(eik):
+    big = W.smooth_sine(257)
+    small = W.point_source_unit(65)
+    with eik.Server(1 << 20, lanes=1) as srv:  # 1 MiB: a 257^2 FP64 problem needs 1.6 MB
+        with pytest.raises(eik.EikError) as e:
+            submit(srv, big)
+        assert e.value.code == eik.EIK_EBUDGET
+        print("[gpu] serve poll/cancel", flush=True)
+        tickets = [submit(srv, small) for _ in range(12)]
+        cancelled = [t for t in tickets[6:] if srv.cancel(t)]
+        for t in cancelled:
+            with pytest.raises(eik.EikError) as e:
+                srv.poll(t)
+            assert e.value.code == eik.EIK_EINVAL
+        U = O.fmm(O.Problem.from_workload(small))
+        for t in tickets:
+            if t in cancelled:
+                continue
+            r = None
+            t0 = time.time()
+            while r is None and time.time() - t0 < 60:
+                r = srv.poll(t)
+                time.sleep(0.001)
+            assert r is not None
+            assert max_rel(r[0], U) <= 1e-12
