@@ -152,19 +152,24 @@ int std_cells(int n, int s) {
   return K;
 }
 
+static int tile_for(int extent) { return extent <= 16 ? 16 : extent <= 32 ? 32 : 64; }
+
 // Standard tiling: K = ceil(n/s) cells of s nodes, a last cell of one node
-// merged into its predecessor.  If that leaves a cell wider than 64 nodes the
-// exact method uses the balanced tiling (K = ceil(n/s) cells of floor/ceil
-// n/K nodes); its result does not depend on the tiling.
+// merged into its predecessor.  The exact method, whose result does not
+// depend on the tiling, uses the balanced tiling instead (K = ceil(n/s) cells
+// of floor/ceil n/K nodes) whenever the merged last cell would need a larger
+// tile than s (e.g. n = 1025, s = 32: 33 cells of 31 or 32 nodes instead of a
+// 33-node last cell).  The approximate methods keep the standard tiling and
+// accept cells of at most 64 nodes.
 int make_tiling(int nx, int ny, int s, int method, Tiling* t) {
   t->s = s;
   t->kx = std_cells(nx, s);
   t->ky = std_cells(ny, s);
   int ex = std::max({std::min(s, nx), nx - (t->kx - 1) * s, std::min(s, ny), ny - (t->ky - 1) * s});
   t->balanced = 0;
-  if (ex > 64) {
-    if (method != EIK_EXACT)
-      return fail(EIK_EINVAL, "cell side %d leaves a cell of %d nodes (> 64) for this method", s, ex);
+  if (ex > 64 && method != EIK_EXACT)
+    return fail(EIK_EINVAL, "cell side %d leaves a cell of %d nodes (> 64) for this method", s, ex);
+  if (method == EIK_EXACT && (ex > 64 || tile_for(ex) > tile_for(std::min(s, 64)))) {
     t->kx = (nx + s - 1) / s;
     t->ky = (ny + s - 1) / s;
     t->balanced = 1;
@@ -173,8 +178,6 @@ int make_tiling(int nx, int ny, int s, int method, Tiling* t) {
   t->extent = ex;
   return EIK_OK;
 }
-
-static int tile_for(int extent) { return extent <= 16 ? 16 : extent <= 32 ? 32 : 64; }
 
 int default_cell(int nx, int ny, int method) {
   const int n = std::max(nx, ny);
@@ -287,8 +290,20 @@ static int setup_engine(Solver& sv, std::vector<Inst>& inst, int dtype, int meth
   return EIK_OK;
 }
 
-static int default_workers(const Workspace* ws, int64_t J, int tile, int dtype, int n) {
-  const int per_cu = tile == 64 ? (dtype == EIK_F64 ? 2 : 4) : tile == 32 ? 8 : 16;
+// Persistent waves: as many as fit on the device at once (at most one per
+// cell); a single problem is capped at 128 waves, beyond which more waves
+// only contend for the few ready cells of one front.
+static int default_workers(const Workspace* ws, int64_t J, int tile, int dtype, int method, int n) {
+  static std::mutex mu;
+  static int cache[2][3][3] = {};
+  const int ti = tile <= 16 ? 0 : tile <= 32 ? 1 : 2;
+  int per_cu;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    int& c = cache[dtype][method][ti];
+    if (!c) c = solve_waves_per_cu(dtype, method, tile);
+    per_cu = c;
+  }
   int64_t w = std::min<int64_t>(J, (int64_t)ws->cus * per_cu);
   if (n == 1) w = std::min<int64_t>(w, 128);
   return (int)std::max<int64_t>(w, 1);
@@ -397,8 +412,9 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
     return rc;
   const int64_t J = e.ncells;
   const int tile = tile_for(extent);
+  if (extent > tile) return fail(EIK_EINVAL, "internal: a cell of %d nodes exceeds the %d-node tile", extent, tile);
   const int workers =
-      o.workers ? o.workers : std::max(1, default_workers(ws, J, tile, dt, n) / std::max(1, ctx.share));
+      o.workers ? o.workers : std::max(1, default_workers(ws, J, tile, dt, method, n) / std::max(1, ctx.share));
 
   const unsigned trace_cap = 1u << 20;
   if (g_trace) {
@@ -456,7 +472,7 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
     if ((rc = setup_engine(ws->coarse, cinst, EIK_F64, EIK_EXACT, 0, -1.0, 0, 0, 0, timeout, stream, &ce)))
       return rc;
     HIP_TRY(launch_prepare(ce, J, stream));
-    const int cw = std::max(1, default_workers(ws, ce.ncells, tile_for(cext), EIK_F64, n) /
+    const int cw = std::max(1, default_workers(ws, ce.ncells, tile_for(cext), EIK_F64, EIK_EXACT, n) /
                                    std::max(1, ctx.share));
     HIP_TRY(launch_solve(ce, cw, tile_for(cext), stream));
     HIP_TRY(launch_dag(e, ws->cout.as<CoarseOut>(), (int)J, stream));

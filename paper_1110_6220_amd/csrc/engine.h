@@ -10,12 +10,13 @@ namespace eik {
 // a wave is processing the cell; kDone1: its first processing has finished
 // (cells that are not ordered by dependency counts start with kDone1 set).
 // Bits 8..11: preferred sweep directions raised by neighbours (0 SW, 1 NW,
-// 2 NE, 3 SE).
+// 2 NE, 3 SE); bits 12..15: the sides (0 W, 1 E, 2 S, 3 N) those neighbours
+// sit on.
 constexpr uint32_t kPending = 1u;
 constexpr uint32_t kRunning = 2u;
 constexpr uint32_t kDone1 = 4u;
 constexpr int kFlagShift = 8;
-constexpr uint32_t kFlagMask = 0xFu << kFlagShift;
+constexpr int kSideShift = 12;
 
 // Per-cell order bits (DAG ordering): bits 0..3 = sides (0 W, 1 E, 2 S, 3 N)
 // whose neighbour comes earlier in the coarse order; kOrdConverge = the cell
@@ -137,6 +138,8 @@ struct CoarseOut {
 // (unless dag) the exit cells queued.
 hipError_t launch_prepare(const Engine& e, int64_t max_nodes, hipStream_t stream);
 hipError_t launch_solve(const Engine& e, int workers, int tile, hipStream_t stream);
+// Solver waves that fit on one compute unit at once (registers and LDS).
+int solve_waves_per_cu(int dtype, int method, int tile);
 hipError_t launch_residual(const Engine& e, int64_t max_nodes, hipStream_t stream);
 // coarse speeds, masks and exit costs of every fine cell (cells of instance k
 // at co[k].*[cell - cell0])

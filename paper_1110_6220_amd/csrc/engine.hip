@@ -151,6 +151,15 @@ __device__ __forceinline__ double shr1_or(double v, double edge) {
 }
 
 __device__ __forceinline__ int bcast(int v, int src_lane) { return __shfl(v, src_lane, 64); }
+
+// The lane id as a value the compiler cannot see through.  Each phase of a
+// cell's processing (load, sweeps, publish, store) derives its addresses from
+// its own opaque copy, so lane-derived values are computed where they are
+// used instead of being hoisted and held in registers across other phases.
+__device__ __forceinline__ int opaque_lane(int lane) {
+  asm volatile("" : "+v"(lane));
+  return lane;
+}
 __device__ __forceinline__ unsigned long long ballot(bool p) { return __ballot(p); }
 
 // orderable encoding of a float as an unsigned int (monotone)
@@ -401,14 +410,16 @@ __device__ __forceinline__ void q_done(const Engine& e, int ring) {
 // cell state transitions (one lane)
 // ----------------------------------------------------------------------------
 
-// A neighbour found that cell g must be processed (again), with preferred
-// directions fl.  Enqueued when it is idle and its first processing is done;
-// a running cell takes the request itself when it finishes, and a cell still
-// waiting for its first processing reads the new values when it starts.
-__device__ void requeue(const Engine& e, int g, uint32_t fl, float key) {
+// A neighbour on side `sides` (bit mask, 0 for none) found that cell g must
+// be processed (again), with preferred directions fl.  Enqueued when it is
+// idle and its first processing is done; a running cell takes the request
+// itself when it finishes, and a cell still waiting for its first processing
+// reads the new values when it starts.
+__device__ void requeue(const Engine& e, int g, uint32_t fl, uint32_t sides, float key) {
   order_release();
-  const uint32_t old = __hip_atomic_fetch_or(&e.st[g], kPending | (fl << kFlagShift),
-                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const uint32_t old =
+      __hip_atomic_fetch_or(&e.st[g], kPending | (fl << kFlagShift) | (sides << kSideShift),
+                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (!(old & (kPending | kRunning)) && (old & kDone1)) {
     atomic_add_relaxed(&e.ctl->active, 1ull);
     if (e.ready_at) e.ready_at[g] = wall_clock64();
@@ -468,6 +479,7 @@ __device__ uint32_t claim(const Engine& e, int g) {
 // oracle's explicit test does.
 template <typename T, int P, bool DIRECTIONAL>
 __device__ uint32_t sweep_tile(T* tu, const T* td, int w, int hgt, int dir, int lane) {
+  lane = opaque_lane(lane);
   const int sx = (dir == 0 || dir == 1) ? 1 : -1;
   const int sy = (dir == 0 || dir == 3) ? 1 : -1;
   const int rowstep = sy * P;
@@ -517,6 +529,7 @@ __device__ uint32_t sweep_tile(T* tu, const T* td, int w, int hgt, int dir, int 
 // each lane walks its column.
 template <typename T, int P>
 __device__ bool tile_converged(const T* tu, const T* td, int w, int hgt, int lane) {
+  lane = opaque_lane(lane);
   bool bad = false;
   if (lane < w) {
 #pragma unroll 4
@@ -586,55 +599,66 @@ __device__ __forceinline__ CellBox cell_box(const Inst& I, int local) {
 }
 
 // Loads the tile (rows -1..hgt, columns -1..w without corners) from u and
-// delta into LDS; outside the grid: +inf.  Every lane loads from a clamped,
-// in-bounds address and substitutes +inf afterwards, so the loads of a chunk
-// of kChunk rows issue back to back without branches and a tile costs a few
-// memory latencies rather than one per row.
+// delta into LDS; outside the grid: +inf.  Rows go straight from memory into
+// LDS (global_load_lds: each active lane moves one dword of the row), so the
+// loads of every row of the tile are in flight together without holding any
+// data in registers; u is read with the coherent policy (sc1) because
+// neighbouring cells write it concurrently.  The west and east halo columns
+// (one element per row) go through registers.  One wait at the end.
 // fresh: the cell has never been processed and holds no exit node, so its
 // interior values are all +inf and only delta and the halo are read.
 template <typename T, int P>
 __device__ void load_tile(T* tu, T* td, const Inst& I, const CellBox& B, int lane,
                           bool with_interior, bool fresh = false) {
-  constexpr int kChunk = 16;
-  const gptr<const T> u = to_global(static_cast<const T*>(I.u));
-  const gptr<const T> dl = to_global(static_cast<const T*>(I.delta));
+  lane = opaque_lane(lane);
+  using lds_ptr = __attribute__((address_space(3))) void*;
+  constexpr int kDw = (int)(sizeof(T) / 4);  // dwords per element
+  constexpr int kCohPolicy = 16;             // sc1
+  const char* ub = static_cast<const char*>(I.u);
+  const char* db = static_cast<const char*>(I.delta);
   const T INF = inf_v<T>();
   const int nx = I.nx, ny = I.ny;
-  const int rows = B.hgt + 2;
-  const bool col = lane < B.w;
-  const int ci = B.x0 + (col ? lane : 0);
-  for (int r0 = 0; r0 < rows; r0 += kChunk) {
-    if (!with_interior && r0 > 0 && r0 + kChunk < rows) continue;
-    T v[kChunk], dv[kChunk];
-#pragma unroll
-    for (int c = 0; c < kChunk; ++c) {
-      const int r = r0 + c - 1;
-      const int j = B.y0 + r;
-      const int jc = j < 0 ? 0 : (j >= ny ? ny - 1 : j);
-      const size_t k = (size_t)jc * nx + ci;
-      const bool halo_row = r < 0 || r >= B.hgt;
-      v[c] = (fresh && !halo_row) ? INF : ld_coh(u + k);
-      dv[c] = dl[k];
+  const int rowdw = B.w * kDw;  // dwords of one tile row
+  for (int r = -1; r <= B.hgt; ++r) {
+    const bool halo_row = r < 0 || r == B.hgt;
+    if (!with_interior && !halo_row) {
+      r = B.hgt - 1;  // skip to the north halo row
+      continue;
     }
+    const int j = B.y0 + r;
+    T* lu = tu + (r + 1) * P + 1;
+    T* ld = td + (r + 1) * P + 1;
+    if (j < 0 || j >= ny) {
+      if (lane < B.w) {
+        lu[lane] = INF;
+        ld[lane] = INF;
+      }
+      continue;
+    }
+    const bool skip_u = fresh && !halo_row;
+    const size_t row = ((size_t)j * nx + B.x0) * sizeof(T);
 #pragma unroll
-    for (int c = 0; c < kChunk; ++c) {
-      const int r = r0 + c - 1;  // tile row, -1 .. hgt
-      const int j = B.y0 + r;
-      const bool need = r0 + c < rows && (with_interior || r < 0 || r >= B.hgt);
-      const bool in = j >= 0 && j < ny;
-      if (col && need) {
-        tu[(r + 1) * P + lane + 1] = in ? v[c] : INF;
-        td[(r + 1) * P + lane + 1] = in ? dv[c] : INF;
+    for (int part = 0; part < (kDw * (P - 2) + 63) / 64; ++part) {
+      const int dw = part * 64 + lane;
+      if (part * 64 < rowdw && dw < rowdw) {
+        if (!skip_u)
+          __builtin_amdgcn_global_load_lds(ub + row + 4 * (size_t)dw,
+                                           (lds_ptr)((char*)lu + part * 256), 4, 0, kCohPolicy);
+        __builtin_amdgcn_global_load_lds(db + row + 4 * (size_t)dw,
+                                         (lds_ptr)((char*)ld + part * 256), 4, 0, 0);
       }
     }
+    if (skip_u && lane < B.w) lu[lane] = INF;
   }
   {
+    const gptr<const T> u = to_global(static_cast<const T*>(I.u));
+    const gptr<const T> dl = to_global(static_cast<const T*>(I.delta));
     const int jr = B.y0 + (lane < B.hgt ? lane : 0);
-    const size_t row = (size_t)jr * nx;
+    const size_t rowi = (size_t)jr * nx;
     const int iw = B.x0 > 0 ? B.x0 - 1 : 0;
     const int ie = B.x1 < nx ? B.x1 : nx - 1;
-    const T vw = ld_coh(u + row + iw), dw = dl[row + iw];
-    const T ve = ld_coh(u + row + ie), de = dl[row + ie];
+    const T vw = ld_coh(u + rowi + iw), dw = dl[rowi + iw];
+    const T ve = ld_coh(u + rowi + ie), de = dl[rowi + ie];
     if (lane < B.hgt) {
       tu[(lane + 1) * P] = B.x0 > 0 ? vw : INF;
       td[(lane + 1) * P] = B.x0 > 0 ? dw : INF;
@@ -642,11 +666,14 @@ __device__ void load_tile(T* tu, T* td, const Inst& I, const CellBox& B, int lan
       td[(lane + 1) * P + B.w + 1] = B.x1 < nx ? de : INF;
     }
   }
+  // the row transfers write LDS asynchronously: wait for all of them
+  __builtin_amdgcn_s_waitcnt(0);
 }
 
 // Writes the whole tile back to u.
 template <typename T, int P>
 __device__ void store_tile(const T* tu, const Inst& I, const CellBox& B, int lane) {
+  lane = opaque_lane(lane);
   T* u = static_cast<T*>(I.u);
   if (lane < B.w)
     for (int r = 0; r < B.hgt; ++r)
@@ -713,46 +740,60 @@ __device__ uint32_t line_monotone(T v, bool fin, int lane) {
 // last published, re-queues neighbours by the add criterion of Algorithm
 // generic_LC_cells (FHCM narrows the raised directions by the monotonicity
 // check of Algorithm FHCM), and lowers their cell values (eq. cell_value).
-template <typename T, int P>
+template <typename T, int P, int M>
 __device__ void publish(const Engine& e, const Inst& I, const CellBox& B, int g, T* tu,
                         const T* td, T pub[4], bool first, int lane) {
+  lane = opaque_lane(lane);
   const T INF = inf_v<T>();
   T* u = static_cast<T*>(I.u);
-  bool crit[4];
-  float kv[4];
-  int karg[4];
-  uint32_t mono[4];
-#pragma unroll
+  // per side: add criterion met somewhere, max finite value and its lane,
+  // monotonicity; lane `side` keeps side's results
+  bool my_crit = false;
+  float my_kv = -__builtin_huge_valf();
+  int my_karg = -1;
+  uint32_t my_mono = 3u;
+#pragma nounroll
   for (int side = 0; side < 4; ++side) {
     // side 0 W: column 0, 1 E: column w-1 (lane = row); 2 S: row 0, 3 N: row
     // hgt-1 (lane = column)
     const bool vert = side <= 1;
     const int len = vert ? B.hgt : B.w;
     const bool ok = lane < len;
-    int idx_in, idx_out;
-    if (side == 0) { idx_in = (lane + 1) * P + 1; idx_out = idx_in - 1; }
-    else if (side == 1) { idx_in = (lane + 1) * P + B.w; idx_out = idx_in + 1; }
-    else if (side == 2) { idx_in = P + lane + 1; idx_out = idx_in - P; }
-    else { idx_in = B.hgt * P + lane + 1; idx_out = idx_in + P; }
-    if (!ok) idx_in = idx_out = P + 1;
+    const int step = vert ? P : 1;      // LDS stride along the side
+    const int out = side == 0 ? -1 : side == 1 ? 1 : side == 2 ? -P : P;
+    const int base = side == 0 ? P + 1 : side == 1 ? P + B.w : side == 2 ? P + 1 : B.hgt * P + 1;
+    const int idx_in = ok ? base + lane * step : P + 1;
+    const int idx_out = ok ? idx_in + out : P + 1;
+    const T ps = side == 0 ? pub[0] : side == 1 ? pub[1] : side == 2 ? pub[2] : pub[3];
     const T v = tu[idx_in];
     bool c = false;
     float vmax = -__builtin_huge_valf();
     if (ok) {
       const bool is_src = td[idx_in] == INF && v != INF;
-      const bool changed = v < pub[side] || (first && is_src);
-      if (v < pub[side]) {
+      const bool changed = v < ps || (first && is_src);
+      if (v < ps) {
         const int ii = vert ? (side == 0 ? B.x0 : B.x1 - 1) : B.x0 + lane;
         const int jj = vert ? B.y0 + lane : (side == 2 ? B.y0 : B.y1 - 1);
         st_coh(u + (size_t)jj * I.nx + ii, v);
       }
-      pub[side] = v;
       c = changed && td[idx_out] != INF && v < tu[idx_out];
       if (v != INF) vmax = (float)v;
     }
-    crit[side] = ballot(c) != 0ull;
-    kv[side] = wave_max(vmax, &karg[side]);
-    mono[side] = e.method == kFhcm ? line_monotone(v, ok && v != INF, lane) : 3u;
+    const T np = ok ? v : ps;
+    if (side == 0) pub[0] = np;
+    else if (side == 1) pub[1] = np;
+    else if (side == 2) pub[2] = np;
+    else pub[3] = np;
+    const bool cr = ballot(c) != 0ull;
+    int ka;
+    const float kvv = wave_max(vmax, &ka);
+    const uint32_t mo = M == kFhcm ? line_monotone(v, ok && v != INF, lane) : 3u;
+    if (lane == side) {
+      my_crit = cr;
+      my_kv = kvv;
+      my_karg = ka;
+      my_mono = mo;
+    }
   }
   // make the boundary values visible before any neighbour is signalled
   order_release();
@@ -774,24 +815,24 @@ __device__ void publish(const Engine& e, const Inst& I, const CellBox& B, int g,
     }
     if (nb >= 0) {
       float key = __builtin_huge_valf();
-      if (!e.dag && karg[side] >= 0) {
+      if (!e.dag && my_karg >= 0) {
         const int along = side == 0 ? B.x0 : side == 1 ? B.x1 - 1 : side == 2 ? B.y0 : B.y1 - 1;
-        const int other = side <= 1 ? B.y0 + karg[side] : B.x0 + karg[side];
+        const int other = side <= 1 ? B.y0 + my_karg : B.x0 + my_karg;
         const double fy = speed_at<T>(I, side, along, other, wk);
         if (fy > 0.0) {
-          key = (float)((double)kv[side] + (0.5 * (1 + wk) * I.h) / fy);
+          key = (float)((double)my_kv + (0.5 * (1 + wk) * I.h) / fy);
           const unsigned int old = __hip_atomic_fetch_min(&e.key[nb], key_bits(key),
                                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           const float okey = key_float(old);
           if (okey < key) key = okey;
         }
       }
-      if (crit[side]) {
+      if (my_crit) {
         const int recv = side ^ 1;  // the receiving cell sees us on the opposite side
         uint32_t dirs = side_dirs(recv);
-        if (e.method == kFhcm) {
+        if (M == kFhcm) {
           // line order N->S for W/E lines (descending lanes), W->E for S/N lines
-          const uint32_t m = mono[side];
+          const uint32_t m = my_mono;
           const bool nondec = side <= 1 ? (m & 2u) : (m & 1u);
           const bool noninc = side <= 1 ? (m & 1u) : (m & 2u);
           atomic_add_relaxed(&e.ctl->mon_checks, 1ull);
@@ -804,7 +845,7 @@ __device__ void publish(const Engine& e, const Inst& I, const CellBox& B, int g,
             dirs = nondec ? a : b;
           }
         }
-        requeue(e, nb, dirs, key);
+        requeue(e, nb, dirs, 1u << recv, key);
       }
     }
   }
@@ -814,7 +855,7 @@ __device__ void publish(const Engine& e, const Inst& I, const CellBox& B, int g,
 // persistent solver kernel
 // ----------------------------------------------------------------------------
 
-template <typename T, int S>
+template <typename T, int S, int M>
 __global__ __launch_bounds__(64) void k_solve(Engine e) {
   constexpr int P = S + 2;
   __shared__ T tu[P * P + 64];  // tile + per-lane dummy slots
@@ -843,13 +884,14 @@ __global__ __launch_bounds__(64) void k_solve(Engine e) {
     if (e.trace) tr[0] = wall_clock64();
     const Inst I = inst_of(e, g);  // by value: fields stay in registers
     const CellBox B = cell_box(I, g - I.cell0);
-    uint32_t fl = 0, ordb = 0;
+    uint32_t fl = 0, ordb = 0, sides = 0;
     int first = 0, done1 = 0;
     uint32_t run_state = kRunning;  // the state word written by claim (lane 0)
     if (lane == 0) {
       const uint32_t old = claim(e, g);
       run_state = (old & kDone1) | kRunning;
       fl = (old >> kFlagShift) & 0xFu;
+      sides = (old >> kSideShift) & 0xFu;
       done1 = (old & kDone1) != 0u;
       const uint32_t v = ld_coh(&e.visits[g]);
       st_coh(&e.visits[g], v + 1u);
@@ -859,10 +901,11 @@ __global__ __launch_bounds__(64) void k_solve(Engine e) {
       if (tot >= ctl->guard) set_err(ctl, kErrGuard);
     }
     fl = (uint32_t)bcast((int)fl, 0);
+    sides = (uint32_t)bcast((int)sides, 0);
     ordb = (uint32_t)bcast((int)ordb, 0);
     done1 = bcast(done1, 0);
     bool is_first = bcast(first, 0) != 0;
-    if (e.dag && !done1) fl |= fmsm_dirs(ordb & 0xFu);
+    if (e.dag && !done1) sides |= ordb & 0xFu;
     order_acquire();
     tick(e, &ctl->t_claim, &t0, lane);
     // a cell's interior is written only by its own processing
@@ -876,7 +919,7 @@ __global__ __launch_bounds__(64) void k_solve(Engine e) {
     if (e.trace) tr[1] = wall_clock64();
     bool aborted = false;
     for (;;) {
-      if (e.method == kFmsm) {
+      if constexpr (M == kFmsm) {
         if (ordb & kOrdConverge) {
           // cells holding exit nodes (or unreached by the coarse front): plain
           // FSM to convergence
@@ -889,6 +932,7 @@ __global__ __launch_bounds__(64) void k_solve(Engine e) {
           // at most four sweeps in the coarse-upwind directions, with
           // sweep-directional updates
           const uint32_t dirs = fmsm_dirs(ordb & 0xFu);
+#pragma nounroll
           for (int d = 0; d < 4; ++d)
             if (dirs & (1u << d)) {
               const bool ch = sweep_tile<T, P, true>(tu, td, B.w, B.hgt, d, lane) & 1u;
@@ -896,25 +940,32 @@ __global__ __launch_bounds__(64) void k_solve(Engine e) {
             }
         }
         tick(e, &ctl->t_sweep, &t0, lane);
-      } else if (e.method == kFhcm) {
+      } else if constexpr (M == kFhcm) {
         // one non-directional sweep per flagged direction, canonical order
+#pragma nounroll
         for (int d = 0; d < 4; ++d)
           if (fl & (1u << d)) {
             const bool ch = sweep_tile<T, P, false>(tu, td, B.w, B.hgt, d, lane) & 1u;
             if (ch) nsweeps++; else nchecks++;
           }
         tick(e, &ctl->t_sweep, &t0, lane);
-        publish<T, P>(e, I, B, g, tu, td, pub, is_first, lane);
+        publish<T, P, M>(e, I, B, g, tu, td, pub, is_first, lane);
         is_first = false;
         tick(e, &ctl->t_publish, &t0, lane);
       } else {
-        // exact: preferred directions first, in canonical order, then the
-        // others; after four sweeps the canonical loop; until converged
+        // exact: first the sweeps that start in a corner between two sides
+        // with inflow (one-axis inflow: both corners of each such side),
+        // then the other preferred directions, then the rest, each group in
+        // canonical order; after four sweeps the canonical loop; until
+        // converged.  The order changes the work, not the result.
+        const uint32_t lead = fmsm_dirs(sides);
         int sched[4], n = 0;
         for (int d = 0; d < 4; ++d)
-          if (fl & (1u << d)) sched[n++] = d;
+          if (lead & (1u << d)) sched[n++] = d;
         for (int d = 0; d < 4; ++d)
-          if (!(fl & (1u << d))) sched[n++] = d;
+          if ((fl & ~lead) & (1u << d)) sched[n++] = d;
+        for (int d = 0; d < 4; ++d)
+          if (!((fl | lead) & (1u << d))) sched[n++] = d;
         for (int k = 0;; ++k) {
           const int dir = k < 4 ? sched[k] : (k & 3);
           const uint32_t res = sweep_tile<T, P, false>(tu, td, B.w, B.hgt, dir, lane);
@@ -922,7 +973,7 @@ __global__ __launch_bounds__(64) void k_solve(Engine e) {
           if (ch) nsweeps++; else nchecks++;
           tick(e, &ctl->t_sweep, &t0, lane);
           if (e.eager && (ch || is_first)) {
-            publish<T, P>(e, I, B, g, tu, td, pub, is_first, lane);
+            publish<T, P, M>(e, I, B, g, tu, td, pub, is_first, lane);
             is_first = false;
             tick(e, &ctl->t_publish, &t0, lane);
           }
@@ -934,7 +985,7 @@ __global__ __launch_bounds__(64) void k_solve(Engine e) {
           }
         }
         if (!e.eager) {
-          publish<T, P>(e, I, B, g, tu, td, pub, is_first, lane);
+          publish<T, P, M>(e, I, B, g, tu, td, pub, is_first, lane);
           is_first = false;
           tick(e, &ctl->t_publish, &t0, lane);
         }
@@ -962,11 +1013,11 @@ __global__ __launch_bounds__(64) void k_solve(Engine e) {
         }
         uint32_t exp = run_state;
         const bool idle =
-            e.method == kFmsm ||
+            M == kFmsm ||
             __hip_atomic_compare_exchange_strong(&e.st[g], &exp, kDone1, __ATOMIC_RELAXED,
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (idle) {
-          if (e.method == kFmsm) st_coh(&e.st[g], kDone1);
+          if (M == kFmsm) st_coh(&e.st[g], kDone1);
           atomic_add_relaxed(&ctl->active, ~0ull);
           q_done(e, ring);
         } else {
@@ -974,6 +1025,7 @@ __global__ __launch_bounds__(64) void k_solve(Engine e) {
           const uint32_t old = claim(e, g);
           run_state = (old & kDone1) | kRunning;
           fl = (old >> kFlagShift) & 0xFu;
+          sides = (old >> kSideShift) & 0xFu;
           const uint32_t v = ld_coh(&e.visits[g]);
           st_coh(&e.visits[g], v + 1u);
           const unsigned long long tot = atomic_add_relaxed(&ctl->visits, 1ull);
@@ -986,6 +1038,7 @@ __global__ __launch_bounds__(64) void k_solve(Engine e) {
       if (!again) break;
       if (get_err(ctl)) break;
       fl = (uint32_t)bcast((int)fl, 0);
+      sides = (uint32_t)bcast((int)sides, 0);
       done1 = 1;
       order_acquire();
       load_tile<T, P>(tu, td, I, B, lane, false);  // fresh halo only
@@ -1142,7 +1195,7 @@ __global__ void k_init_u(Engine e) {
         const int g = cell_of_node(I, (int)(k % I.nx), (int)(k / I.nx));
         __hip_atomic_fetch_min(&e.key[g], key_bits((float)v), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
-        requeue(e, g, e.method == kFhcm ? 0xFu : 0u, (float)v);
+        requeue(e, g, e.method == kFhcm ? 0xFu : 0u, 0u, (float)v);
       }
     }
     u[k] = v;
@@ -1190,7 +1243,7 @@ __global__ void k_apply_sources(Engine e) {
     const int g = cell_of_node(I, (int)(k % I.nx), (int)(k / I.nx));
     const float key = e.method == kFhcm ? 0.0f : (float)q;
     __hip_atomic_fetch_min(&e.key[g], key_bits(key), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    requeue(e, g, e.method == kFhcm ? 0xFu : 0u, key);
+    requeue(e, g, e.method == kFhcm ? 0xFu : 0u, 0u, key);
   }
 }
 
@@ -1381,17 +1434,48 @@ hipError_t launch_prepare(const Engine& e, int64_t max_nodes, hipStream_t stream
   return hipGetLastError();
 }
 
-hipError_t launch_solve(const Engine& e, int workers, int tile, hipStream_t stream) {
-  const dim3 g(workers), b(64);
-  if (e.dtype == 0) {
-    if (tile <= 16) hipLaunchKernelGGL((k_solve<double, 16>), g, b, 0, stream, e);
-    else if (tile <= 32) hipLaunchKernelGGL((k_solve<double, 32>), g, b, 0, stream, e);
-    else hipLaunchKernelGGL((k_solve<double, 64>), g, b, 0, stream, e);
-  } else {
-    if (tile <= 16) hipLaunchKernelGGL((k_solve<float, 16>), g, b, 0, stream, e);
-    else if (tile <= 32) hipLaunchKernelGGL((k_solve<float, 32>), g, b, 0, stream, e);
-    else hipLaunchKernelGGL((k_solve<float, 64>), g, b, 0, stream, e);
+template <typename T, int M>
+static void launch_solve_t(const Engine& e, dim3 g, int tile, hipStream_t stream) {
+  if (tile <= 16) hipLaunchKernelGGL((k_solve<T, 16, M>), g, dim3(64), 0, stream, e);
+  else if (tile <= 32) hipLaunchKernelGGL((k_solve<T, 32, M>), g, dim3(64), 0, stream, e);
+  else hipLaunchKernelGGL((k_solve<T, 64, M>), g, dim3(64), 0, stream, e);
+}
+
+template <typename T>
+static void launch_solve_m(const Engine& e, dim3 g, int tile, hipStream_t stream) {
+  if (e.method == kFmsm) launch_solve_t<T, kFmsm>(e, g, tile, stream);
+  else if (e.method == kFhcm) launch_solve_t<T, kFhcm>(e, g, tile, stream);
+  else launch_solve_t<T, kExact>(e, g, tile, stream);
+}
+
+template <typename T, int M>
+static int occupancy_t(int tile) {
+  int n = 0;
+  hipError_t err;
+  if (tile <= 16)
+    err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_solve<T, 16, M>, 64, 0);
+  else if (tile <= 32)
+    err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_solve<T, 32, M>, 64, 0);
+  else
+    err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_solve<T, 64, M>, 64, 0);
+  return err == hipSuccess && n > 0 ? n : 1;
+}
+
+int solve_waves_per_cu(int dtype, int method, int tile) {
+  if (dtype == 0) {
+    if (method == kFmsm) return occupancy_t<double, kFmsm>(tile);
+    if (method == kFhcm) return occupancy_t<double, kFhcm>(tile);
+    return occupancy_t<double, kExact>(tile);
   }
+  if (method == kFmsm) return occupancy_t<float, kFmsm>(tile);
+  if (method == kFhcm) return occupancy_t<float, kFhcm>(tile);
+  return occupancy_t<float, kExact>(tile);
+}
+
+hipError_t launch_solve(const Engine& e, int workers, int tile, hipStream_t stream) {
+  const dim3 g(workers);
+  if (e.dtype == 0) launch_solve_m<double>(e, g, tile, stream);
+  else launch_solve_m<float>(e, g, tile, stream);
   return hipGetLastError();
 }
 

@@ -84,6 +84,19 @@ def test_ragged_tiles_and_degenerate_grids(eik):
             assert max_rel(got, U) <= TOL64, (nx, ny, cell)
 
 
+@pytest.mark.parametrize("n,cell", [(769, 64), (289, 32), (129, 16), (65, 64), (1025, 32)])
+def test_last_cell_one_node_wider(eik, n, cell):
+    """n = 1 (mod s): the standard tiling would merge a one-node last cell into
+    a cell wider than the tile; every node must still be solved."""
+    w = W.smooth_sine(n, 0.4, 2.0)
+    w["src"] = np.array([0, n * n - 1, (n // 3) * n + n // 2], dtype=np.int64)
+    w["q"] = np.zeros(3)
+    U = O.fmm(O.Problem.from_workload(w))
+    got, st = solve_dev(eik, w, cell=cell)
+    assert max_rel(got, U) <= TOL64
+    assert st["cell_used"] == cell
+
+
 def test_every_node_a_source(eik):
     F = np.ones((20, 30))
     w = W._pack("allsrc", F, 0.1, np.arange(600), q=np.linspace(0.0, 1.0, 600))
