@@ -533,8 +533,8 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
     if (FILE* f = std::fopen(g_trace, "w")) {
       for (unsigned k = 0; k < cnt; ++k) {
         const unsigned long long* r = &t[(size_t)k * 8];
-        std::fprintf(f, "%llu %llu %llu %llu %llu %llu %llu %llu %llu\n", r[0] & 0xffffffffull,
-                     (r[0] >> 32) & 0xffff, r[0] >> 48, r[1], r[2], r[3], r[4], r[5], r[6]);
+        std::fprintf(f, "%llu %llu %llu %llu %llu %llu %llu %llu %llu %llu\n", r[0] & 0xffffffffull,
+                     (r[0] >> 32) & 0xffff, r[0] >> 48, r[1], r[2], r[3], r[4], r[5], r[6], r[7]);
       }
       std::fclose(f);
     }

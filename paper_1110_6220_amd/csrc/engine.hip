@@ -150,7 +150,11 @@ __device__ __forceinline__ double shr1_or(double v, double edge) {
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
-__device__ __forceinline__ int bcast(int v, int src_lane) { return __shfl(v, src_lane, 64); }
+// Broadcast of lane src_lane's value; the result is marked wave-uniform so
+// that everything derived from it lives in scalar registers.
+__device__ __forceinline__ int bcast(int v, int src_lane) {
+  return __builtin_amdgcn_readfirstlane(__shfl(v, src_lane, 64));
+}
 
 // The lane id as a value the compiler cannot see through.  Each phase of a
 // cell's processing (load, sweeps, publish, store) derives its addresses from
@@ -600,7 +604,7 @@ __device__ __forceinline__ CellBox cell_box(const Inst& I, int local) {
 
 // Loads the tile (rows -1..hgt, columns -1..w without corners) from u and
 // delta into LDS; outside the grid: +inf.  Rows go straight from memory into
-// LDS (global_load_lds: each active lane moves one dword of the row), so the
+// LDS (global_load_lds: each active lane moves 16 bytes of the row), so the
 // loads of every row of the tile are in flight together without holding any
 // data in registers; u is read with the coherent policy (sc1) because
 // neighbouring cells write it concurrently.  The west and east halo columns
@@ -612,13 +616,14 @@ __device__ void load_tile(T* tu, T* td, const Inst& I, const CellBox& B, int lan
                           bool with_interior, bool fresh = false) {
   lane = opaque_lane(lane);
   using lds_ptr = __attribute__((address_space(3))) void*;
-  constexpr int kDw = (int)(sizeof(T) / 4);  // dwords per element
   constexpr int kCohPolicy = 16;             // sc1
   const char* ub = static_cast<const char*>(I.u);
   const char* db = static_cast<const char*>(I.delta);
   const T INF = inf_v<T>();
   const int nx = I.nx, ny = I.ny;
-  const int rowdw = B.w * kDw;  // dwords of one tile row
+  const int rowbytes = B.w * (int)sizeof(T);
+  const int n16 = rowbytes >> 4;           // full 16-byte pieces of a row
+  const int tail_dw = (rowbytes & 15) >> 2;  // remaining dwords
   for (int r = -1; r <= B.hgt; ++r) {
     const bool halo_row = r < 0 || r == B.hgt;
     if (!with_interior && !halo_row) {
@@ -637,15 +642,19 @@ __device__ void load_tile(T* tu, T* td, const Inst& I, const CellBox& B, int lan
     }
     const bool skip_u = fresh && !halo_row;
     const size_t row = ((size_t)j * nx + B.x0) * sizeof(T);
-#pragma unroll
-    for (int part = 0; part < (kDw * (P - 2) + 63) / 64; ++part) {
-      const int dw = part * 64 + lane;
-      if (part * 64 < rowdw && dw < rowdw) {
+    // 16 bytes per lane for the bulk of the row, then single dwords for the
+    // ragged end (rows are at most 512 bytes: one instruction each)
+    if (lane < n16) {
+      if (!skip_u)
+        __builtin_amdgcn_global_load_lds(ub + row + 16 * (size_t)lane, (lds_ptr)lu, 16, 0, kCohPolicy);
+      __builtin_amdgcn_global_load_lds(db + row + 16 * (size_t)lane, (lds_ptr)ld, 16, 0, 0);
+    }
+    if (tail_dw) {
+      if (lane < tail_dw) {
+        const size_t at = row + 16 * (size_t)n16 + 4 * (size_t)lane;
         if (!skip_u)
-          __builtin_amdgcn_global_load_lds(ub + row + 4 * (size_t)dw,
-                                           (lds_ptr)((char*)lu + part * 256), 4, 0, kCohPolicy);
-        __builtin_amdgcn_global_load_lds(db + row + 4 * (size_t)dw,
-                                         (lds_ptr)((char*)ld + part * 256), 4, 0, 0);
+          __builtin_amdgcn_global_load_lds(ub + at, (lds_ptr)((char*)lu + 16 * n16), 4, 0, kCohPolicy);
+        __builtin_amdgcn_global_load_lds(db + at, (lds_ptr)((char*)ld + 16 * n16), 4, 0, 0);
       }
     }
     if (skip_u && lane < B.w) lu[lane] = INF;
@@ -908,6 +917,7 @@ __global__ __launch_bounds__(64) void k_solve(Engine e) {
     if (e.dag && !done1) sides |= ordb & 0xFu;
     order_acquire();
     tick(e, &ctl->t_claim, &t0, lane);
+    if (e.trace) tr[3] = wall_clock64();
     // a cell's interior is written only by its own processing
     load_tile<T, P>(tu, td, I, B, lane, true, e.dag && is_first && !(ordb & kOrdSource));
     T pub[4];
@@ -1056,7 +1066,7 @@ __global__ __launch_bounds__(64) void k_solve(Engine e) {
           t[4] = tr[2];
           t[5] = wall_clock64();
           t[6] = __builtin_amdgcn_s_getreg(4 | (0 << 6) | (31 << 11));  // HW_ID
-          t[7] = 0;
+          t[7] = tr[3];
         }
       }
     }
