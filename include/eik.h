@@ -87,6 +87,8 @@ typedef struct {
                                changed a value; 0: once per removal, after the
                                cell converged (the paper's order)              */
   int32_t schedule;         /* eik_schedule                                     */
+  int32_t timeout_ms;       /* time limit of one solve on the device; 0 = 10000.
+                               A solve that exceeds it fails with EDEVICE.     */
 } eik_opts;
 
 typedef struct {

@@ -1,0 +1,144 @@
+"""Cell-side autotuner for the exact method.
+
+The exact method's result does not depend on the cell side (the Theorem of
+Section 3.2.1 of Chacon & Vladimirsky: label-correcting on cells converges to
+the solution of the discrete system for any decomposition), so the side is a
+pure speed knob.  This script times every candidate side on synthetic problems
+of each class (precision, single problem or batch, grid size, open grid or
+dense walls) on the current device and writes the table the library compiles
+in (csrc/tuned_cells.h).
+
+    python -m paper_1110_6220_amd.autotune --out paper_1110_6220_amd/csrc/tuned_cells.h
+
+Rebuild the library afterwards (__graft_entry__.build()).
+"""
+from __future__ import annotations
+
+import argparse
+import statistics
+import time
+
+import numpy as np
+
+from . import workloads as W
+
+CANDIDATES = (8, 16, 32, 64)
+DENSE_WALLS = 0.03
+# size buckets (largest side) per wall class
+OPEN_BUCKETS = (160, 512, 1 << 30)
+DENSE_BUCKETS = (512, 1 << 30)
+
+
+def _open_samples(nmax_prev, nmax, batched, rng):
+    lo = max(nmax_prev + 1, 33)
+    hi = min(nmax, 2049)
+    if batched:
+        sides = rng.integers(lo, hi + 1, size=24 if hi <= 512 else 12)
+        return [W.gaussian_bumps(int(n), rng) for n in sides]
+    sides = sorted({lo, (lo + hi) // 2, hi})
+    return [W.smooth_sine(int(n), 0.5) for n in sides] + [W.gaussian_bumps(int(hi), rng)]
+
+
+def _dense_samples(nmax_prev, nmax, batched, rng):
+    lo = max(nmax_prev + 1, 129)
+    hi = min(nmax, 2049)
+    count = 16 if batched else 3
+    out = []
+    for _ in range(count):
+        n = int(round(np.exp(rng.uniform(np.log(lo), np.log(hi)))))
+        out.append(W.kruskal_maze(n, rng))
+    return out
+
+
+def _time(fn, reps=3):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t)
+    return statistics.median(ts)
+
+
+def tune(dtypes=("f64", "f32"), log=print):
+    import torch
+
+    from . import eik
+    dev = torch.device("cuda:0")
+    rows, notes = [], []
+    for dt_code, dtype in enumerate(("f64", "f32")):
+        if dtype not in dtypes:
+            continue
+        tdt = torch.float64 if dtype == "f64" else torch.float32
+        for dense, buckets in ((0, OPEN_BUCKETS), (1, DENSE_BUCKETS)):
+            prev = 0
+            for nmax in buckets:
+                for batched in (0, 1):
+                    rng = np.random.default_rng(1000 + 10 * nmax % 997 + batched + 2 * dense)
+                    ws = (_dense_samples if dense else _open_samples)(prev, nmax, batched, rng)
+                    ds = []
+                    for w in ws:
+                        d = dict(F=torch.from_numpy(w["F"]).to(dev, tdt), h=w["h"],
+                                 src=torch.from_numpy(w["src"]).to(dev),
+                                 q=torch.from_numpy(w["q"]).to(dev))
+                        if w.get("mask") is not None:
+                            d["mask"] = torch.from_numpy(w["mask"]).to(dev)
+                        ds.append(d)
+                    times = {}
+                    for cell in CANDIDATES:
+                        if batched:
+                            t = _time(lambda: eik.eik_solve_batched(ds, dtype=dtype, cell=cell))
+                        else:
+                            t = _time(lambda: [eik.eik_solve(d["F"], d["h"], d["src"], d["q"],
+                                                             d.get("mask"), dtype=dtype, cell=cell)
+                                               for d in ds])
+                        times[cell] = t
+                    best = min(times, key=times.get)
+                    rows.append((dt_code, batched, nmax, dense, best))
+                    sides = [w["nx"] for w in ws]
+                    note = (f"{dtype} batched={batched} dense={dense} n<={nmax if nmax < 1 << 30 else 'any'}"
+                            f" ({len(ws)} problems, sides {min(sides)}..{max(sides)}): "
+                            + ", ".join(f"{c}: {times[c] * 1e3:.2f} ms" for c in CANDIDATES)
+                            + f" -> {best}")
+                    notes.append(note)
+                    log(note)
+                prev = nmax
+    return rows, notes
+
+
+def write_header(path, rows, notes, device_name):
+    lines = [
+        "// Cell sides chosen by paper_1110_6220_amd/autotune.py on " + device_name + ".",
+        "// Exact method only: its result does not depend on the cell side, so the",
+        "// table changes speed, never results.  Row: dtype (0 f64, 1 f32), batched",
+        "// (problems per launch > 1), largest side of the bucket, dense walls (wall",
+        "// density >= kDenseWalls), cell side.  Measurements (median of 3):",
+    ]
+    lines += ["//   " + n for n in notes]
+    lines += ["#pragma once", "namespace eik {", f"constexpr double kDenseWalls = {DENSE_WALLS};",
+              "struct TunedCell {", "  int dtype, batched, nmax, dense, cell;", "};",
+              "constexpr TunedCell kTunedCells[] = {"]
+    for r in rows:
+        nmax = "1 << 30" if r[2] >= 1 << 30 else str(r[2])
+        lines.append(f"    {{{r[0]}, {r[1]}, {nmax}, {r[3]}, {r[4]}}},")
+    lines += ["};", "}  // namespace eik", ""]
+    with open(path, "w") as f:
+        f.write("\n".join(lines))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--out", required=True, help="header to write")
+    ap.add_argument("--dtype", action="append", choices=["f64", "f32"])
+    args = ap.parse_args()
+    import torch
+    rows, notes = tune(tuple(args.dtype or ("f64", "f32")), log=lambda s: print(s, flush=True))
+    write_header(args.out, rows, notes, torch.cuda.get_device_name(0))
+    print("wrote", args.out, flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -18,6 +18,7 @@
 #include "../../include/eik.h"
 #include "engine.h"
 #include "internal.h"
+#include "tuned_cells.h"
 
 namespace eik {
 
@@ -76,7 +77,8 @@ void workspace_free(Workspace* w) {
   w->fine.release();
   w->coarse.release();
   for (DevBuf* b : {&w->F, &w->u, &w->mask, &w->src, &w->q, &w->cF, &w->cmask, &w->cq, &w->cu,
-                    &w->cout, &w->F64, &w->u64, &w->ready_at, &w->trace, &w->trace_n})
+                    &w->cout, &w->F64, &w->u64, &w->ready_at, &w->trace, &w->trace_n, &w->wall_in,
+                    &w->wall_cnt})
     b->release();
   if (w->ctl_host) (void)hipHostFree(w->ctl_host);
   if (w->ev0) (void)hipEventDestroy(w->ev0);
@@ -137,6 +139,7 @@ int check_opts(const eik_opts& o) {
   if (!(o.band == o.band) || std::isinf(o.band)) return fail(EIK_EINVAL, "band must be finite");
   if (o.workers < 0) return fail(EIK_EINVAL, "workers must be >= 0");
   if (o.band_window < 0 || o.band_window > 63) return fail(EIK_EINVAL, "band_window outside [0, 63]");
+  if (o.timeout_ms < 0) return fail(EIK_EINVAL, "timeout_ms must be >= 0");
   if (o.schedule < EIK_SCHED_AUTO || o.schedule > EIK_SCHED_FIFO)
     return fail(EIK_EINVAL, "unknown schedule %d", (int)o.schedule);
   if (o.method == EIK_FMSM && o.schedule != EIK_SCHED_AUTO && o.schedule != EIK_SCHED_COARSE)
@@ -187,6 +190,33 @@ int default_cell(int nx, int ny, int method) {
     return n >= 160 ? 32 : 16;
   }
   return n >= 512 ? 64 : n >= 160 ? 32 : 16;
+}
+
+// Cell side for the exact method from the tuned table (first matching row).
+static int tuned_cell(int dtype, bool batched, int nx, int ny, double wall_density) {
+  const int n = std::max(nx, ny);
+  const int dense = wall_density >= kDenseWalls ? 1 : 0;
+  for (const TunedCell& t : kTunedCells)
+    if (t.dtype == dtype && t.batched == (batched ? 1 : 0) && t.dense == dense && n <= t.nmax)
+      return t.cell;
+  return default_cell(nx, ny, EIK_EXACT);
+}
+
+// Wall density of host masks: the share of accessible nodes with an
+// inaccessible 4-neighbour, estimated on every fourth row.
+static double wall_density_host(const eik_problem& p) {
+  if (!p.mask) return 0.0;
+  uint64_t acc = 0, wall = 0;
+  for (int j = 0; j < p.ny; j += 4) {
+    const uint8_t* m = p.mask + (size_t)j * p.nx;
+    for (int i = 0; i < p.nx; ++i) {
+      if (!m[i]) continue;
+      acc++;
+      wall += (i > 0 && !m[i - 1]) || (i + 1 < p.nx && !m[i + 1]) || (j > 0 && !m[i - p.nx]) ||
+              (j + 1 < p.ny && !m[i + p.nx]);
+    }
+  }
+  return acc ? (double)wall / (double)acc : 0.0;
 }
 
 static uint32_t pow2_at_least(uint64_t v) {
@@ -330,6 +360,39 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
   if (sched == EIK_SCHED_AUTO) sched = method == EIK_FHCM ? EIK_SCHED_BANDS : EIK_SCHED_COARSE;
   const bool dag = sched == EIK_SCHED_COARSE;
 
+  // cell side per instance: the caller's, else (exact method) the tuned
+  // table, keyed by the wall density of masked problems
+  std::vector<double> density(n, 0.0);
+  if (!o.cell && method == EIK_EXACT) {
+    std::vector<WallIn> win;
+    std::vector<int> which;
+    int64_t wmax = 0;
+    for (int k = 0; k < n; ++k) {
+      if (!probs[k].mask) continue;
+      if (!o.device_ptrs) {
+        density[k] = wall_density_host(probs[k]);
+        continue;
+      }
+      win.push_back(WallIn{probs[k].mask, probs[k].nx, probs[k].ny});
+      which.push_back(k);
+      wmax = std::max<int64_t>(wmax, (int64_t)probs[k].nx * probs[k].ny);
+    }
+    if (!win.empty()) {
+      const int m = (int)win.size();
+      HIP_TRY(ws->wall_in.ensure(m * sizeof(WallIn)));
+      HIP_TRY(ws->wall_cnt.ensure(2 * m * sizeof(unsigned long long)));
+      HIP_TRY(hipMemcpyAsync(ws->wall_in.p, win.data(), m * sizeof(WallIn), hipMemcpyHostToDevice, stream));
+      HIP_TRY(hipMemsetAsync(ws->wall_cnt.p, 0, 2 * m * sizeof(unsigned long long), stream));
+      HIP_TRY(launch_wall_density(ws->wall_in.as<WallIn>(), m, wmax,
+                                  ws->wall_cnt.as<unsigned long long>(), stream));
+      std::vector<unsigned long long> cnt(2 * m);
+      HIP_TRY(hipMemcpyAsync(cnt.data(), ws->wall_cnt.p, cnt.size() * 8, hipMemcpyDeviceToHost, stream));
+      HIP_TRY(hipStreamSynchronize(stream));
+      for (int x = 0; x < m; ++x)
+        density[which[x]] = cnt[2 * x] ? (double)cnt[2 * x + 1] / (double)cnt[2 * x] : 0.0;
+    }
+  }
+
   // tiling and sizes per instance
   std::vector<Inst> inst(n);
   std::vector<Tiling> til(n);
@@ -338,7 +401,9 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
   double hs_max = 0.0;
   for (int k = 0; k < n; ++k) {
     const eik_problem& p = probs[k];
-    const int s = o.cell ? o.cell : default_cell(p.nx, p.ny, method);
+    const int s = o.cell ? o.cell
+                         : method == EIK_EXACT ? tuned_cell(dt, n > 1, p.nx, p.ny, density[k])
+                                               : default_cell(p.nx, p.ny, method);
     if ((rc = make_tiling(p.nx, p.ny, s, method, &til[k]))) return rc;
     extent = std::max(extent, til[k].extent);
     total_nodes += (int64_t)p.nx * p.ny;
@@ -405,7 +470,7 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
 
   double band = -1.0;
   if (sched == EIK_SCHED_BANDS) band = o.band > 0.0 ? o.band : hs_max;  // one cell crossing at unit speed
-  const uint64_t timeout = (uint64_t)ws->wall_khz * 1000ull * 10ull;  // 10 s
+  const uint64_t timeout = (uint64_t)ws->wall_khz * (uint64_t)(o.timeout_ms ? o.timeout_ms : 10000);
   Engine e;
   if ((rc = setup_engine(ws->fine, inst, dt, method, dag, band, o.band_window, o.eager_publish,
                          o.max_cell_visits, timeout, stream, &e)))

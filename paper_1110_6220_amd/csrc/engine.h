@@ -149,6 +149,14 @@ hipError_t launch_coarse_inputs(const Engine& fine, const CoarseOut* co_dev, int
 // cells that have no earlier neighbour
 hipError_t launch_dag(const Engine& fine, const CoarseOut* co_dev, int max_cells,
                       hipStream_t stream);
+// wall density of masked problems (cell-size tuning): counts must hold 2 n
+// zeroed entries
+struct WallIn {
+  const uint8_t* mask;
+  int32_t nx, ny;
+};
+hipError_t launch_wall_density(const WallIn* in_dev, int n, int64_t max_nodes,
+                               unsigned long long* counts, hipStream_t stream);
 // element-wise copies between precisions (FP32 results re-solved in FP64)
 hipError_t launch_convert(const void* src, int src_dtype, void* dst, int dst_dtype, int64_t n,
                           hipStream_t stream);

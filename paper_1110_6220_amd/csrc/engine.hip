@@ -1073,6 +1073,9 @@ __global__ __launch_bounds__(64) void k_solve(Engine e) {
     if (get_err(ctl)) break;
   }
   if (lane == 0) {
+    // leaving while cells are still waiting, queued or running, with no
+    // error recorded, can only be the time limit: the result is incomplete
+    if (!get_err(ctl) && ld64(&ctl->active) != 0ull) set_err(ctl, kErrDeadline);
     atomic_add_relaxed(&ctl->sweeps, nsweeps);
     atomic_add_relaxed(&ctl->checks, nchecks);
   }
@@ -1510,6 +1513,39 @@ hipError_t launch_dag(const Engine& fine, const CoarseOut* co_dev, int, hipStrea
   const dim3 gc(grid_for(fine.ncells, 256, 4096));
   hipLaunchKernelGGL(k_dag, gc, dim3(256), 0, stream, fine, co_dev);
   hipLaunchKernelGGL(k_dag_roots, gc, dim3(256), 0, stream, fine);
+  return hipGetLastError();
+}
+
+// Wall density inputs: per problem the share of accessible nodes that have
+// an inaccessible 4-neighbour inside the grid (counts[2k] accessible nodes,
+// counts[2k+1] such nodes).
+__global__ void k_wall_density(const WallIn* in, unsigned long long* counts) {
+  const WallIn w = in[blockIdx.y];
+  const int64_t n = (int64_t)w.nx * w.ny;
+  unsigned long long acc = 0, wall = 0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    if (!w.mask[k]) continue;
+    acc++;
+    const int i = (int)(k % w.nx), j = (int)(k / w.nx);
+    const bool near = (i > 0 && !w.mask[k - 1]) || (i + 1 < w.nx && !w.mask[k + 1]) ||
+                      (j > 0 && !w.mask[k - w.nx]) || (j + 1 < w.ny && !w.mask[k + w.nx]);
+    wall += near;
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    acc += __shfl_xor(acc, o, 64);
+    wall += __shfl_xor(wall, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomic_add_relaxed(&counts[2 * blockIdx.y], acc);
+    atomic_add_relaxed(&counts[2 * blockIdx.y + 1], wall);
+  }
+}
+
+hipError_t launch_wall_density(const WallIn* in_dev, int n, int64_t max_nodes,
+                               unsigned long long* counts, hipStream_t stream) {
+  hipLaunchKernelGGL(k_wall_density, dim3(grid_for(max_nodes, 256, 1024), n), dim3(256), 0, stream,
+                     in_dev, counts);
   return hipGetLastError();
 }
 

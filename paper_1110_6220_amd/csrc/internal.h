@@ -47,6 +47,7 @@ struct Workspace {
   DevBuf cF, cmask, cq, cu, cout;     // coarse problems
   DevBuf F64, u64;                    // FP64 re-solve of FP32 problems
   DevBuf ready_at, trace, trace_n;    // diagnostic trace (EIK_TRACE)
+  DevBuf wall_in, wall_cnt;           // wall density of masked problems
   Ctl* ctl_host = nullptr;            // pinned: fine and coarse control blocks
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int cus = 0;

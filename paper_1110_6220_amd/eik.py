@@ -39,7 +39,7 @@ class Opts(ctypes.Structure):
                 ("stream", ctypes.c_void_p), ("max_cell_visits", ctypes.c_uint64),
                 ("residual_check", ctypes.c_int32), ("workers", ctypes.c_int32),
                 ("band_window", ctypes.c_int32), ("eager_publish", ctypes.c_int32),
-                ("schedule", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("timeout_ms", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -107,10 +107,10 @@ def _is_torch(x) -> bool:
 
 
 def _opts(dtype, method, cell, band, device, stream, residual_check, workers, max_cell_visits,
-          band_window=0, eager_publish=False, schedule="auto"):
+          band_window=0, eager_publish=False, schedule="auto", timeout_ms=0):
     return Opts(dtype, METHODS[method], int(cell), float(band), int(device),
                 stream, int(max_cell_visits), int(bool(residual_check)), int(workers),
-                int(band_window), int(bool(eager_publish)), SCHEDULES[schedule])
+                int(band_window), int(bool(eager_publish)), SCHEDULES[schedule], int(timeout_ms))
 
 
 def _marshal(F, h, src, q, mask, u_out, dtype):
@@ -154,12 +154,13 @@ def _stream_of(device: bool):
 
 def eik_solve(F, h, src, q=None, mask=None, u_out=None, *, dtype="f64", method="exact",
               cell=0, band=0.0, workers=0, residual_check=False, max_cell_visits=0,
-              band_window=0, eager_publish=False, schedule="auto"):
+              band_window=0, eager_publish=False, schedule="auto", timeout_ms=0):
     """Solves |grad u| F = 1 with u = q on src (see include/eik.h).
     Returns (u, stats dict)."""
     p, keep, u_out, device = _marshal(F, h, src, q, mask, u_out, dtype)
     o = _opts(F64 if dtype == "f64" else F32, method, cell, band, device, _stream_of(device),
-              residual_check, workers, max_cell_visits, band_window, eager_publish, schedule)
+              residual_check, workers, max_cell_visits, band_window, eager_publish, schedule,
+              timeout_ms)
     st = Stats()
     _check(lib.eik_solve(p.nx, p.ny, p.h, p.F, p.mask, p.nsrc, p.src, p.q, p.u_out,
                          ctypes.byref(o), ctypes.byref(st)))
@@ -169,7 +170,7 @@ def eik_solve(F, h, src, q=None, mask=None, u_out=None, *, dtype="f64", method="
 
 def eik_solve_batched(problems, *, dtype="f64", method="exact", cell=0, band=0.0, workers=0,
                       residual_check=False, max_cell_visits=0, band_window=0,
-                      eager_publish=False, schedule="auto"):
+                      eager_publish=False, schedule="auto", timeout_ms=0):
     """problems: list of dicts with F, h, src and optional q, mask, u_out.
     Returns (list of u, list of stats dicts)."""
     ps, keeps, outs = [], [], []
@@ -186,7 +187,8 @@ def eik_solve_batched(problems, *, dtype="f64", method="exact", cell=0, band=0.0
         outs.append(u)
     arr = (Problem * len(ps))(*ps)
     o = _opts(F64 if dtype == "f64" else F32, method, cell, band, device, _stream_of(device),
-              residual_check, workers, max_cell_visits, band_window, eager_publish, schedule)
+              residual_check, workers, max_cell_visits, band_window, eager_publish, schedule,
+              timeout_ms)
     st = (Stats * len(ps))()
     _check(lib.eik_solve_batched(len(ps), arr, ctypes.byref(o), st))
     del keeps

@@ -156,3 +156,17 @@ def test_fp32_within_bound(eik):
         print(f"  fp32 {w['name']}: max {err.max():.2e} L1 {err.sum() * w['h'] ** 2:.2e} "
               f"bound {bound:.2e}", flush=True)
         assert err.max() <= bound
+
+
+def test_time_limit_is_reported(eik):
+    """A solve stopped by its time limit fails with EDEVICE instead of
+    returning a partial result (the limit is forced from the host: workers
+    give up between cells, every kernel exits normally)."""
+    w = W.config(2)
+    d = to_dev(w)
+    print("[gpu] 1025^2 solve with a 1 ms limit", flush=True)
+    with pytest.raises(eik.EikError) as e:
+        eik.eik_solve(d["F"], d["h"], d["src"], d["q"], None, timeout_ms=1, cell=16)
+    assert e.value.code == eik.EIK_EDEVICE
+    got, _ = solve_dev(eik, w)  # the next solve is unaffected
+    assert max_rel(got, O.fmm(O.Problem.from_workload(w))) <= TOL64
