@@ -97,6 +97,10 @@ def tune(dtypes=("f64", "f32"), log=print):
                                                for d in ds])
                         times[cell] = t
                     best = min(times, key=times.get)
+                    if batched:
+                        # a batch's widest cell sets every wave's LDS: take
+                        # the smallest side within 3% of the fastest
+                        best = min(c for c in CANDIDATES if times[c] <= 1.03 * times[best])
                     rows.append((dt_code, batched, nmax, dense, best))
                     sides = [w["nx"] for w in ws]
                     note = (f"{dtype} batched={batched} dense={dense} n<={nmax if nmax < 1 << 30 else 'any'}"

@@ -52,10 +52,14 @@ static const char* g_trace = std::getenv("EIK_TRACE");
 
 hipError_t DevBuf::ensure(size_t need) {
   if (need <= bytes) return hipSuccess;
-  if (p) (void)hipFree(p);
+  if (p) {
+    if (graveyard) graveyard->push_back(p);
+    else (void)hipFree(p);
+  }
   p = nullptr;
+  size_t b = std::max<size_t>(need, 256);
+  if (graveyard) b = std::max(b, 2 * bytes);  // geometric growth: few outgrown buffers
   bytes = 0;
-  const size_t b = std::max<size_t>(need, 256);
   hipError_t e = hipMalloc(&p, b);
   if (e == hipSuccess) bytes = b;
   return e;
@@ -73,7 +77,22 @@ void Solver::release() {
     b->release();
 }
 
+// Makes every buffer of the workspace grow without hipFree.
+void workspace_defer_frees(Workspace* w) {
+  w->defer_free = true;
+  for (Solver* sv : {&w->fine, &w->coarse})
+    for (DevBuf* b : {&sv->delta, &sv->st, &sv->visits, &sv->cell_inst, &sv->key, &sv->deps, &sv->ord,
+                      &sv->slot, &sv->head, &sv->tail, &sv->inflight, &sv->cursor, &sv->ctl, &sv->inst})
+      b->graveyard = &w->graveyard;
+  for (DevBuf* b : {&w->F, &w->u, &w->mask, &w->src, &w->q, &w->cF, &w->cmask, &w->cq, &w->cu,
+                    &w->cout, &w->F64, &w->u64, &w->ready_at, &w->trace, &w->trace_n, &w->wall_in,
+                    &w->wall_cnt})
+    b->graveyard = &w->graveyard;
+}
+
 void workspace_free(Workspace* w) {
+  for (void* p : w->graveyard) (void)hipFree(p);
+  w->graveyard.clear();
   w->fine.release();
   w->coarse.release();
   for (DevBuf* b : {&w->F, &w->u, &w->mask, &w->src, &w->q, &w->cF, &w->cmask, &w->cq, &w->cu,
@@ -204,7 +223,7 @@ static int tuned_cell(int dtype, bool batched, int nx, int ny, double wall_densi
 
 // Wall density of host masks: the share of accessible nodes with an
 // inaccessible 4-neighbour, estimated on every fourth row.
-static double wall_density_host(const eik_problem& p) {
+double wall_density_host(const eik_problem& p) {
   if (!p.mask) return 0.0;
   uint64_t acc = 0, wall = 0;
   for (int j = 0; j < p.ny; j += 4) {
@@ -369,6 +388,10 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
     int64_t wmax = 0;
     for (int k = 0; k < n; ++k) {
       if (!probs[k].mask) continue;
+      if (ctx.density) {
+        density[k] = ctx.density[k];
+        continue;
+      }
       if (!o.device_ptrs) {
         density[k] = wall_density_host(probs[k]);
         continue;
@@ -399,11 +422,23 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
   int64_t total_nodes = 0, max_nodes = 0, max_src = 0;
   int extent = 0;
   double hs_max = 0.0;
+  // A launch sizes every wave's LDS for its widest cell: a batch keeps its
+  // cells within 32 nodes (several waves per compute unit) unless every
+  // problem asks for 64.
+  std::vector<int> cells(n);
+  bool all64 = true;
   for (int k = 0; k < n; ++k) {
     const eik_problem& p = probs[k];
-    const int s = o.cell ? o.cell
-                         : method == EIK_EXACT ? tuned_cell(dt, n > 1, p.nx, p.ny, density[k])
-                                               : default_cell(p.nx, p.ny, method);
+    cells[k] = o.cell ? o.cell
+                      : method == EIK_EXACT ? tuned_cell(dt, n > 1, p.nx, p.ny, density[k])
+                                            : default_cell(p.nx, p.ny, method);
+    all64 = all64 && cells[k] > 32;
+  }
+  if (!o.cell && method == EIK_EXACT && n > 1 && !all64)
+    for (int& c : cells) c = std::min(c, 32);
+  for (int k = 0; k < n; ++k) {
+    const eik_problem& p = probs[k];
+    const int s = cells[k];
     if ((rc = make_tiling(p.nx, p.ny, s, method, &til[k]))) return rc;
     extent = std::max(extent, til[k].extent);
     total_nodes += (int64_t)p.nx * p.ny;

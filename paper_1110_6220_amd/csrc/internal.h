@@ -23,10 +23,13 @@ double now_s();
       return ::eik::fail(EIK_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
-// A device allocation that only grows.
+// A device allocation that only grows.  With a graveyard, a buffer that
+// grows keeps its old allocation there (freed later by the owner) instead of
+// calling hipFree, which would wait for all work on the device.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  std::vector<void*>* graveyard = nullptr;
   hipError_t ensure(size_t need);
   void release();
   template <typename T>
@@ -48,6 +51,8 @@ struct Workspace {
   DevBuf F64, u64;                    // FP64 re-solve of FP32 problems
   DevBuf ready_at, trace, trace_n;    // diagnostic trace (EIK_TRACE)
   DevBuf wall_in, wall_cnt;           // wall density of masked problems
+  std::vector<void*> graveyard;       // outgrown buffers (deferred frees)
+  bool defer_free = false;            // grow without hipFree (serving lanes)
   Ctl* ctl_host = nullptr;            // pinned: fine and coarse control blocks
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int cus = 0;
@@ -71,6 +76,10 @@ int workspace(Workspace** out);
 int workspace_init(Workspace* w);
 // Frees everything a workspace holds (no work may be pending on it).
 void workspace_free(Workspace* w);
+// Makes the workspace's buffers grow without calling hipFree.
+void workspace_defer_frees(Workspace* w);
+// Share of accessible nodes next to an obstacle (host mask, sampled rows).
+double wall_density_host(const eik_problem& p);
 
 // Where a run takes its buffers from.  Defaults: the device's shared
 // workspace for everything.
@@ -80,6 +89,7 @@ struct RunCtx {
   void* const* f64 = nullptr;    // per problem: 3 x nodes doubles (F, u, delta)
                                  // for the FP64 re-solve of FP32 problems
   int share = 1;                 // the run gets 1/share of the default waves
+  const double* density = nullptr;  // per problem: wall density, if known
 };
 eik_opts default_opts();
 int check_opts(const eik_opts& o);

@@ -14,6 +14,8 @@
 
 #include <algorithm>
 #include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -34,6 +36,12 @@ constexpr size_t kAlign = 256;
 constexpr int kDefaultLanes = 4;        // one per hardware queue of the process
 constexpr int kMaxBatch = 256;          // requests per launch
 constexpr uint64_t kDefaultBudget = 64ull << 30;
+// EIK_SERVE_LOG=1: one line per launched batch on stderr (lane, requests,
+// nodes, upload / solve / download milliseconds), a diagnostic
+const bool g_serve_log = [] {
+  const char* v = std::getenv("EIK_SERVE_LOG");
+  return v && v[0] == '1';
+}();
 
 size_t up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
 
@@ -91,6 +99,7 @@ struct Req {
   std::string err;
   eik_stats st{};
   double t_submit = 0.0;
+  double density = 0.0;     // wall density (host masks; cell-side tuning)
 };
 
 // Byte offsets of a request's arrays inside its arena block.
@@ -187,6 +196,7 @@ void eik_server::lane(int id) {
 // as a whole is retried request by request, so one bad request (speeds or
 // sources checked on the device) fails alone.
 void eik_server::solve(int id, std::vector<Req*>& batch) {
+  const double t_up = now_s();
   hipStream_t st = streams[id];
   eik_opts o = cfg.opts;
   o.device_ptrs = 1;
@@ -195,6 +205,7 @@ void eik_server::solve(int id, std::vector<Req*>& batch) {
   const int n = (int)batch.size();
   std::vector<eik_problem> probs(n);
   std::vector<void*> delta(n), f64(n);
+  std::vector<double> density(n);
   int rc = EIK_OK;
   for (int k = 0; k < n && !rc; ++k) {
     Req* r = batch[k];
@@ -221,18 +232,26 @@ void eik_server::solve(int id, std::vector<Req*>& batch) {
     probs[k] = d;
     delta[k] = b + L.delta;
     f64[k] = b + L.f64;
+    density[k] = r->density;
   }
+  if (g_serve_log) (void)hipStreamSynchronize(st);
+  const double t_up1 = now_s();
   std::vector<eik_stats> stats(n);
   RunCtx ctx;
   ctx.ws = ws[id].get();
   ctx.delta = delta.data();
   ctx.f64 = f64.data();
   ctx.share = lanes;
+  if (!cfg.opts.device_ptrs) ctx.density = density.data();
   if (!rc) rc = run(n, probs.data(), o, stats.data(), nullptr, &ctx);
   if (rc && n > 1) {
     // isolate the failing request(s)
     for (int k = 0; k < n; ++k) {
-      batch[k]->rc = run(1, &probs[k], o, &stats[k], nullptr, &ctx);
+      RunCtx one = ctx;  // the request's own arena buffers
+      one.delta = &delta[k];
+      one.f64 = &f64[k];
+      one.density = ctx.density ? &density[k] : nullptr;
+      batch[k]->rc = run(1, &probs[k], o, &stats[k], nullptr, &one);
       if (batch[k]->rc) batch[k]->err = g_err;
     }
   } else {
@@ -241,6 +260,7 @@ void eik_server::solve(int id, std::vector<Req*>& batch) {
       if (rc) batch[k]->err = g_err;
     }
   }
+  const double t_solved = now_s();
   for (int k = 0; k < n; ++k) {
     Req* r = batch[k];
     if (r->rc) continue;
@@ -253,6 +273,13 @@ void eik_server::solve(int id, std::vector<Req*>& batch) {
   }
   (void)hipStreamSynchronize(st);
   const double t = now_s();
+  if (g_serve_log) {
+    double nodes = 0;
+    for (Req* r : batch) nodes += (double)r->p.nx * r->p.ny;
+    std::fprintf(stderr, "[eik serve] lane %d: %d requests, %.2f Mnodes; upload %.2f ms, solve %.2f ms "
+                 "(kernel %.2f ms), download %.2f ms\n", id, n, nodes * 1e-6, (t_up1 - t_up) * 1e3,
+                 (t_solved - t_up1) * 1e3, stats[0].kernel_seconds * 1e3, (t - t_solved) * 1e3);
+  }
   for (int k = 0; k < n; ++k) {
     Req* r = batch[k];
     r->st = stats[k];
@@ -292,6 +319,7 @@ int eik_serve_create(const eik_serve_cfg* cfg, eik_server** out) {
     }
     s->streams.push_back(st);
     s->ws.emplace_back(new Workspace());
+    workspace_defer_frees(s->ws.back().get());
     if ((rc = workspace_init(s->ws.back().get()))) {
       for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
       for (auto& w : s->ws) workspace_free(w.get());
@@ -325,6 +353,7 @@ int eik_serve_submit(eik_server* s, const eik_problem* p, uint64_t* ticket) {
     const size_t nn = (size_t)p->nx * p->ny;
     r->F.assign((const char*)p->F, (const char*)p->F + nn * dsize(o.dtype));
     if (p->mask) r->mask.assign(p->mask, p->mask + nn);
+    r->density = wall_density_host(*p);
     r->src.assign(p->src, p->src + p->nsrc);
     if (p->q) r->q.assign(p->q, p->q + p->nsrc);
   }

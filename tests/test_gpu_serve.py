@@ -87,3 +87,35 @@ def test_budget_cancel_poll(eik):
                 time.sleep(0.001)
             assert r is not None
             assert max_rel(r[0], U) <= 1e-12
+
+
+def test_device_inputs_bad_request_fails_alone(eik):
+    """Device-resident inputs are checked on the device: a batch holding one
+    request with a zero speed fails, is retried request by request (each with
+    its own buffers), and only the bad request reports EINVAL."""
+    import torch
+    dev = torch.device("cuda:0")
+    ws = [W.smooth_sine(n, 0.3) for n in (65, 257, 129, 193)]
+    bad = W.smooth_sine(97, 0.3)
+    bad["F"] = bad["F"].copy()
+    bad["F"][10, 10] = 0.0
+    order = [ws[0], bad, ws[1], ws[2], ws[3]]
+    with eik.Server(64 << 20, lanes=1, device_inputs=True) as srv:
+        # hold the lane with a first request so the rest arrive as one batch
+        print("[gpu] serve device inputs with one bad request", flush=True)
+        tickets = []
+        for w in order:
+            tickets.append(srv.submit(torch.from_numpy(w["F"]).to(dev), w["h"],
+                                      torch.from_numpy(w["src"]).to(dev),
+                                      torch.from_numpy(w["q"]).to(dev)))
+        results = []
+        for t in tickets:
+            try:
+                results.append(srv.wait(t))
+            except eik.EikError as e:
+                results.append(e)
+    assert isinstance(results[1], eik.EikError) and results[1].code == eik.EIK_EINVAL
+    for w, r in zip(order, results):
+        if w is bad:
+            continue
+        assert max_rel(r[0], O.fmm(O.Problem.from_workload(w))) <= 1e-12, w["name"]
