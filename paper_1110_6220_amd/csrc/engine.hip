@@ -864,6 +864,22 @@ __device__ void publish(const Engine& e, const Inst& I, const CellBox& B, int g,
 // persistent solver kernel
 // ----------------------------------------------------------------------------
 
+// First processing of cell g done: a later neighbour starts once all its
+// earlier neighbours are done.  One lane.
+__device__ void release_later(const Engine& e, int g, const Inst& I, const CellBox& B,
+                              uint32_t ordb) {
+  for (int side = 0; side < 4; ++side) {
+    int nb = -1;
+    if (side == 0 && B.cx > 0) nb = g - 1;
+    if (side == 1 && B.cx + 1 < I.kx) nb = g + 1;
+    if (side == 2 && B.cy > 0) nb = g - I.kx;
+    if (side == 3 && B.cy + 1 < I.ky) nb = g + I.kx;
+    if (nb < 0 || (ordb & (1u << side))) continue;  // none, or earlier
+    if (e.ord[nb] & kOrdEmpty) continue;
+    if (atomic_add_relaxed(&e.deps[nb], -1) == 1) release_first(e, nb);
+  }
+}
+
 template <typename T, int S, int M>
 __global__ __launch_bounds__(64) void k_solve(Engine e) {
   constexpr int P = S + 2;
@@ -1007,18 +1023,7 @@ __global__ __launch_bounds__(64) void k_solve(Engine e) {
       int again = 0;
       if (lane == 0) {
         if (e.dag && !done1) {
-          // first processing done: a later neighbour starts once all its
-          // earlier neighbours are done
-          for (int side = 0; side < 4; ++side) {
-            int nb = -1;
-            if (side == 0 && B.cx > 0) nb = g - 1;
-            if (side == 1 && B.cx + 1 < I.kx) nb = g + 1;
-            if (side == 2 && B.cy > 0) nb = g - I.kx;
-            if (side == 3 && B.cy + 1 < I.ky) nb = g + I.kx;
-            if (nb < 0 || (ordb & (1u << side))) continue;  // none, or earlier
-            if (e.ord[nb] & kOrdEmpty) continue;
-            if (atomic_add_relaxed(&e.deps[nb], -1) == 1) release_first(e, nb);
-          }
+          release_later(e, g, I, B, ordb);
           done1 = 1;
         }
         uint32_t exp = run_state;

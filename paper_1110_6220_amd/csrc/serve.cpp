@@ -36,6 +36,7 @@ constexpr size_t kAlign = 256;
 constexpr int kDefaultLanes = 4;        // one per hardware queue of the process
 constexpr int kMaxBatch = 256;          // requests per launch
 constexpr uint64_t kDefaultBudget = 64ull << 30;
+constexpr size_t kPinnedBytes = 1ull << 30;  // pinned staging of submitted inputs
 // EIK_SERVE_LOG=1: one line per launched batch on stderr (lane, requests,
 // nodes, upload / solve / download milliseconds), a diagnostic
 const bool g_serve_log = [] {
@@ -89,10 +90,17 @@ enum ReqState { kReqQueued, kReqRunning, kReqDone };
 struct Req {
   uint64_t ticket = 0;
   eik_problem p{};          // the caller's problem (pointers valid until admission)
-  std::vector<char> F;      // host copies (device_ptrs = 0)
+  // host copies (device_ptrs = 0): in the server's pinned arena when it has
+  // room (hoff, hbytes), else in these vectors
+  std::vector<char> F;
   std::vector<uint8_t> mask;
   std::vector<int64_t> src;
   std::vector<double> q;
+  const void* hF = nullptr;
+  const void* hmask = nullptr;
+  const void* hsrc = nullptr;
+  const void* hq = nullptr;
+  size_t hoff = 0, hbytes = 0;  // pinned block (hbytes = 0: none)
   size_t bytes = 0, off = 0;
   ReqState state = kReqQueued;
   int rc = EIK_OK;
@@ -132,6 +140,8 @@ struct eik_server {
   int dev = 0;
   char* base = nullptr;  // device arena
   Arena arena;
+  char* pinned = nullptr;  // host staging arena (page-locked)
+  Arena host_arena;
   int lanes = kDefaultLanes;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -183,6 +193,8 @@ void eik_server::lane(int id) {
       std::lock_guard<std::mutex> lk(mu);
       for (Req* r : batch) {
         arena.release(r->off, r->bytes);
+        if (r->hbytes) host_arena.release(r->hoff, r->hbytes);
+        r->hbytes = 0;
         r->state = kReqDone;
         in_flight--;
       }
@@ -214,10 +226,10 @@ void eik_server::solve(int id, std::vector<Req*>& batch) {
     char* b = base + r->off;
     const size_t nn = (size_t)p.nx * p.ny;
     const hipMemcpyKind kind = cfg.opts.device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-    const void* F = cfg.opts.device_ptrs ? p.F : (const void*)r->F.data();
-    const void* M = cfg.opts.device_ptrs ? (const void*)p.mask : (const void*)r->mask.data();
-    const void* S = cfg.opts.device_ptrs ? (const void*)p.src : (const void*)r->src.data();
-    const void* Q = cfg.opts.device_ptrs ? (const void*)p.q : (const void*)r->q.data();
+    const void* F = cfg.opts.device_ptrs ? p.F : r->hF;
+    const void* M = cfg.opts.device_ptrs ? (const void*)p.mask : r->hmask;
+    const void* S = cfg.opts.device_ptrs ? (const void*)p.src : r->hsrc;
+    const void* Q = cfg.opts.device_ptrs ? (const void*)p.q : r->hq;
     hipError_t e = hipMemcpyAsync(b + L.F, F, nn * es, kind, st);
     if (e == hipSuccess && p.mask) e = hipMemcpyAsync(b + L.mask, M, nn, kind, st);
     if (e == hipSuccess) e = hipMemcpyAsync(b + L.src, S, p.nsrc * sizeof(int64_t), kind, st);
@@ -286,6 +298,8 @@ void eik_server::solve(int id, std::vector<Req*>& batch) {
     r->st.seconds = t - r->t_submit;
     std::vector<char>().swap(r->F);
     std::vector<uint8_t>().swap(r->mask);
+    std::vector<int64_t>().swap(r->src);
+    std::vector<double>().swap(r->q);
   }
 }
 
@@ -310,11 +324,22 @@ int eik_serve_create(const eik_serve_cfg* cfg, eik_server** out) {
                 (unsigned long long)s->cfg.hbm_budget_bytes);
   s->base = static_cast<char*>(base);
   s->arena.reset(s->cfg.hbm_budget_bytes / kAlign * kAlign);
+  if (!s->cfg.opts.device_ptrs) {
+    // page-locked staging for submitted inputs; without it, pageable copies
+    const size_t pb = std::min<size_t>(kPinnedBytes, s->cfg.hbm_budget_bytes) / kAlign * kAlign;
+    void* h = nullptr;
+    if (pb && hipHostMalloc(&h, pb, hipHostMallocDefault) == hipSuccess) {
+      s->pinned = static_cast<char*>(h);
+      s->host_arena.reset(pb);
+    }
+  }
   for (int i = 0; i < s->lanes; ++i) {
     hipStream_t st = nullptr;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
       for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
+      for (auto& w : s->ws) workspace_free(w.get());
       (void)hipFree(s->base);
+      if (s->pinned) (void)hipHostFree(s->pinned);
       return fail(EIK_EDEVICE, "cannot create a stream");
     }
     s->streams.push_back(st);
@@ -324,6 +349,7 @@ int eik_serve_create(const eik_serve_cfg* cfg, eik_server** out) {
       for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
       for (auto& w : s->ws) workspace_free(w.get());
       (void)hipFree(s->base);
+      if (s->pinned) (void)hipHostFree(s->pinned);
       return rc;
     }
   }
@@ -351,11 +377,41 @@ int eik_serve_submit(eik_server* s, const eik_problem* p, uint64_t* ticket) {
                 (unsigned long long)s->cfg.hbm_budget_bytes);
   if (!o.device_ptrs) {
     const size_t nn = (size_t)p->nx * p->ny;
-    r->F.assign((const char*)p->F, (const char*)p->F + nn * dsize(o.dtype));
-    if (p->mask) r->mask.assign(p->mask, p->mask + nn);
+    const size_t bF = up(nn * dsize(o.dtype)), bM = p->mask ? up(nn) : 0;
+    const size_t bS = up(p->nsrc * sizeof(int64_t)), bQ = p->q ? up(p->nsrc * sizeof(double)) : 0;
+    size_t hoff = 0;
+    bool pin = false;
+    if (s->pinned) {
+      std::lock_guard<std::mutex> lk(s->mu);
+      pin = s->host_arena.alloc(bF + bM + bS + bQ, &hoff);
+    }
+    if (pin) {
+      char* h = s->pinned + hoff;
+      r->hoff = hoff;
+      r->hbytes = bF + bM + bS + bQ;
+      std::memcpy(h, p->F, nn * dsize(o.dtype));
+      r->hF = h;
+      if (p->mask) {
+        std::memcpy(h + bF, p->mask, nn);
+        r->hmask = h + bF;
+      }
+      std::memcpy(h + bF + bM, p->src, p->nsrc * sizeof(int64_t));
+      r->hsrc = h + bF + bM;
+      if (p->q) {
+        std::memcpy(h + bF + bM + bS, p->q, p->nsrc * sizeof(double));
+        r->hq = h + bF + bM + bS;
+      }
+    } else {
+      r->F.assign((const char*)p->F, (const char*)p->F + nn * dsize(o.dtype));
+      if (p->mask) r->mask.assign(p->mask, p->mask + nn);
+      r->src.assign(p->src, p->src + p->nsrc);
+      if (p->q) r->q.assign(p->q, p->q + p->nsrc);
+      r->hF = r->F.data();
+      r->hmask = p->mask ? r->mask.data() : nullptr;
+      r->hsrc = r->src.data();
+      r->hq = p->q ? r->q.data() : nullptr;
+    }
     r->density = wall_density_host(*p);
-    r->src.assign(p->src, p->src + p->nsrc);
-    if (p->q) r->q.assign(p->q, p->q + p->nsrc);
   }
   r->t_submit = now_s();
   {
@@ -410,6 +466,7 @@ int eik_serve_cancel(eik_server* s, uint64_t ticket) {
   auto it = s->reqs.find(ticket);
   if (it == s->reqs.end()) return fail(EIK_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
   if (it->second->state != kReqQueued) return fail(EIK_EBUSY, "request already admitted");
+  if (it->second->hbytes) s->host_arena.release(it->second->hoff, it->second->hbytes);
   s->pending.erase(std::find(s->pending.begin(), s->pending.end(), it->second.get()));
   s->reqs.erase(it);
   return EIK_OK;
@@ -427,6 +484,7 @@ int eik_serve_destroy(eik_server* s) {
   for (auto& w : s->ws) workspace_free(w.get());
   for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
   (void)hipFree(s->base);
+  if (s->pinned) (void)hipHostFree(s->pinned);
   delete s;
   return EIK_OK;
 }

@@ -80,3 +80,57 @@ def test_serving_arguments_are_checked_before_device_work():
     assert L.eik_serve_wait(None, 1, ctypes.byref(st)) == eik.EIK_EINVAL
     assert L.eik_serve_cancel(None, 1) == eik.EIK_EINVAL
     assert L.eik_serve_destroy(None) == eik.EIK_EINVAL
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of eik_opts, eik_stats, eik_problem and
+    eik_serve_cfg have the sizes and field offsets the C header gives them
+    (compiled with the host compiler; no device needed)."""
+    import subprocess
+    from paper_1110_6220_amd import eik
+    structs = {"eik_opts": eik.Opts, "eik_stats": eik.Stats, "eik_problem": eik.Problem,
+               "eik_serve_cfg": eik.ServeCfg}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "eik.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(c)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_tuned_cell_table_covers_every_class():
+    """Every (precision, batch, wall class) has a catch-all row, so the
+    lookup always finds a cell side, and every side is a valid tile."""
+    text = open(os.path.join(ROOT, "paper_1110_6220_amd", "csrc", "tuned_cells.h")).read()
+    rows = re.findall(r"\{(\d), (\d), ([0-9 <]+), (\d), (\d+)\},", text)
+    assert rows
+    seen = set()
+    for dt, batched, nmax, dense, cell in rows:
+        assert int(cell) in (8, 16, 32, 64)
+        if nmax.strip() == "1 << 30":
+            seen.add((dt, batched, dense))
+    assert seen == {(a, b, c) for a in "01" for b in "01" for c in "01"}
+
+
+def test_negative_timeout_rejected():
+    import numpy as np
+    from paper_1110_6220_amd import eik
+    u = np.full((4, 4), 7.0)
+    try:
+        eik.eik_solve(np.ones((4, 4)), 0.1, [0], u_out=u, timeout_ms=-1)
+    except eik.EikError as e:
+        assert e.code == eik.EIK_EINVAL
+    else:
+        raise AssertionError("negative timeout accepted")
+    assert (u == 7.0).all()
