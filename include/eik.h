@@ -89,6 +89,13 @@ typedef struct {
   int32_t schedule;         /* eik_schedule                                     */
   int32_t timeout_ms;       /* time limit of one solve on the device; 0 = 10000.
                                A solve that exceeds it fails with EDEVICE.     */
+  int32_t graph;            /* 1 (device_ptrs only): capture the call's launch
+                               sequence into a HIP graph and replay it when the
+                               same problem set (sizes, spacing, buffer
+                               addresses, options) comes again; the buffers'
+                               contents may change between calls.  Up to 8
+                               graphs are kept per device and dropped when the
+                               library's workspace has to grow.              */
 } eik_opts;
 
 typedef struct {
@@ -109,6 +116,7 @@ typedef struct {
   int32_t fell_back_to_f64; /* F32 residual check failed and FP64 re-solved     */
   uint64_t cells_total;     /* cells of the whole launch (batches: all problems;
                                visit and sweep counters are launch totals)      */
+  int32_t graph_replayed;   /* 1: this call replayed a captured graph          */
 } eik_stats;
 
 /* Solve one problem.

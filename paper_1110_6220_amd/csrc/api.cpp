@@ -56,6 +56,7 @@ hipError_t DevBuf::ensure(size_t need) {
     if (graveyard) graveyard->push_back(p);
     else (void)hipFree(p);
   }
+  if (gen) ++*gen;
   p = nullptr;
   size_t b = std::max<size_t>(need, 256);
   if (graveyard) b = std::max(b, 2 * bytes);  // geometric growth: few outgrown buffers
@@ -77,28 +78,42 @@ void Solver::release() {
     b->release();
 }
 
-// Makes every buffer of the workspace grow without hipFree.
-void workspace_defer_frees(Workspace* w) {
-  w->defer_free = true;
+static std::vector<DevBuf*> all_bufs(Workspace* w) {
+  std::vector<DevBuf*> v;
   for (Solver* sv : {&w->fine, &w->coarse})
     for (DevBuf* b : {&sv->delta, &sv->st, &sv->visits, &sv->cell_inst, &sv->key, &sv->deps, &sv->ord,
                       &sv->slot, &sv->head, &sv->tail, &sv->inflight, &sv->cursor, &sv->ctl, &sv->inst})
-      b->graveyard = &w->graveyard;
+      v.push_back(b);
   for (DevBuf* b : {&w->F, &w->u, &w->mask, &w->src, &w->q, &w->cF, &w->cmask, &w->cq, &w->cu,
                     &w->cout, &w->F64, &w->u64, &w->ready_at, &w->trace, &w->trace_n, &w->wall_in,
                     &w->wall_cnt})
-    b->graveyard = &w->graveyard;
+    v.push_back(b);
+  return v;
+}
+
+// Makes every buffer of the workspace grow without hipFree.
+void workspace_defer_frees(Workspace* w) {
+  w->defer_free = true;
+  for (DevBuf* b : all_bufs(w)) b->graveyard = &w->graveyard;
+}
+
+static void drop_plan(Plan* pl) {
+  if (pl->pre) (void)hipGraphExecDestroy(pl->pre);
+  if (pl->post) (void)hipGraphExecDestroy(pl->post);
+  pl->pre = pl->post = nullptr;
+  pl->inst.release();
+  pl->cinst.release();
+  pl->cout.release();
 }
 
 void workspace_free(Workspace* w) {
+  for (auto& pl : w->plans) drop_plan(pl.get());
+  w->plans.clear();
+  if (w->capture) (void)hipStreamDestroy(w->capture);
+  w->capture = nullptr;
   for (void* p : w->graveyard) (void)hipFree(p);
   w->graveyard.clear();
-  w->fine.release();
-  w->coarse.release();
-  for (DevBuf* b : {&w->F, &w->u, &w->mask, &w->src, &w->q, &w->cF, &w->cmask, &w->cq, &w->cu,
-                    &w->cout, &w->F64, &w->u64, &w->ready_at, &w->trace, &w->trace_n, &w->wall_in,
-                    &w->wall_cnt})
-    b->release();
+  for (DevBuf* b : all_bufs(w)) b->release();
   if (w->ctl_host) (void)hipHostFree(w->ctl_host);
   if (w->ev0) (void)hipEventDestroy(w->ev0);
   if (w->ev1) (void)hipEventDestroy(w->ev1);
@@ -112,6 +127,7 @@ static std::vector<std::unique_ptr<Workspace>> g_ws;
 
 int workspace_init(Workspace* w) {
   if (w->ready) return EIK_OK;
+  for (DevBuf* b : all_bufs(w)) b->gen = &w->gen;
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   HIP_TRY(hipHostMalloc((void**)&w->ctl_host, 2 * sizeof(Ctl), hipHostMallocDefault));
@@ -282,7 +298,8 @@ int validate_shape(const eik_problem& p) {
 // here) and fills the engine arguments.
 static int setup_engine(Solver& sv, std::vector<Inst>& inst, int dtype, int method, int dag,
                         double band, int window, int eager, uint64_t guard, uint64_t timeout,
-                        hipStream_t stream, Engine* out) {
+                        hipStream_t stream, Engine* out, DevBuf* instbuf = nullptr) {
+  DevBuf& ib = instbuf ? *instbuf : sv.inst;
   int64_t J = 0;
   for (auto& I : inst) {
     I.cell0 = (int32_t)J;
@@ -304,11 +321,11 @@ static int setup_engine(Solver& sv, std::vector<Inst>& inst, int dtype, int meth
   HIP_TRY(sv.inflight.ensure((size_t)nb * kCtrStride * sizeof(unsigned long long)));
   HIP_TRY(sv.cursor.ensure(128));
   HIP_TRY(sv.ctl.ensure(sizeof(Ctl)));
-  HIP_TRY(sv.inst.ensure(n * sizeof(Inst)));
-  HIP_TRY(hipMemcpyAsync(sv.inst.p, inst.data(), n * sizeof(Inst), hipMemcpyHostToDevice, stream));
+  HIP_TRY(ib.ensure(n * sizeof(Inst)));
+  HIP_TRY(hipMemcpyAsync(ib.p, inst.data(), n * sizeof(Inst), hipMemcpyHostToDevice, stream));
   Engine& e = *out;
   std::memset(&e, 0, sizeof e);
-  e.inst = sv.inst.as<Inst>();
+  e.inst = ib.as<Inst>();
   e.one = inst[0];
   e.args_inst = n == 1;
   e.ninst = n;
@@ -362,6 +379,46 @@ static int default_workers(const Workspace* ws, int64_t J, int tile, int dtype, 
 // the solve driver shared by eik_solve, eik_solve_batched and the server
 // ---------------------------------------------------------------------------
 
+constexpr unsigned kTraceCap = 1u << 20;  // trace records (EIK_TRACE)
+constexpr size_t kMaxPlans = 8;           // captured graphs kept per workspace
+
+static int complete(Workspace* ws, int n, const eik_problem* probs, const eik_opts& o,
+                    const RunCtx& ctx, const std::vector<Inst>& inst, int64_t J, double band,
+                    bool have_coarse, bool want_resid, hipStream_t stream, double t0,
+                    eik_stats* stats, RunInfo* info, std::unique_lock<std::mutex>& lk,
+                    bool replayed);
+
+// Identity of a problem set for graph replay: every input that shapes the
+// launch sequence (sizes, spacing, buffer addresses, options).  The contents
+// of the buffers may change between replays.
+static uint64_t plan_key(int n, const eik_problem* probs, const eik_opts& o, const RunCtx& ctx) {
+  uint64_t hsh = 1469598103934665603ull;
+  auto mix = [&](const void* p, size_t b) {
+    const unsigned char* c = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < b; ++i) hsh = (hsh ^ c[i]) * 1099511628211ull;
+  };
+  mix(&n, sizeof n);
+  for (int k = 0; k < n; ++k) {
+    const eik_problem& p = probs[k];
+    mix(&p.nx, sizeof p.nx);
+    mix(&p.ny, sizeof p.ny);
+    mix(&p.h, sizeof p.h);
+    mix(&p.F, sizeof p.F);
+    mix(&p.mask, sizeof p.mask);
+    mix(&p.nsrc, sizeof p.nsrc);
+    mix(&p.src, sizeof p.src);
+    mix(&p.q, sizeof p.q);
+    mix(&p.u_out, sizeof p.u_out);
+    if (ctx.delta) mix(&ctx.delta[k], sizeof(void*));
+  }
+  for (const int32_t v : {(int32_t)o.dtype, (int32_t)o.method, o.cell, o.workers, o.band_window,
+                          o.eager_publish, o.schedule, o.residual_check, o.timeout_ms, ctx.share})
+    mix(&v, sizeof v);
+  mix(&o.band, sizeof o.band);
+  mix(&o.max_cell_visits, sizeof o.max_cell_visits);
+  return hsh;
+}
+
 int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, RunInfo* info,
         const RunCtx* ctx_in) {
   const double t0 = now_s();
@@ -378,6 +435,34 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
   int sched = o.schedule;
   if (sched == EIK_SCHED_AUTO) sched = method == EIK_FHCM ? EIK_SCHED_BANDS : EIK_SCHED_COARSE;
   const bool dag = sched == EIK_SCHED_COARSE;
+  const bool dev = o.device_ptrs != 0;
+  const bool want_resid = o.residual_check != 0;
+
+  // graph replay: a problem set seen before (same buffers, sizes and options)
+  // runs its captured launch sequence
+  const bool use_graph = o.graph && dev && !g_trace && !g_profile;
+  const uint64_t key = use_graph ? plan_key(n, probs, o, ctx) : 0;
+  ws->uses++;
+  if (use_graph) {
+    for (size_t x = 0; x < ws->plans.size(); ++x) {  // drop graphs of moved buffers
+      if (ws->plans[x]->gen == ws->gen) continue;
+      drop_plan(ws->plans[x].get());
+      ws->plans.erase(ws->plans.begin() + x--);
+    }
+    for (auto& pl : ws->plans) {
+      if (pl->key != key) continue;
+      pl->last_use = ws->uses;
+      HIP_TRY(hipGraphLaunch(pl->pre, stream));
+      HIP_TRY(hipEventRecord(ws->ev0, stream));
+      HIP_TRY(launch_solve(pl->e, pl->workers, pl->tile, stream));
+      HIP_TRY(hipEventRecord(ws->ev1, stream));
+      HIP_TRY(hipGraphLaunch(pl->post, stream));
+      HIP_TRY(hipStreamSynchronize(stream));
+      return complete(ws, n, probs, o, ctx, pl->host_inst, pl->J, pl->band, pl->have_coarse,
+                      pl->want_resid, stream, t0, stats, info, lk, true);
+    }
+  }
+  std::unique_ptr<Plan> np(use_graph ? new Plan() : nullptr);
 
   // cell side per instance: the caller's, else (exact method) the tuned
   // table, keyed by the wall density of masked problems
@@ -448,7 +533,6 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
   }
 
   // staging of host inputs
-  const bool dev = o.device_ptrs != 0;
   if (!dev) {
     int64_t nmask = 0, nsrc = 0;
     for (int k = 0; k < n; ++k) {
@@ -508,7 +592,7 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
   const uint64_t timeout = (uint64_t)ws->wall_khz * (uint64_t)(o.timeout_ms ? o.timeout_ms : 10000);
   Engine e;
   if ((rc = setup_engine(ws->fine, inst, dt, method, dag, band, o.band_window, o.eager_publish,
-                         o.max_cell_visits, timeout, stream, &e)))
+                         o.max_cell_visits, timeout, stream, &e, np ? &np->inst : nullptr)))
     return rc;
   const int64_t J = e.ncells;
   const int tile = tile_for(extent);
@@ -516,21 +600,20 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
   const int workers =
       o.workers ? o.workers : std::max(1, default_workers(ws, J, tile, dt, method, n) / std::max(1, ctx.share));
 
-  const unsigned trace_cap = 1u << 20;
   if (g_trace) {
     HIP_TRY(ws->ready_at.ensure(J * 8));
-    HIP_TRY(ws->trace.ensure((size_t)trace_cap * 64));
+    HIP_TRY(ws->trace.ensure((size_t)kTraceCap * 64));
     HIP_TRY(ws->trace_n.ensure(4));
     HIP_TRY(hipMemsetAsync(ws->trace_n.p, 0, 4, stream));
     HIP_TRY(hipMemsetAsync(ws->ready_at.p, 0, J * 8, stream));
     e.ready_at = ws->ready_at.as<unsigned long long>();
     e.trace = ws->trace.as<unsigned long long>();
     e.trace_n = ws->trace_n.as<unsigned int>();
-    e.trace_cap = trace_cap;
+    e.trace_cap = kTraceCap;
   }
-  HIP_TRY(launch_prepare(e, max_nodes, stream));
   Engine ce;
   bool have_coarse = false;
+  int cext = 0;
   if (dag) {
     // FMSM Part I on every instance: coarse speeds, exit cells, and an exact
     // solve on the grid of cell centres with spacing h^c = s h
@@ -539,10 +622,10 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
     HIP_TRY(ws->cq.ensure(J * sizeof(double)));
     HIP_TRY(ws->cu.ensure(J * sizeof(double)));
     HIP_TRY(ws->coarse.delta.ensure(J * sizeof(double)));
-    HIP_TRY(ws->cout.ensure(n * sizeof(CoarseOut)));
+    DevBuf& coutbuf = np ? np->cout : ws->cout;
+    HIP_TRY(coutbuf.ensure(n * sizeof(CoarseOut)));
     std::vector<CoarseOut> co(n);
     std::vector<Inst> cinst(n);
-    int cext = 0;
     for (int k = 0; k < n; ++k) {
       const int64_t c0 = inst[k].cell0;
       co[k].F = ws->cF.as<double>() + c0;
@@ -567,26 +650,115 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
       C.balanced = ct.balanced;
       cext = std::max(cext, ct.extent);
     }
-    HIP_TRY(hipMemcpyAsync(ws->cout.p, co.data(), n * sizeof(CoarseOut), hipMemcpyHostToDevice, stream));
-    HIP_TRY(launch_coarse_inputs(e, ws->cout.as<CoarseOut>(), (int)max_src, stream));
-    if ((rc = setup_engine(ws->coarse, cinst, EIK_F64, EIK_EXACT, 0, -1.0, 0, 0, 0, timeout, stream, &ce)))
+    HIP_TRY(hipMemcpyAsync(coutbuf.p, co.data(), n * sizeof(CoarseOut), hipMemcpyHostToDevice, stream));
+    if ((rc = setup_engine(ws->coarse, cinst, EIK_F64, EIK_EXACT, 0, -1.0, 0, 0, 0, timeout, stream, &ce,
+                           np ? &np->cinst : nullptr)))
       return rc;
-    HIP_TRY(launch_prepare(ce, J, stream));
-    const int cw = std::max(1, default_workers(ws, ce.ncells, tile_for(cext), EIK_F64, EIK_EXACT, n) /
-                                   std::max(1, ctx.share));
-    HIP_TRY(launch_solve(ce, cw, tile_for(cext), stream));
-    HIP_TRY(launch_dag(e, ws->cout.as<CoarseOut>(), (int)J, stream));
     have_coarse = true;
   }
-  HIP_TRY(hipEventRecord(ws->ev0, stream));
-  HIP_TRY(launch_solve(e, workers, tile, stream));
-  HIP_TRY(hipEventRecord(ws->ev1, stream));
-  const bool want_resid = o.residual_check != 0;
-  if (want_resid) HIP_TRY(launch_residual(e, max_nodes, stream));
-  HIP_TRY(hipMemcpyAsync(ws->ctl_host, e.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
-  if (have_coarse)
-    HIP_TRY(hipMemcpyAsync(ws->ctl_host + 1, ce.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+  const CoarseOut* co_dev = have_coarse ? (np ? np->cout : ws->cout).as<CoarseOut>() : nullptr;
+
+  const int cw = have_coarse ? std::max(1, default_workers(ws, ce.ncells, tile_for(cext), EIK_F64,
+                                                          EIK_EXACT, n) / std::max(1, ctx.share))
+                            : 1;
+
+  // The launch sequence: preparation (a1), coarse solve and ordering (a5),
+  // the solver kernel between two timing events, residual and statistics
+  // copy (a6).  With graph replay the parts before and after the solver
+  // kernel are captured (on a private stream) into two graphs.
+  const char* failed_step = "";
+  hipError_t er = hipSuccess;
+  auto step = [&](const char* what, hipError_t r) {
+    if (er == hipSuccess && r != hipSuccess) {
+      er = r;
+      failed_step = what;
+    }
+  };
+  auto pre = [&](hipStream_t ls) {
+    step("prepare", launch_prepare(e, max_nodes, ls));
+    if (have_coarse) {
+      step("coarse inputs", launch_coarse_inputs(e, co_dev, (int)max_src, ls));
+      step("coarse prepare", launch_prepare(ce, J, ls));
+      step("coarse solve", launch_solve(ce, cw, tile_for(cext), ls));
+      step("order", launch_dag(e, co_dev, (int)J, ls));
+    }
+  };
+  auto post = [&](hipStream_t ls) {
+    if (want_resid) step("residual", launch_residual(e, max_nodes, ls));
+    step("statistics copy", hipMemcpyAsync(ws->ctl_host, e.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ls));
+    if (have_coarse)
+      step("coarse statistics copy",
+           hipMemcpyAsync(ws->ctl_host + 1, ce.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ls));
+  };
+  auto capture = [&](auto&& body, hipGraphExec_t* exec) -> int {
+    HIP_TRY(hipStreamBeginCapture(ws->capture, hipStreamCaptureModeThreadLocal));
+    body(ws->capture);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(ws->capture, &graph);
+    if (er != hipSuccess || ec != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return fail(EIK_EDEVICE, "graph capture failed (%s): %s", er != hipSuccess ? failed_step : "end",
+                  hipGetErrorString(er != hipSuccess ? er : ec));
+    }
+    const hipError_t ei = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return fail(EIK_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(ei));
+    return EIK_OK;
+  };
+  if (np) {
+    if (!ws->capture) HIP_TRY(hipStreamCreateWithFlags(&ws->capture, hipStreamNonBlocking));
+    if ((rc = capture(pre, &np->pre)) || (rc = capture(post, &np->post))) {
+      drop_plan(np.get());
+      return rc;
+    }
+    HIP_TRY(hipGraphLaunch(np->pre, stream));
+  } else {
+    pre(stream);
+  }
+  step("event 0", hipEventRecord(ws->ev0, stream));
+  step("solve", launch_solve(e, workers, tile, stream));
+  step("event 1", hipEventRecord(ws->ev1, stream));
+  if (np) HIP_TRY(hipGraphLaunch(np->post, stream));
+  else post(stream);
+  if (er != hipSuccess) return fail(EIK_EDEVICE, "launch failed (%s): %s", failed_step, hipGetErrorString(er));
+  if (np) {
+    np->e = e;
+    np->workers = workers;
+    np->tile = tile;
+    np->key = key;
+    np->gen = ws->gen;
+    np->last_use = ws->uses;
+    np->host_inst = inst;
+    np->J = J;
+    np->band = band;
+    np->have_coarse = have_coarse;
+    np->want_resid = want_resid;
+    if (ws->plans.size() >= kMaxPlans) {
+      auto lru = std::min_element(ws->plans.begin(), ws->plans.end(),
+                                  [](const std::unique_ptr<Plan>& a, const std::unique_ptr<Plan>& b) {
+                                    return a->last_use < b->last_use;
+                                  });
+      drop_plan(lru->get());
+      ws->plans.erase(lru);
+    }
+    ws->plans.push_back(std::move(np));
+  }
   HIP_TRY(hipStreamSynchronize(stream));
+  return complete(ws, n, probs, o, ctx, inst, J, band, have_coarse, want_resid, stream, t0, stats,
+                  info, lk, false);
+}
+
+// After the solve's stream has completed: errors, FP32 certification, copies
+// to host outputs, diagnostics and statistics.
+static int complete(Workspace* ws, int n, const eik_problem* probs, const eik_opts& o,
+                    const RunCtx& ctx, const std::vector<Inst>& inst, int64_t J, double band,
+                    bool have_coarse, bool want_resid, hipStream_t stream, double t0,
+                    eik_stats* stats, RunInfo* info, std::unique_lock<std::mutex>& lk,
+                    bool replayed) {
+  const int dt = o.dtype;
+  const size_t es = dsize(dt);
+  const bool dev = o.device_ptrs != 0;
+  int rc = EIK_OK;
   const Ctl c = ws->ctl_host[0];
   const unsigned err = c.err | (have_coarse ? ws->ctl_host[1].err : 0u);
   if (err & (kErrSpeed | kErrSource))
@@ -627,7 +799,7 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
   if (g_trace) {
     unsigned cnt = 0;
     HIP_TRY(hipMemcpy(&cnt, ws->trace_n.p, 4, hipMemcpyDeviceToHost));
-    cnt = std::min(cnt, trace_cap);
+    cnt = std::min(cnt, kTraceCap);
     std::vector<unsigned long long> t((size_t)cnt * 8);
     HIP_TRY(hipMemcpy(t.data(), ws->trace.p, t.size() * 8, hipMemcpyDeviceToHost));
     if (FILE* f = std::fopen(g_trace, "w")) {
@@ -661,6 +833,7 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
       S.band_used = band;
       S.fell_back_to_f64 = fell_back;
       S.cells_total = (uint64_t)J;
+      S.graph_replayed = replayed ? 1 : 0;
     }
   }
   return EIK_OK;
@@ -705,6 +878,7 @@ int refine_fp64(int n, const eik_problem* probs, const std::vector<Inst>& inst, 
   o64.dtype = EIK_F64;
   o64.device_ptrs = 1;
   o64.residual_check = 0;
+  o64.graph = 0;
   RunCtx c64;
   c64.ws = ws;
   c64.delta = ctx.f64 ? d64.data() : nullptr;

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -30,6 +31,7 @@ struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
   std::vector<void*>* graveyard = nullptr;
+  uint64_t* gen = nullptr;  // bumped when the buffer moves (captured graphs go stale)
   hipError_t ensure(size_t need);
   void release();
   template <typename T>
@@ -42,6 +44,23 @@ struct Solver {
   void release();
 };
 
+// A captured launch sequence of one problem set (graph replay): the graph
+// and what the host needs after a replay.  Problem descriptors live in
+// buffers of the plan; all other buffers it uses belong to the workspace and
+// are re-initialised by the graph's own kernels on every replay.
+struct Plan {
+  uint64_t key = 0, gen = 0, last_use = 0;
+  hipGraphExec_t pre = nullptr;   // preparation, coarse solve, ordering
+  hipGraphExec_t post = nullptr;  // residual, statistics copy
+  Engine e{};                     // the solver kernel's arguments ...
+  int workers = 0, tile = 0;      // ... and launch shape (launched between events)
+  DevBuf inst, cinst, cout;
+  std::vector<Inst> host_inst;
+  int64_t J = 0;
+  double band = -1.0;
+  bool have_coarse = false, want_resid = false;
+};
+
 // Per-device workspace, reused by every call on that device.
 struct Workspace {
   std::mutex mu;
@@ -52,6 +71,10 @@ struct Workspace {
   DevBuf ready_at, trace, trace_n;    // diagnostic trace (EIK_TRACE)
   DevBuf wall_in, wall_cnt;           // wall density of masked problems
   std::vector<void*> graveyard;       // outgrown buffers (deferred frees)
+  uint64_t gen = 1;                   // changes whenever a buffer moves
+  std::vector<std::unique_ptr<Plan>> plans;  // captured graphs (eik_opts.graph)
+  hipStream_t capture = nullptr;      // private stream for graph capture
+  uint64_t uses = 0;
   bool defer_free = false;            // grow without hipFree (serving lanes)
   Ctl* ctl_host = nullptr;            // pinned: fine and coarse control blocks
   hipEvent_t ev0 = nullptr, ev1 = nullptr;

@@ -39,7 +39,8 @@ class Opts(ctypes.Structure):
                 ("stream", ctypes.c_void_p), ("max_cell_visits", ctypes.c_uint64),
                 ("residual_check", ctypes.c_int32), ("workers", ctypes.c_int32),
                 ("band_window", ctypes.c_int32), ("eager_publish", ctypes.c_int32),
-                ("schedule", ctypes.c_int32), ("timeout_ms", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("timeout_ms", ctypes.c_int32),
+                ("graph", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -49,7 +50,8 @@ class Stats(ctypes.Structure):
                 ("band_steps", ctypes.c_uint64), ("mon_checks", ctypes.c_uint64),
                 ("mon_ok", ctypes.c_uint64), ("max_residual", ctypes.c_double),
                 ("cell_used", ctypes.c_int32), ("band_used", ctypes.c_double),
-                ("fell_back_to_f64", ctypes.c_int32), ("cells_total", ctypes.c_uint64)]
+                ("fell_back_to_f64", ctypes.c_int32), ("cells_total", ctypes.c_uint64),
+                ("graph_replayed", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -107,10 +109,11 @@ def _is_torch(x) -> bool:
 
 
 def _opts(dtype, method, cell, band, device, stream, residual_check, workers, max_cell_visits,
-          band_window=0, eager_publish=False, schedule="auto", timeout_ms=0):
+          band_window=0, eager_publish=False, schedule="auto", timeout_ms=0, graph=False):
     return Opts(dtype, METHODS[method], int(cell), float(band), int(device),
                 stream, int(max_cell_visits), int(bool(residual_check)), int(workers),
-                int(band_window), int(bool(eager_publish)), SCHEDULES[schedule], int(timeout_ms))
+                int(band_window), int(bool(eager_publish)), SCHEDULES[schedule], int(timeout_ms),
+                int(bool(graph)))
 
 
 def _marshal(F, h, src, q, mask, u_out, dtype):
@@ -154,13 +157,13 @@ def _stream_of(device: bool):
 
 def eik_solve(F, h, src, q=None, mask=None, u_out=None, *, dtype="f64", method="exact",
               cell=0, band=0.0, workers=0, residual_check=False, max_cell_visits=0,
-              band_window=0, eager_publish=False, schedule="auto", timeout_ms=0):
+              band_window=0, eager_publish=False, schedule="auto", timeout_ms=0, graph=False):
     """Solves |grad u| F = 1 with u = q on src (see include/eik.h).
     Returns (u, stats dict)."""
     p, keep, u_out, device = _marshal(F, h, src, q, mask, u_out, dtype)
     o = _opts(F64 if dtype == "f64" else F32, method, cell, band, device, _stream_of(device),
               residual_check, workers, max_cell_visits, band_window, eager_publish, schedule,
-              timeout_ms)
+              timeout_ms, graph)
     st = Stats()
     _check(lib.eik_solve(p.nx, p.ny, p.h, p.F, p.mask, p.nsrc, p.src, p.q, p.u_out,
                          ctypes.byref(o), ctypes.byref(st)))
@@ -170,7 +173,7 @@ def eik_solve(F, h, src, q=None, mask=None, u_out=None, *, dtype="f64", method="
 
 def eik_solve_batched(problems, *, dtype="f64", method="exact", cell=0, band=0.0, workers=0,
                       residual_check=False, max_cell_visits=0, band_window=0,
-                      eager_publish=False, schedule="auto", timeout_ms=0):
+                      eager_publish=False, schedule="auto", timeout_ms=0, graph=False):
     """problems: list of dicts with F, h, src and optional q, mask, u_out.
     Returns (list of u, list of stats dicts)."""
     ps, keeps, outs = [], [], []
@@ -188,7 +191,7 @@ def eik_solve_batched(problems, *, dtype="f64", method="exact", cell=0, band=0.0
     arr = (Problem * len(ps))(*ps)
     o = _opts(F64 if dtype == "f64" else F32, method, cell, band, device, _stream_of(device),
               residual_check, workers, max_cell_visits, band_window, eager_publish, schedule,
-              timeout_ms)
+              timeout_ms, graph)
     st = (Stats * len(ps))()
     _check(lib.eik_solve_batched(len(ps), arr, ctypes.byref(o), st))
     del keeps
