@@ -1150,7 +1150,7 @@ __global__ void k_prep_cells(Engine e) {
 // delta = h/F on accessible nodes (validating F), +inf on obstacles.
 template <typename T>
 __global__ void k_prep_nodes(Engine e) {
-  const Inst& I = inst_at(e, blockIdx.y);
+  const Inst I = inst_at(e, blockIdx.y);
   const size_t n = (size_t)I.nx * I.ny;
   const T* F = static_cast<const T*>(I.F);
   const double* Fd = static_cast<const double*>(I.F);
@@ -1173,7 +1173,7 @@ __global__ void k_prep_nodes(Engine e) {
 
 // Source validation (index range, accessibility, finite q).
 __global__ void k_check_sources(Engine e) {
-  const Inst& I = inst_at(e, blockIdx.y);
+  const Inst I = inst_at(e, blockIdx.y);
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < I.nsrc; s += gridDim.x * blockDim.x) {
     const long long k = I.src[s];
     const double q = I.q ? I.q[s] : 0.0;
@@ -1199,7 +1199,7 @@ __device__ __forceinline__ int cell_of_node(const Inst& I, int i, int j) {
 template <typename T>
 __global__ void k_init_u(Engine e) {
   if (get_err(e.ctl)) return;
-  const Inst& I = inst_at(e, blockIdx.y);
+  const Inst I = inst_at(e, blockIdx.y);
   const size_t n = (size_t)I.nx * I.ny;
   T* u = static_cast<T*>(I.u);
   T* dl = static_cast<T*>(I.delta);
@@ -1248,7 +1248,7 @@ __device__ __forceinline__ void atomic_min_val(float* p, float v) {
 template <typename T>
 __global__ void k_apply_sources(Engine e) {
   if (get_err(e.ctl)) return;
-  const Inst& I = inst_at(e, blockIdx.y);
+  const Inst I = inst_at(e, blockIdx.y);
   if (I.qdense) return;
   T* u = static_cast<T*>(I.u);
   T* dl = static_cast<T*>(I.delta);
@@ -1277,13 +1277,13 @@ __global__ __launch_bounds__(64) void k_coarse_cells(Engine e, const CoarseOut* 
   const int lane = threadIdx.x;
   for (int g = blockIdx.x; g < e.ncells; g += gridDim.x) {
     const int k = inst_index(e, g);
-    const Inst& I = inst_at(e, k);
+    const Inst I = inst_at(e, k);
     const CellBox B = cell_box(I, g - I.cell0);
     const T* F = static_cast<const T*>(I.F);
     double col = 0.0;
     int cnt = 0;
     if (lane < B.w) {
-#pragma unroll 8
+#pragma unroll 16
       for (int j = B.y0; j < B.y1; ++j) {
         const size_t n = (size_t)j * I.nx + B.x0 + lane;
         const bool acc = !I.mask || I.mask[n];
@@ -1315,7 +1315,7 @@ __global__ __launch_bounds__(64) void k_coarse_cells(Engine e, const CoarseOut* 
 
 __global__ void k_coarse_sources(Engine e, const CoarseOut* co) {
   const int k = blockIdx.y;
-  const Inst& I = inst_at(e, k);
+  const Inst I = inst_at(e, k);
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < I.nsrc; s += gridDim.x * blockDim.x) {
     const long long n = I.src[s];
     const double q = I.q ? I.q[s] : 0.0;
@@ -1331,7 +1331,7 @@ __global__ void k_coarse_sources(Engine e, const CoarseOut* co) {
 __global__ void k_dag(Engine e, const CoarseOut* co) {
   for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < e.ncells; g += gridDim.x * blockDim.x) {
     const int k = inst_index(e, g);
-    const Inst& I = inst_at(e, k);
+    const Inst I = inst_at(e, k);
     const CoarseOut C = co[k];
     const int c = g - I.cell0;
     if (!C.mask[c]) {
@@ -1383,7 +1383,7 @@ __global__ void k_dag_roots(Engine e) {
 // non-exit nodes with finite u (inf where u is inf but T(u) is finite).
 template <typename T>
 __global__ void k_residual(Engine e) {
-  const Inst& I = inst_at(e, blockIdx.y);
+  const Inst I = inst_at(e, blockIdx.y);
   const T* u = static_cast<const T*>(I.u);
   const T* F = static_cast<const T*>(I.F);
   const T* dl = static_cast<const T*>(I.delta);

@@ -120,13 +120,22 @@ def _marshal(F, h, src, q, mask, u_out, dtype):
     """Returns (Problem, keepalive, u_out, device, dtype code)."""
     if _is_torch(F):
         import torch
-        dev = F.device
         tdt = torch.float64 if dtype == "f64" else torch.float32
-        F = F.to(tdt).contiguous()
-        srct = torch.as_tensor(np.asarray(src, dtype=np.int64).ravel() if not _is_torch(src) else src,
-                               device=dev).to(torch.int64).contiguous()
-        qt = None if q is None else torch.as_tensor(q, device=dev).to(torch.float64).contiguous()
-        mt = None if mask is None else torch.as_tensor(mask, device=dev).to(torch.uint8).contiguous()
+        if F.dtype != tdt or not F.is_contiguous():
+            F = F.to(tdt).contiguous()
+        dev = F.device
+
+        def as_dev(x, dt):
+            # tensors already in place are used as they are
+            if _is_torch(x) and x.dtype == dt and x.device == dev and x.is_contiguous():
+                return x
+            if not _is_torch(x):
+                x = np.asarray(x)
+            return torch.as_tensor(x, device=dev).to(dt).contiguous()
+
+        srct = as_dev(src if _is_torch(src) else np.asarray(src, dtype=np.int64).ravel(), torch.int64)
+        qt = None if q is None else as_dev(q, torch.float64)
+        mt = None if mask is None else as_dev(mask, torch.uint8)
         if u_out is None:
             u_out = torch.empty_like(F)
         ny, nx = F.shape
@@ -263,3 +272,42 @@ class Server:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Batch:
+    """A batch marshalled once and solved repeatedly (eik_solve_batched);
+    with graph=True the library replays the batch's captured launch sequence
+    from the second solve on.  problems: dicts with F, h, src and optional q,
+    mask, u_out (device tensors, or numpy arrays for host problems)."""
+
+    def __init__(self, problems, *, dtype="f64", method="exact", cell=0, band=0.0, workers=0,
+                 residual_check=False, max_cell_visits=0, band_window=0, eager_publish=False,
+                 schedule="auto", timeout_ms=0, graph=True):
+        ps, self._keep, self.outputs = [], [], []
+        device = None
+        for w in problems:
+            p, keep, u, dev = _marshal(w["F"], w["h"], w["src"], w.get("q"), w.get("mask"),
+                                       w.get("u_out"), dtype)
+            if device is None:
+                device = dev
+            elif device != dev:
+                raise ValueError("all problems of a batch must be host or all device arrays")
+            ps.append(p)
+            self._keep.append(keep)
+            self.outputs.append(u)
+        self._n = len(ps)
+        self._arr = (Problem * self._n)(*ps)
+        self._device = device
+        self._args = (F64 if dtype == "f64" else F32, method, cell, band, device, residual_check,
+                      workers, max_cell_visits, band_window, eager_publish, schedule, timeout_ms,
+                      graph)
+        self._stats = (Stats * self._n)()
+
+    def solve(self):
+        """Solves the batch into self.outputs; returns the stats dicts."""
+        (dt, method, cell, band, device, resid, workers, mcv, bw, eager, sched, tmo,
+         graph) = self._args
+        o = _opts(dt, method, cell, band, device, _stream_of(device), resid, workers, mcv, bw,
+                  eager, sched, tmo, graph)
+        _check(lib.eik_solve_batched(self._n, self._arr, ctypes.byref(o), self._stats))
+        return [s.as_dict() for s in self._stats]

@@ -88,3 +88,19 @@ def test_full_256_instance_batch_sampled(eik, dtype):
     for w, g in zip(ws, got):
         assert np.isfinite(g).all()  # no obstacles: every node reachable
         assert (g[np.unravel_index(w["src"], g.shape)] == 0.0).all()
+
+
+def test_batch_object_repeated_solves(eik):
+    """eik.Batch marshals once; repeated solves (graph replay from the second
+    on) give the oracle's results every time."""
+    ws = W.batch_bumps(count=10, seed=44, n_lo=50, n_hi=260)
+    refs = [O.fmm(O.Problem.from_workload(w)) for w in ws]
+    b = eik.Batch([to_dev(w) for w in ws], graph=True)
+    print("[gpu] Batch object, three solves", flush=True)
+    for rep in range(3):
+        for u in b.outputs:
+            u.fill_(-1.0)
+        st = b.solve()
+        assert st[0]["graph_replayed"] == (1 if rep else 0)
+        for w, u, U in zip(ws, b.outputs, refs):
+            assert max_rel(u.double().cpu().numpy(), U) <= 1e-12, (rep, w["name"])
