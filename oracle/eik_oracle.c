@@ -858,11 +858,16 @@ int orc_fmsm(const orc_problem* p, int32_t s, double* V, int64_t* order_out,
     rc = -2;
     goto done;
   }
-  /* Part I.  Coarse grid of cell centres, h^c = s h.  READING: coarse speed is
-     the mean of F over the cell's accessible nodes (an all-obstacle cell is a
-     coarse obstacle), summed column by column (each column bottom to top,
-     then the column sums left to right); a cell holding sources is a coarse
-     source with the smallest of their q. */
+  /* Part I.  Coarse grid of cell centres, h^c = s h (Section 3.1: a coarse
+     gridpoint is the centre of its cell, and Fast Marching runs on the coarse
+     grid).  READING: the coarse speed is F at the cell centre: the centre
+     node for an odd side, else the mean of the two or four accessible nodes
+     around the centre, added in the order (x ascending, then y ascending
+     within each x).  If none of those is accessible, the mean of F over the
+     cell's accessible nodes, summed column by column (each column bottom to
+     top, then the column sums left to right); an all-obstacle cell is a
+     coarse obstacle.  A cell holding sources is a coarse source with the
+     smallest of their q. */
   long nsc = 0;
   for (long c = 0; c < J; ++c) {
     int x0, x1, y0, y1, cnt = 0, has = 0;
@@ -884,6 +889,19 @@ int orc_fmsm(const orc_problem* p, int32_t s, double* V, int64_t* order_out,
     }
     mc[c] = cnt > 0;
     Fc[c] = cnt > 0 ? sum / cnt : 1.0;
+    {
+      int is[2] = {(x0 + x1 - 1) / 2, (x0 + x1) / 2}, js[2] = {(y0 + y1 - 1) / 2, (y0 + y1) / 2};
+      int ni = is[0] == is[1] ? 1 : 2, nj = js[0] == js[1] ? 1 : 2, nc = 0;
+      double sc = 0.0;
+      for (int a = 0; a < ni; ++a)
+        for (int b = 0; b < nj; ++b) {
+          long k = (long)js[b] * g.nx + is[a];
+          if (!g.acc[k]) continue;
+          sc += g.F[k];
+          nc++;
+        }
+      if (nc > 0) Fc[c] = sc / nc;
+    }
     if (has) {
       csrc[nsc] = c;
       cq[nsc] = qmin;

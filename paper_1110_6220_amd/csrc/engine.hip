@@ -1265,11 +1265,14 @@ __global__ void k_apply_sources(Engine e) {
   }
 }
 
-// Coarse grid inputs (FMSM Part I): per cell the mean speed over its
-// accessible nodes, whether it has one, and (initially +inf) the smallest exit
-// cost of its exit nodes.  One wave per cell: lane l sums column l bottom to
-// top (loads of a row are contiguous), then lane 0 adds the column sums left
-// to right -- a fixed order the CPU oracle uses as well.
+// Coarse grid inputs (FMSM Part I, Section 3.1: a coarse gridpoint is the
+// centre of its cell): per cell the speed at the centre -- the centre node,
+// or the mean of the accessible nodes around it -- falling back to the mean
+// speed over the cell's accessible nodes; whether it has an accessible node;
+// and (initially +inf) the smallest exit cost of its exit nodes.  One wave
+// per cell: lane l sums column l bottom to top (loads of a row are
+// contiguous), then lane 0 adds the column sums left to right -- a fixed
+// order the CPU oracle uses as well.
 template <typename T>
 __global__ __launch_bounds__(64) void k_coarse_cells(Engine e, const CoarseOut* co) {
   __shared__ double csum[64];
@@ -1304,8 +1307,22 @@ __global__ __launch_bounds__(64) void k_coarse_cells(Engine e, const CoarseOut* 
         sum += csum[l];
         c += ccnt[l];
       }
+      // the speed at the cell centre: the centre node, or the mean of the
+      // accessible nodes around it (x ascending, then y); the cell mean when
+      // none of them is accessible
+      const int ia = (B.x0 + B.x1 - 1) / 2, ib = (B.x0 + B.x1) / 2;
+      const int ja = (B.y0 + B.y1 - 1) / 2, jb = (B.y0 + B.y1) / 2;
+      double sc = 0.0;
+      int nc = 0;
+      for (int a = 0; a < (ia == ib ? 1 : 2); ++a)
+        for (int b = 0; b < (ja == jb ? 1 : 2); ++b) {
+          const size_t n = (size_t)(b ? jb : ja) * I.nx + (a ? ib : ia);
+          if (I.mask && !I.mask[n]) continue;
+          sc += (double)F[n];
+          nc++;
+        }
       const int cl = g - I.cell0;
-      co[k].F[cl] = c ? sum / c : 1.0;
+      co[k].F[cl] = nc ? sc / nc : c ? sum / c : 1.0;
       co[k].mask[cl] = c > 0;
       co[k].q[cl] = __builtin_huge_val();
     }

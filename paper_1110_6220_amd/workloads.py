@@ -49,6 +49,37 @@ def smooth_sine(n: int = 1025, amp: float = 0.5, freq: float = 1.0):
     return _pack(f"sine_{n}_a{amp}_f{freq}", F, h, [c * n + c])
 
 
+def sinusoid_point(n: int = 1408, amp: float = 0.5, freq: float = 10.0):
+    """F(x, y) = 1 + amp sin(2 pi freq x) sin(2 pi freq y) on [0, 1]^2 with the
+    exit set at the centre (0.5, 0.5) (Section 4.3): the centre node with q = 0
+    when n is odd, else the four nodes around it with q = their distance to
+    the centre."""
+    h = 1.0 / (n - 1)
+    x = np.arange(n) * h
+    s = np.sin(2.0 * math.pi * freq * x)
+    F = 1.0 + amp * np.outer(s, s)
+    if n % 2:
+        c = (n - 1) // 2
+        return _pack(f"sine_pt_{n}_a{amp}_f{freq}", F, h, [c * n + c])
+    a, b = n // 2 - 1, n // 2
+    src = [a * n + a, a * n + b, b * n + a, b * n + b]
+    q = [math.hypot(0.5 * h, 0.5 * h)] * 4
+    return _pack(f"sine_pt_{n}_a{amp}_f{freq}", F, h, src, q=q)
+
+
+def sinusoid_boundary(n: int = 1408, amp: float = 0.5, freq: float = 10.0):
+    """F(x, y) = 1 + amp sin(2 pi freq x) sin(2 pi freq y) on [0, 1]^2 with the
+    exit set Q = every boundary node, q = 0 (the general boundary conditions
+    of Section 4.5)."""
+    h = 1.0 / (n - 1)
+    x = np.arange(n) * h
+    s = np.sin(2.0 * math.pi * freq * x)
+    F = 1.0 + amp * np.outer(s, s)
+    idx = np.arange(n * n).reshape(n, n)
+    src = np.unique(np.concatenate([idx[0], idx[-1], idx[:, 0], idx[:, -1]]))
+    return _pack(f"sine_gbc_{n}_a{amp}_f{freq}", F, h, src)
+
+
 def checker_obstacles(n: int = 4097, squares: int = 16, seed: int = 3, obst_seed: int = 33,
                       cover: float = 0.20, side_lo: int = 64, side_hi: int = 512,
                       keep: int = 16):

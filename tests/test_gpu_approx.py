@@ -46,10 +46,15 @@ def fmsm_cases():
         nx, ny = (int(v) for v in rng.integers(20, 120, size=2))
         cases.append((W.random_small(rng, nx, ny, obst=0.1, nsrc=int(rng.integers(1, 4)),
                                      q_spread=0.2), int(rng.choice([4, 8, 16]))))
+    # the paper's sinusoids (Sections 4.3, 4.5): four-node point source, and
+    # the whole boundary as exit set (every boundary cell a coarse source)
+    cases += [(W.sinusoid_point(352, 0.5, 10.0), 16), (W.sinusoid_point(704, 0.5, 10.0), 32),
+              (W.sinusoid_boundary(352, 0.5, 10.0), 16), (W.sinusoid_boundary(704, 0.99, 1.0), 32),
+              (W.sinusoid_boundary(1408, 0.5, 10.0), 64)]
     return cases
 
 
-@pytest.mark.parametrize("case", range(9))
+@pytest.mark.parametrize("case", range(14))
 def test_fmsm_bitwise(eik, case):
     w, s = fmsm_cases()[case]
     V, info = O.fmsm(O.Problem.from_workload(w), s)
@@ -95,3 +100,18 @@ def test_exact_schedules_agree(eik):
     for sched in ("coarse", "bands", "fifo"):
         got, _ = solve_dev(eik, w, cell=32, schedule=sched)
         assert (np.abs(got - U) / U.max()).max() <= 1e-12, sched
+
+
+@pytest.mark.parametrize("family", ["pt", "gbc"])
+def test_exact_on_paper_sinusoids_1408(eik, family):
+    """The exact method on the 1408^2 sinusoids of Sections 4.3 and 4.5 (four
+    exit nodes with q = distance to the centre; the whole boundary), FP64,
+    against Fast Marching."""
+    gen = W.sinusoid_point if family == "pt" else W.sinusoid_boundary
+    for amp, freq in ((0.5, 10.0), (0.99, 1.0)):
+        w = gen(1408, amp, freq)
+        U = O.fmm(O.Problem.from_workload(w))
+        got, _ = solve_dev(eik, w, method="exact")
+        fin = np.isfinite(U)
+        assert np.array_equal(np.isfinite(got), fin)
+        assert (np.abs(got[fin] - U[fin]) / U[fin].clip(1e-300)).max() <= 1e-12, (family, amp)
