@@ -85,8 +85,8 @@ static std::vector<DevBuf*> all_bufs(Workspace* w) {
                       &sv->slot, &sv->head, &sv->tail, &sv->inflight, &sv->cursor, &sv->ctl, &sv->inst})
       v.push_back(b);
   for (DevBuf* b : {&w->F, &w->u, &w->mask, &w->src, &w->q, &w->cF, &w->cmask, &w->cq, &w->cu,
-                    &w->cout, &w->F64, &w->u64, &w->ready_at, &w->trace, &w->trace_n, &w->wall_in,
-                    &w->wall_cnt})
+                    &w->cout, &w->crank, &w->fmm_spill, &w->F64, &w->u64, &w->ready_at, &w->trace,
+                    &w->trace_n, &w->wall_in, &w->wall_cnt})
     v.push_back(b);
   return v;
 }
@@ -384,7 +384,7 @@ constexpr size_t kMaxPlans = 8;           // captured graphs kept per workspace
 
 static int complete(Workspace* ws, int n, const eik_problem* probs, const eik_opts& o,
                     const RunCtx& ctx, const std::vector<Inst>& inst, int64_t J, double band,
-                    bool have_coarse, bool want_resid, hipStream_t stream, double t0,
+                    bool coarse_engine, bool want_resid, hipStream_t stream, double t0,
                     eik_stats* stats, RunInfo* info, std::unique_lock<std::mutex>& lk,
                     bool replayed);
 
@@ -458,7 +458,7 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
       HIP_TRY(hipEventRecord(ws->ev1, stream));
       HIP_TRY(hipGraphLaunch(pl->post, stream));
       HIP_TRY(hipStreamSynchronize(stream));
-      return complete(ws, n, probs, o, ctx, pl->host_inst, pl->J, pl->band, pl->have_coarse,
+      return complete(ws, n, probs, o, ctx, pl->host_inst, pl->J, pl->band, pl->coarse_engine,
                       pl->want_resid, stream, t0, stats, info, lk, true);
     }
   }
@@ -612,16 +612,38 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
     e.trace_cap = kTraceCap;
   }
   Engine ce;
-  bool have_coarse = false;
-  int cext = 0;
+  // coarse grid of cell centres with spacing h^c = s h (FMSM Part I): FMSM
+  // orders its cells by Fast Marching on it, as the method prescribes; the
+  // other methods use the order only as a schedule and take the faster
+  // parallel exact solve (coarse_engine)
+  bool have_coarse = false, coarse_engine = false;
+  const bool fmm = method == EIK_FMSM;
+  int cext = 0, fmm_lds = 0;
+  FmmSpill spill{};
   if (dag) {
-    // FMSM Part I on every instance: coarse speeds, exit cells, and an exact
-    // solve on the grid of cell centres with spacing h^c = s h
     HIP_TRY(ws->cF.ensure(J * sizeof(double)));
     HIP_TRY(ws->cmask.ensure(J));
     HIP_TRY(ws->cq.ensure(J * sizeof(double)));
     HIP_TRY(ws->cu.ensure(J * sizeof(double)));
-    HIP_TRY(ws->coarse.delta.ensure(J * sizeof(double)));
+    if (fmm) {
+      HIP_TRY(ws->crank.ensure(J * sizeof(int32_t)));
+      const int lim = coarse_fmm_lds_cells();
+      int64_t big = 0;  // coarse cells of the problems that do not fit in LDS
+      for (int k = 0; k < n; ++k) {
+        const int64_t jk = (int64_t)inst[k].kx * inst[k].ky;
+        if (jk <= lim) fmm_lds = std::max<int>(fmm_lds, (int)jk);
+        else big = J;
+      }
+      if (big) {
+        HIP_TRY(ws->fmm_spill.ensure(J * (2 * sizeof(double) + 2 * sizeof(int32_t))));
+        spill.delta = ws->fmm_spill.as<double>();
+        spill.fval = spill.delta + J;
+        spill.st = reinterpret_cast<int32_t*>(spill.fval + J);
+        spill.fidx = spill.st + J;
+      }
+    } else {
+      HIP_TRY(ws->coarse.delta.ensure(J * sizeof(double)));
+    }
     DevBuf& coutbuf = np ? np->cout : ws->cout;
     HIP_TRY(coutbuf.ensure(n * sizeof(CoarseOut)));
     std::vector<CoarseOut> co(n);
@@ -632,6 +654,8 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
       co[k].mask = ws->cmask.as<uint8_t>() + c0;
       co[k].q = ws->cq.as<double>() + c0;
       co[k].u = ws->cu.as<double>() + c0;
+      co[k].rank = fmm ? ws->crank.as<int32_t>() + c0 : nullptr;
+      if (fmm) continue;
       Inst& C = cinst[k];
       std::memset(&C, 0, sizeof C);
       C.u = co[k].u;
@@ -651,14 +675,15 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
       cext = std::max(cext, ct.extent);
     }
     HIP_TRY(hipMemcpyAsync(coutbuf.p, co.data(), n * sizeof(CoarseOut), hipMemcpyHostToDevice, stream));
-    if ((rc = setup_engine(ws->coarse, cinst, EIK_F64, EIK_EXACT, 0, -1.0, 0, 0, 0, timeout, stream, &ce,
-                           np ? &np->cinst : nullptr)))
+    if (!fmm && (rc = setup_engine(ws->coarse, cinst, EIK_F64, EIK_EXACT, 0, -1.0, 0, 0, 0, timeout, stream,
+                                   &ce, np ? &np->cinst : nullptr)))
       return rc;
     have_coarse = true;
+    coarse_engine = !fmm;
   }
   const CoarseOut* co_dev = have_coarse ? (np ? np->cout : ws->cout).as<CoarseOut>() : nullptr;
 
-  const int cw = have_coarse ? std::max(1, default_workers(ws, ce.ncells, tile_for(cext), EIK_F64,
+  const int cw = coarse_engine ? std::max(1, default_workers(ws, ce.ncells, tile_for(cext), EIK_F64,
                                                           EIK_EXACT, n) / std::max(1, ctx.share))
                             : 1;
 
@@ -678,15 +703,19 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
     step("prepare", launch_prepare(e, max_nodes, ls));
     if (have_coarse) {
       step("coarse inputs", launch_coarse_inputs(e, co_dev, (int)max_src, ls));
-      step("coarse prepare", launch_prepare(ce, J, ls));
-      step("coarse solve", launch_solve(ce, cw, tile_for(cext), ls));
+      if (coarse_engine) {
+        step("coarse prepare", launch_prepare(ce, J, ls));
+        step("coarse solve", launch_solve(ce, cw, tile_for(cext), ls));
+      } else {
+        step("coarse fast marching", launch_coarse_fmm(e, co_dev, fmm_lds, spill, ls));
+      }
       step("order", launch_dag(e, co_dev, (int)J, ls));
     }
   };
   auto post = [&](hipStream_t ls) {
     if (want_resid) step("residual", launch_residual(e, max_nodes, ls));
     step("statistics copy", hipMemcpyAsync(ws->ctl_host, e.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ls));
-    if (have_coarse)
+    if (coarse_engine)
       step("coarse statistics copy",
            hipMemcpyAsync(ws->ctl_host + 1, ce.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ls));
   };
@@ -731,7 +760,7 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
     np->host_inst = inst;
     np->J = J;
     np->band = band;
-    np->have_coarse = have_coarse;
+    np->coarse_engine = coarse_engine;
     np->want_resid = want_resid;
     if (ws->plans.size() >= kMaxPlans) {
       auto lru = std::min_element(ws->plans.begin(), ws->plans.end(),
@@ -744,7 +773,7 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
     ws->plans.push_back(std::move(np));
   }
   HIP_TRY(hipStreamSynchronize(stream));
-  return complete(ws, n, probs, o, ctx, inst, J, band, have_coarse, want_resid, stream, t0, stats,
+  return complete(ws, n, probs, o, ctx, inst, J, band, coarse_engine, want_resid, stream, t0, stats,
                   info, lk, false);
 }
 
@@ -752,7 +781,7 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
 // to host outputs, diagnostics and statistics.
 static int complete(Workspace* ws, int n, const eik_problem* probs, const eik_opts& o,
                     const RunCtx& ctx, const std::vector<Inst>& inst, int64_t J, double band,
-                    bool have_coarse, bool want_resid, hipStream_t stream, double t0,
+                    bool coarse_engine, bool want_resid, hipStream_t stream, double t0,
                     eik_stats* stats, RunInfo* info, std::unique_lock<std::mutex>& lk,
                     bool replayed) {
   const int dt = o.dtype;
@@ -760,7 +789,7 @@ static int complete(Workspace* ws, int n, const eik_problem* probs, const eik_op
   const bool dev = o.device_ptrs != 0;
   int rc = EIK_OK;
   const Ctl c = ws->ctl_host[0];
-  const unsigned err = c.err | (have_coarse ? ws->ctl_host[1].err : 0u);
+  const unsigned err = c.err | (coarse_engine ? ws->ctl_host[1].err : 0u);
   if (err & (kErrSpeed | kErrSource))
     return fail(EIK_EINVAL, "%s", (err & kErrSpeed) ? "a speed value is not positive and finite"
                                                    : "a source is out of range, on an obstacle or has non-finite q");

@@ -131,6 +131,16 @@ struct CoarseOut {
   uint8_t* mask;    // J 1 = the cell has an accessible node
   double* q;        // J min exit cost over the cell's exit nodes, +inf if none
   double* u;        // J coarse solution (filled by the coarse solve)
+  int32_t* rank;    // J acceptance rank of Fast Marching (FMSM), else nullptr
+};
+
+// Workspace of the coarse Fast Marching kernel for problems whose coarse grid
+// does not fit in LDS (J entries per problem at the problem's cell0).
+struct FmmSpill {
+  double* delta;  // h^c / F^c, +inf on coarse obstacles
+  double* fval;   // front values
+  int32_t* st;    // -2 obstacle, -1 far, -3 accepted, else the front slot
+  int32_t* fidx;  // front cells
 };
 
 // Host-side launchers (engine.hip).  All work is enqueued on `stream`.
@@ -145,6 +155,15 @@ hipError_t launch_residual(const Engine& e, int64_t max_nodes, hipStream_t strea
 // at co[k].*[cell - cell0])
 hipError_t launch_coarse_inputs(const Engine& fine, const CoarseOut* co_dev, int max_cells,
                                 hipStream_t stream);
+// Fast Marching on the coarse grid of every problem (FMSM Part I): values
+// into co[k].u, acceptance ranks into co[k].rank.  Problems with at most
+// lds_cells coarse cells work in LDS (kFmmLdsBytesPerCell bytes per cell),
+// the others in `spill`.
+constexpr int kFmmLdsBytesPerCell = 32;
+hipError_t launch_coarse_fmm(const Engine& fine, const CoarseOut* co_dev, int lds_cells,
+                             const FmmSpill& spill, hipStream_t stream);
+// Largest coarse grid the Fast Marching kernel keeps in LDS on this device.
+int coarse_fmm_lds_cells();
 // dependency counts and order bits from the coarse solutions; queues the
 // cells that have no earlier neighbour
 hipError_t launch_dag(const Engine& fine, const CoarseOut* co_dev, int max_cells,

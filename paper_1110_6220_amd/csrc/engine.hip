@@ -1341,6 +1341,165 @@ __global__ void k_coarse_sources(Engine e, const CoarseOut* co) {
   }
 }
 
+// Fast Marching on the grid of cell centres (FMSM Part I, Section 3.1; the
+// method of Section 2): one wave per problem.  Every exit cell is accepted
+// first; their neighbours are then relaxed exit cell by exit cell in
+// (q, index) order, and after that the smallest (value, index) entry of the
+// front is accepted, one at a time, and its neighbours relaxed.  The four
+// neighbours of a cell are pairwise non-adjacent, so four lanes relax them at
+// once with the same result as one after the other.  The front is an
+// unordered array; each acceptance takes a wave-wide argmin over it.
+// Values, the front and the cell states live in LDS when the coarse grid
+// fits (lds_cells), else in the spill workspace.
+constexpr int kFmmFar = -1, kFmmObst = -2, kFmmAcc = -3;
+
+__device__ __forceinline__ double bcast_d(double v, int src_lane) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = bcast((int)b, src_lane), hi = bcast((int)(b >> 32), src_lane);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Wave-wide minimum of (v, c) in lexicographic order; the winning lane's
+// (v, c, slot) is returned, wave-uniform.
+__device__ __forceinline__ void wave_argmin(double& v, int& c, int& slot) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(v, off, 64);
+    const int oc = __shfl_xor(c, off, 64), os = __shfl_xor(slot, off, 64);
+    if (ov < v || (ov == v && oc < c)) {
+      v = ov;
+      c = oc;
+      slot = os;
+    }
+  }
+  v = bcast_d(v, 0);
+  c = bcast(c, 0);
+  slot = bcast(slot, 0);
+}
+
+__global__ __launch_bounds__(64) void k_coarse_fmm(Engine e, const CoarseOut* co, int lds_cells,
+                                                   FmmSpill spill) {
+  extern __shared__ __align__(16) unsigned char fmm_lds[];
+  const int k = blockIdx.x;
+  const Inst I = inst_at(e, k);
+  const CoarseOut C = co[k];
+  const int lane = threadIdx.x, kx = I.kx, ky = I.ky, J = kx * ky;
+  const double INF = __builtin_huge_val();
+  const double hc = (double)I.s * I.h;
+  double *V, *dl, *fv;
+  int *st, *fi;
+  const bool in_lds = J <= lds_cells;
+  if (in_lds) {
+    V = reinterpret_cast<double*>(fmm_lds);
+    dl = V + J;
+    fv = dl + J;
+    st = reinterpret_cast<int*>(fv + J);
+    fi = st + J;
+  } else {
+    V = C.u;
+    dl = spill.delta + I.cell0;
+    fv = spill.fval + I.cell0;
+    st = spill.st + I.cell0;
+    fi = spill.fidx + I.cell0;
+  }
+  for (int c = lane; c < J; c += 64) {
+    const bool acc = C.mask[c] != 0;
+    const double q = C.q[c];
+    const bool exit = acc && q < INF;
+    V[c] = exit ? q : INF;
+    dl[c] = acc ? hc / C.F[c] : INF;
+    st[c] = !acc ? kFmmObst : exit ? kFmmAcc : kFmmFar;
+    C.rank[c] = J + c;  // cells the front never reaches: after all others, by index
+  }
+  __syncthreads();
+  // exit cells into the top of the front arrays, [J - ns, J)
+  int ns = 0;
+  for (int base = 0; base < J; base += 64) {
+    const int c = base + lane;
+    const bool is = c < J && st[c] == kFmmAcc;
+    const unsigned long long m = ballot(is);
+    if (is) {
+      const int slot = J - 1 - ns - (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+      fv[slot] = V[c];
+      fi[slot] = c;
+    }
+    ns += __builtin_popcountll(m);
+  }
+  __syncthreads();
+  int nf = 0, na = 0, rs = ns;
+  for (;;) {
+    const bool exits = rs > 0;
+    const int lo = exits ? J - rs : 0, hi = exits ? J : nf;
+    if (lo == hi) break;
+    // accept the (value, index) minimum of [lo, hi)
+    double bv = INF;
+    int bc = 0x7fffffff, bs = -1;
+    for (int t = lo + lane; t < hi; t += 64) {
+      const double v = fv[t];
+      const int c = fi[t];
+      if (v < bv || (v == bv && c < bc)) {
+        bv = v;
+        bc = c;
+        bs = t;
+      }
+    }
+    wave_argmin(bv, bc, bs);
+    if (lane == 0) {
+      if (exits) {  // the exit list shrinks from below
+        fv[bs] = fv[lo];
+        fi[bs] = fi[lo];
+      } else {
+        const int last = nf - 1;
+        if (bs != last) {
+          const int mv = fi[last];
+          fv[bs] = fv[last];
+          fi[bs] = mv;
+          st[mv] = bs;
+        }
+        st[bc] = kFmmAcc;
+      }
+      C.rank[bc] = na;
+    }
+    if (exits) rs--;
+    else nf--;
+    na++;
+    __syncthreads();
+    // relax the four neighbours W, E, S, N of the accepted cell
+    const int cx = bc % kx, cy = bc / kx;
+    const int nx = cx + (lane == 0 ? -1 : lane == 1 ? 1 : 0);
+    const int ny = cy + (lane == 2 ? -1 : lane == 3 ? 1 : 0);
+    bool live = lane < 4 && nx >= 0 && nx < kx && ny >= 0 && ny < ky;
+    const int nb = ny * kx + nx;
+    const int sn = live ? st[nb] : kFmmObst;
+    live = live && sn != kFmmObst && sn != kFmmAcc;
+    double vn = INF;
+    if (live) {
+      const double uW = nx > 0 ? V[nb - 1] : INF, uE = nx + 1 < kx ? V[nb + 1] : INF;
+      const double uS = ny > 0 ? V[nb - kx] : INF, uN = ny + 1 < ky ? V[nb + kx] : INF;
+      const double a = uW < uE ? uW : uE, b = uS < uN ? uS : uN;
+      const double t = (a < b ? a : b) == INF ? INF : local_update(a, b, dl[nb]);
+      vn = V[nb];
+      if (t < vn) {
+        vn = t;
+        V[nb] = t;
+      }
+      if (sn >= 0) fv[sn] = vn;
+    }
+    const bool push = live && sn == kFmmFar;
+    const unsigned long long m = ballot(push);
+    if (push) {
+      const int slot = nf + (int)__builtin_amdgcn_mbcnt_lo((unsigned)m, 0u);
+      fv[slot] = vn;
+      fi[slot] = nb;
+      st[nb] = slot;
+    }
+    nf += __builtin_popcountll(m);
+    __syncthreads();
+  }
+  if (in_lds)
+    for (int c = lane; c < J; c += 64) C.u[c] = V[c];
+}
+
 // Order of the cells: exit cells first by (q, index), then by (coarse value,
 // index) -- the acceptance order of Fast Marching on the coarse grid -- and
 // cells the coarse front does not reach last, by index.  Each cell counts
@@ -1359,6 +1518,7 @@ __global__ void k_dag(Engine e, const CoarseOut* co) {
     auto cls = [&](int x) { return C.q[x] < __builtin_huge_val() ? 0 : 1; };
     auto val = [&](int x) { return C.q[x] < __builtin_huge_val() ? C.q[x] : C.u[x]; };
     auto before = [&](int x, int y) {  // does cell x precede cell y?
+      if (C.rank) return C.rank[x] < C.rank[y];
       const int cxx = cls(x), cyy = cls(y);
       if (cxx != cyy) return cxx < cyy;
       const double vx = val(x), vy = val(y);
@@ -1528,6 +1688,28 @@ hipError_t launch_coarse_inputs(const Engine& fine, const CoarseOut* co_dev, int
   else hipLaunchKernelGGL(k_coarse_cells<float>, gc, dim3(64), 0, stream, fine, co_dev);
   hipLaunchKernelGGL(k_coarse_sources, dim3(grid_for(max_src, 64, 1024), fine.ninst), dim3(64), 0,
                      stream, fine, co_dev);
+  return hipGetLastError();
+}
+
+int coarse_fmm_lds_cells() {
+  static const int cells = [] {
+    int dev = 0, lim = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      lim = 65536;
+    if (lim > 65536 &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_coarse_fmm),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess)
+      lim = 65536;
+    return lim / kFmmLdsBytesPerCell;
+  }();
+  return cells;
+}
+
+hipError_t launch_coarse_fmm(const Engine& fine, const CoarseOut* co_dev, int lds_cells,
+                             const FmmSpill& spill, hipStream_t stream) {
+  hipLaunchKernelGGL(k_coarse_fmm, dim3(fine.ninst), dim3(64),
+                     (size_t)lds_cells * kFmmLdsBytesPerCell, stream, fine, co_dev, lds_cells, spill);
   return hipGetLastError();
 }
 

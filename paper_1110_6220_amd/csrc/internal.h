@@ -58,7 +58,7 @@ struct Plan {
   std::vector<Inst> host_inst;
   int64_t J = 0;
   double band = -1.0;
-  bool have_coarse = false, want_resid = false;
+  bool coarse_engine = false, want_resid = false;
 };
 
 // Per-device workspace, reused by every call on that device.
@@ -67,6 +67,7 @@ struct Workspace {
   Solver fine, coarse;
   DevBuf F, u, mask, src, q;          // staging of host inputs
   DevBuf cF, cmask, cq, cu, cout;     // coarse problems
+  DevBuf crank, fmm_spill;            // coarse Fast Marching (FMSM)
   DevBuf F64, u64;                    // FP64 re-solve of FP32 problems
   DevBuf ready_at, trace, trace_n;    // diagnostic trace (EIK_TRACE)
   DevBuf wall_in, wall_cnt;           // wall density of masked problems

@@ -67,6 +67,24 @@ def sinusoid_point(n: int = 1408, amp: float = 0.5, freq: float = 10.0):
     return _pack(f"sine_pt_{n}_a{amp}_f{freq}", F, h, src, q=q)
 
 
+def checkerboard_point(n: int = 1408, k: int = 11):
+    """k x k checkerboard on [0, 1]^2 (checker of node x_i: floor(k x_i)) with
+    F = 1 on the slow checkers, the centre one among them, and F = 2 on the
+    others; exit set at the centre (0.5, 0.5) as in sinusoid_point
+    (Section 4.2)."""
+    h = 1.0 / (n - 1)
+    idx = np.minimum((np.arange(n) * h * k).astype(np.int64), k - 1)
+    parity = (idx[None, :] + idx[:, None]) % 2
+    F = np.where(parity == (2 * (k // 2)) % 2, 1.0, 2.0)
+    if n % 2:
+        c = (n - 1) // 2
+        return _pack(f"checker{k}_pt_{n}", F, h, [c * n + c])
+    a, b = n // 2 - 1, n // 2
+    src = [a * n + a, a * n + b, b * n + a, b * n + b]
+    q = [math.hypot(0.5 * h, 0.5 * h) / F[a, a]] * 4
+    return _pack(f"checker{k}_pt_{n}", F, h, src, q=q)
+
+
 def sinusoid_boundary(n: int = 1408, amp: float = 0.5, freq: float = 10.0):
     """F(x, y) = 1 + amp sin(2 pi freq x) sin(2 pi freq y) on [0, 1]^2 with the
     exit set Q = every boundary node, q = 0 (the general boundary conditions

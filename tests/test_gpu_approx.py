@@ -50,11 +50,12 @@ def fmsm_cases():
     # the whole boundary as exit set (every boundary cell a coarse source)
     cases += [(W.sinusoid_point(352, 0.5, 10.0), 16), (W.sinusoid_point(704, 0.5, 10.0), 32),
               (W.sinusoid_boundary(352, 0.5, 10.0), 16), (W.sinusoid_boundary(704, 0.99, 1.0), 32),
-              (W.sinusoid_boundary(1408, 0.5, 10.0), 64)]
+              (W.sinusoid_boundary(1408, 0.5, 10.0), 64),
+              (W.checkerboard_point(352, 11), 16), (W.checkerboard_point(656, 41), 8)]
     return cases
 
 
-@pytest.mark.parametrize("case", range(14))
+@pytest.mark.parametrize("case", range(16))
 def test_fmsm_bitwise(eik, case):
     w, s = fmsm_cases()[case]
     V, info = O.fmsm(O.Problem.from_workload(w), s)
@@ -102,14 +103,18 @@ def test_exact_schedules_agree(eik):
         assert (np.abs(got - U) / U.max()).max() <= 1e-12, sched
 
 
-@pytest.mark.parametrize("family", ["pt", "gbc"])
-def test_exact_on_paper_sinusoids_1408(eik, family):
-    """The exact method on the 1408^2 sinusoids of Sections 4.3 and 4.5 (four
-    exit nodes with q = distance to the centre; the whole boundary), FP64,
-    against Fast Marching."""
-    gen = W.sinusoid_point if family == "pt" else W.sinusoid_boundary
-    for amp, freq in ((0.5, 10.0), (0.99, 1.0)):
-        w = gen(1408, amp, freq)
+@pytest.mark.parametrize("family", ["pt", "gbc", "chk"])
+def test_exact_on_paper_workloads_1408(eik, family):
+    """The exact method on the 1408^2 workloads of Sections 4.2, 4.3 and 4.5
+    (sinusoids with four exit nodes at the centre or the whole boundary as
+    exit set; 11 x 11 and 41 x 41 checkerboards), FP64, against Fast Marching."""
+    if family == "chk":
+        ws = [W.checkerboard_point(1408, 11), W.checkerboard_point(1312, 41)]
+    else:
+        gen = W.sinusoid_point if family == "pt" else W.sinusoid_boundary
+        ws = [gen(1408, 0.5, 10.0), gen(1408, 0.99, 1.0)]
+    for w in ws:
+        amp = w["name"]
         U = O.fmm(O.Problem.from_workload(w))
         got, _ = solve_dev(eik, w, method="exact")
         fin = np.isfinite(U)

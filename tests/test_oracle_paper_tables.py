@@ -1,12 +1,14 @@
 """Oracle pins against values the paper prints for its 1408^2 workloads
-(Sections 4.3 and 4.5: tables tab:const, tab:sinu_1, tab:sinu_2,
-tab:sinu_1_gbc, tab:sinu_2_gbc; fixture tests/golden/sinusoid_1408.txt):
+(Sections 4.2, 4.3 and 4.5: tables tab:checker_11, tab:checker_41,
+tab:const, tab:sinu_1, tab:sinu_2, tab:sinu_1_gbc, tab:sinu_2_gbc; fixture
+tests/golden/paper_tables_1408.txt):
 Fast Marching's errors against an h/4 Fast Marching ground truth, Fast
 Sweeping's sweep counts, and the error ratios, sweep counts and
 monotonicity rates of FMSM and FHCM.  These fix the grid and exit-set
 readings, the update, and the two approximate methods (coarse speed and
-order, sweep directions, monotonicity flags).  Slow: five 5629^2 Fast
-Marching solves for the ground truths."""
+order, sweep directions, monotonicity flags) on smooth and piecewise-constant
+speeds.  Slow: seven Fast Marching solves of ~30M nodes for the ground
+truths."""
 import os
 
 import numpy as np
@@ -16,8 +18,7 @@ import oracle as O
 from paper_1110_6220_amd import workloads as W
 
 pytestmark = pytest.mark.slow
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sinusoid_1408.txt")
-N = 1408
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "paper_tables_1408.txt")
 
 
 def rows():
@@ -33,7 +34,12 @@ def within_last_digit(value, printed):
     return abs(value - float(printed)) <= unit * (1 + 1e-9)
 
 
+SIZE = {"pt": 1408, "gbc": 1408, "chk11": 1408, "chk41": 1312}
+
+
 def workload(family, amp, freq, n):
+    if family.startswith("chk"):
+        return W.checkerboard_point(n, int(family[3:]))
     gen = W.sinusoid_point if family == "pt" else W.sinusoid_boundary
     return gen(n, amp, freq)
 
@@ -44,8 +50,9 @@ _cache = {}
 def case(family, amp, freq):
     key = (family, amp, freq)
     if key not in _cache:
-        p = O.Problem.from_workload(workload(family, amp, freq, N))
-        fine = workload(family, amp, freq, 4 * (N - 1) + 1)
+        n = SIZE[family]
+        p = O.Problem.from_workload(workload(family, amp, freq, n))
+        fine = workload(family, amp, freq, 4 * (n - 1) + 1)
         truth = O.fmm(O.Problem.from_workload(fine))[::4, ::4]
         _cache[key] = (p, truth, O.fmm(p))
     return _cache[key]
@@ -60,7 +67,7 @@ def ratios(V, U, truth):
     return {"rmax": r.max(), "rho": r.mean(), "r": E.max() / e.max()}
 
 
-@pytest.mark.parametrize("family", ["pt", "gbc"])
+@pytest.mark.parametrize("family", ["pt", "gbc", "chk11", "chk41"])
 def test_paper_tables(family):
     for row in rows():
         if row[0] != family:
@@ -71,12 +78,14 @@ def test_paper_tables(family):
             e = np.abs(U - truth)
             assert within_last_digit(e.max(), row[4]), (row, e.max())
             assert within_last_digit(e.mean(), row[5]), (row, e.mean())
+        elif kind == "fmm_linf":
+            assert within_last_digit(np.abs(U - truth).max(), row[4]), row
         elif kind == "fsm":
             assert O.fsm(p)[1] == int(row[4]), row
         else:
             method, what = kind.split("_")
-            V, st = (O.fmsm if method == "fmsm" else O.fhcm)(p, N // int(row[4]))
-            got = {"avs": st["AvS"], "mon": st["Mon%"]}.get(what)
+            V, st = (O.fmsm if method == "fmsm" else O.fhcm)(p, SIZE[family] // int(row[4]))
+            got = {"avs": st["AvS"], "mon": st["Mon%"], "avhr": st["AvHR"]}.get(what)
             if got is None:
                 got = ratios(V, U, truth)[what]
             assert within_last_digit(got, row[5]), (row, got)
