@@ -461,8 +461,9 @@ __device__ uint32_t claim(const Engine& e, int g) {
 // ascending for SW, x ascending / y descending for NW, ...) over the w x hgt
 // tile in LDS (pitch P, halo at row/column 0 and w+1/hgt+1; P*P + lane is a
 // per-lane dummy slot).  Returns (wave-uniform) bit 0: some node decreased;
-// bit 1: some node that decreased is now below one of its upwind neighbours
-// inside the tile.  Without bit 1 the tile is converged: every node was
+// bit 1 (bit 2): some node that decreased is now below its upwind neighbour
+// in x (in y) inside the tile.  Without bits 1 and 2 the tile is converged:
+// every node was
 // evaluated with its upwind neighbours' final values, and a node can only be
 // lowered further through a downwind neighbour that fell below it during the
 // sweep (a neighbour that stays at or above it cannot lower it, by the
@@ -500,7 +501,7 @@ __device__ uint32_t sweep_tile(T* tu, const T* td, int w, int hgt, int dir, int 
   int c = idx_t(-lane);
   T prev = tu[idx_t(-1)];
   T ev = tu[c + sx], nv = tu[c + rowstep], uo = tu[c], dl = td[c], hw = tu[c - sx];
-  bool changed = false, backflow = false;
+  bool changed = false, back_x = false, back_y = false;
 
   for (int d = 0; d < nsteps; ++d) {
     const int t = d - lane;
@@ -514,7 +515,8 @@ __device__ uint32_t sweep_tile(T* tu, const T* td, int w, int hgt, int dir, int 
     const T r = vmin(uo, U);
     const bool dec = valid && (r < uo);
     changed |= dec;
-    backflow |= dec && ((lane > 0 && r < wv) || (t > 0 && r < prev));
+    back_x |= dec && lane > 0 && r < wv;
+    back_y |= dec && t > 0 && r < prev;
     tu[valid ? c : dummy] = r;
     prev = valid ? r : prev;
     c = c1;
@@ -524,7 +526,7 @@ __device__ uint32_t sweep_tile(T* tu, const T* td, int w, int hgt, int dir, int 
     dl = dl1;
     hw = hw1;
   }
-  return (ballot(changed) ? 1u : 0u) | (ballot(backflow) ? 2u : 0u);
+  return (ballot(changed) ? 1u : 0u) | (ballot(back_x) ? 2u : 0u) | (ballot(back_y) ? 4u : 0u);
 }
 
 // Convergence test of the tile against its halo: true when no node would
@@ -931,6 +933,10 @@ __global__ __launch_bounds__(64) void k_solve(Engine e) {
     done1 = bcast(done1, 0);
     bool is_first = bcast(first, 0) != 0;
     if (e.dag && !done1) sides |= ordb & 0xFu;
+    // trace only: sweep history of the exact method, inflow sides and flags
+    unsigned long long hist = e.trace ? ((unsigned long long)sides << 60 | (unsigned long long)fl << 56 |
+                                         (unsigned long long)is_first << 55)
+                                      : 0ull;
     order_acquire();
     tick(e, &ctl->t_claim, &t0, lane);
     if (e.trace) tr[3] = wall_clock64();
@@ -979,21 +985,17 @@ __global__ __launch_bounds__(64) void k_solve(Engine e) {
         is_first = false;
         tick(e, &ctl->t_publish, &t0, lane);
       } else {
-        // exact: first the sweeps that start in a corner between two sides
-        // with inflow (one-axis inflow: both corners of each such side),
-        // then the other preferred directions, then the rest, each group in
-        // canonical order; after four sweeps the canonical loop; until
-        // converged.  The order changes the work, not the result.
+        // exact: the first sweep starts in a corner between two sides with
+        // inflow (one-axis inflow: a corner of such a side), else in a
+        // flagged direction.  Each further sweep reverses the axis along
+        // which the last sweep left a node below its upwind neighbour (both
+        // axes: x and y in turn); after eight sweeps the canonical cycle.
+        // Until converged.  The order changes the work, not the result.
         const uint32_t lead = fmsm_dirs(sides);
-        int sched[4], n = 0;
-        for (int d = 0; d < 4; ++d)
-          if (lead & (1u << d)) sched[n++] = d;
-        for (int d = 0; d < 4; ++d)
-          if ((fl & ~lead) & (1u << d)) sched[n++] = d;
-        for (int d = 0; d < 4; ++d)
-          if (!((fl | lead) & (1u << d))) sched[n++] = d;
+        const uint32_t pick = lead ? lead : fl;
+        int dir = pick ? __builtin_ctz(pick) : 0;
+        bool flip_x_next = true;
         for (int k = 0;; ++k) {
-          const int dir = k < 4 ? sched[k] : (k & 3);
           const uint32_t res = sweep_tile<T, P, false>(tu, td, B.w, B.hgt, dir, lane);
           const bool ch = res & 1u;
           if (ch) nsweeps++; else nchecks++;
@@ -1003,11 +1005,25 @@ __global__ __launch_bounds__(64) void k_solve(Engine e) {
             is_first = false;
             tick(e, &ctl->t_publish, &t0, lane);
           }
-          if (!(res & 2u)) break;  // no change, or no backflow: converged
+          if (e.trace && k < 11) hist |= (unsigned long long)(dir | (res << 2)) << (5 * k);
+          if (!(res & 6u)) break;  // no change, or no backflow: converged
           if (k > 4096) {  // a cell solve always terminates; guard anyway
             if (lane == 0) set_err(ctl, kErrGuard);
             aborted = true;
             break;
+          }
+          // direction bits: x reversed by dir ^ 3, y reversed by dir ^ 1
+          if (k >= 7) {
+            dir = (k + 1) & 3;
+          } else if ((res & 6u) == 6u) {
+            dir ^= flip_x_next ? 3 : 1;
+            flip_x_next = !flip_x_next;
+          } else if (res & 2u) {
+            dir ^= 3;
+            flip_x_next = false;
+          } else {
+            dir ^= 1;
+            flip_x_next = true;
           }
         }
         if (!e.eager) {
@@ -1018,12 +1034,17 @@ __global__ __launch_bounds__(64) void k_solve(Engine e) {
       }
       if (aborted) break;
       if (e.trace && !tr[2]) tr[2] = wall_clock64();
+      if constexpr (M != kFmsm) {
+        // publish has made the boundary visible: later neighbours start
+        // while the interior is written back
+        if (lane == 0 && e.dag && !done1) release_later(e, g, I, B, ordb);
+      }
       store_tile<T, P>(tu, I, B, lane);
       order_release();
       int again = 0;
       if (lane == 0) {
         if (e.dag && !done1) {
-          release_later(e, g, I, B, ordb);
+          if (M == kFmsm) release_later(e, g, I, B, ordb);
           done1 = 1;
         }
         uint32_t exp = run_state;
@@ -1070,7 +1091,7 @@ __global__ __launch_bounds__(64) void k_solve(Engine e) {
           t[3] = tr[1];
           t[4] = tr[2];
           t[5] = wall_clock64();
-          t[6] = __builtin_amdgcn_s_getreg(4 | (0 << 6) | (31 << 11));  // HW_ID
+          t[6] = hist;  // exact method: 5 bits per sweep (direction, result bits)
           t[7] = tr[3];
         }
       }
