@@ -204,6 +204,51 @@ int eik_serve_cancel(eik_server* s, uint64_t ticket);
    (results not yet collected are dropped). */
 int eik_serve_destroy(eik_server* s);
 
+/* Whole-grid sweeping: the prior methods of Section 2 -- Fast Sweeping
+   (Algorithm FSM: Gauss-Seidel sweeps over the whole grid in the four
+   alternating orderings, quadrant update of eq. Eik_discr) and Locking
+   Sweeping -- on the same device, one sweep at a time, with the early
+   termination of the Section 4 remark on stopping sweeping methods before
+   convergence (stop once the largest change of a sweep is at most a
+   threshold t*).  Every sweep equals the serial lexicographic sweep bit for
+   bit: tiles of 64 x 64 nodes go in anti-diagonal wavefronts of the sweep
+   direction, each tile swept by one wave.  Locking skips a tile whose last
+   sweep changed nothing and whose neighbours have not changed since (such a
+   tile is a fixed point of its halo, so skipping changes no value; node-level
+   locking as in Locking Sweeping does not pay on a SIMD machine). */
+typedef struct {
+  eik_dtype dtype;      /* EIK_F64 or EIK_F32 storage (FP32: FP64 two-sided branch) */
+  int32_t locking;      /* 0: Fast Sweeping; 1: Locking Sweeping (tile locks) */
+  int32_t max_sweeps;   /* >= 1; 0 = 65536 */
+  double threshold;     /* t*: stop after the first sweep whose largest change is
+                           <= t* (0: run to convergence); negative: stop only
+                           when a sweep changes nothing or at max_sweeps */
+  int32_t device_ptrs;  /* as in eik_opts */
+  void* stream;         /* hipStream_t; NULL = default stream */
+} eik_sweep_opts;
+
+typedef struct {
+  int32_t sweeps;         /* sweeps performed */
+  int32_t converged;      /* 1: the last sweep changed no node */
+  double seconds;         /* device time of the sweeps (preparation excluded) */
+  int64_t tiles_swept;    /* tile sweeps performed ... */
+  int64_t tiles_skipped;  /* ... and skipped by locking */
+} eik_sweep_stats;
+
+/* Solves one problem (arguments as eik_solve) by whole-grid sweeping.
+   max_change[k] (optional, max_sweeps entries) receives the largest decrease
+   of a node in sweep k (+inf when a node left +inf, 0 when none decreased),
+   n_changed[k] (optional) the number of nodes that decreased; entries past the
+   last sweep are left untouched.  Sweep k runs in ordering k mod 4: x and y
+   ascending, x ascending and y descending, both descending, x descending and
+   y ascending.  Errors as eik_solve (EINVAL before any device work on host
+   inputs; device-side validation of device inputs reports EINVAL with u_out
+   unspecified). */
+int eik_sweep_solve(int32_t nx, int32_t ny, double h, const void* F, const uint8_t* mask,
+                    int32_t nsrc, const int64_t* src, const double* q, void* u_out,
+                    const eik_sweep_opts* opts, double* max_change, int64_t* n_changed,
+                    eik_sweep_stats* stats);
+
 /* Message for the last failed call on this thread ("" if none). */
 const char* eik_last_error(void);
 

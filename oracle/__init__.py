@@ -76,6 +76,10 @@ def lib() -> ctypes.CDLL:
         L.orc_fmm.argtypes = [P, vp, vp, i64p]
         L.orc_fsm.argtypes = [P, vp, ctypes.POINTER(i32)]
         L.orc_lsm.argtypes = [P, vp, ctypes.POINTER(i32)]
+        L.orc_sweep_init.argtypes = [P, vp, vp]
+        L.orc_fsm_sweep.argtypes = [P, vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+        L.orc_lsm_sweep.argtypes = [P, vp, vp, i32, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_int64)]
         L.orc_jacobi.argtypes = [P, vp, ctypes.POINTER(i32)]
         L.orc_residual.restype = ctypes.c_double
         L.orc_residual.argtypes = [P, vp, vp]
@@ -145,6 +149,37 @@ def lsm(p: Problem):
     n = ctypes.c_int32(0)
     _check(lib().orc_lsm(p.c, V.ctypes.data, ctypes.byref(n)), "orc_lsm")
     return V, n.value
+
+
+def sweep_init(p: Problem, locking: bool = False):
+    """Start of the sweeping methods: V (q on exit nodes, +inf elsewhere)
+    and, for Locking Sweeping, the unlocked flags."""
+    V = np.empty((p.ny, p.nx))
+    unl = np.zeros((p.ny, p.nx), dtype=np.uint8) if locking else None
+    _check(lib().orc_sweep_init(p.c, V.ctypes.data, None if unl is None else unl.ctypes.data),
+           "orc_sweep_init")
+    return V, unl
+
+
+def fsm_sweep(p: Problem, V, sweep: int):
+    """Fast Sweeping's sweep number `sweep` over the whole grid, in place.
+    Returns (largest decrease, number of nodes that decreased)."""
+    assert V.dtype == np.float64 and V.flags.c_contiguous and V.shape == (p.ny, p.nx)
+    mx, cnt = ctypes.c_double(0.0), ctypes.c_int64(0)
+    _check(lib().orc_fsm_sweep(p.c, V.ctypes.data, int(sweep), ctypes.byref(mx), ctypes.byref(cnt)),
+           "orc_fsm_sweep")
+    return mx.value, cnt.value
+
+
+def lsm_sweep(p: Problem, V, unl, sweep: int):
+    """Locking Sweeping's sweep number `sweep`, in place (V and unlocked
+    flags).  Returns (largest decrease, number of nodes that decreased)."""
+    assert V.dtype == np.float64 and V.flags.c_contiguous and V.shape == (p.ny, p.nx)
+    assert unl.dtype == np.uint8 and unl.flags.c_contiguous and unl.shape == (p.ny, p.nx)
+    mx, cnt = ctypes.c_double(0.0), ctypes.c_int64(0)
+    _check(lib().orc_lsm_sweep(p.c, V.ctypes.data, unl.ctypes.data, int(sweep), ctypes.byref(mx),
+                               ctypes.byref(cnt)), "orc_lsm_sweep")
+    return mx.value, cnt.value
 
 
 def jacobi(p: Problem):

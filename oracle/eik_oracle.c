@@ -339,6 +339,43 @@ static int sweep_box(const grid_t* g, double* V, int d, int x0, int x1, int y0,
   return changed;
 }
 
+/* Change record of one sweep: largest decrease (+inf when a node leaves
+   +inf) and number of nodes that decreased. */
+static void note_change(double before, double after, double* mx, int64_t* cnt) {
+  if (!(after < before)) return;
+  double d = before == INF ? INF : before - after;
+  if (d > *mx) *mx = d;
+  (*cnt)++;
+}
+
+int orc_fsm_sweep(const orc_problem* p, double* V, int32_t sweep, double* max_change,
+                  int64_t* n_changed) {
+  grid_t g;
+  int rc = grid_init(&g, p);
+  if (rc) return rc;
+  int sx, sy;
+  double mx = 0.0;
+  int64_t cnt = 0;
+  dir_steps(sweep % 4, &sx, &sy);
+  for (int ii = 0; ii < g.nx; ++ii) {
+    int i = sx > 0 ? ii : g.nx - 1 - ii;
+    for (int jj = 0; jj < g.ny; ++jj) {
+      int j = sy > 0 ? jj : g.ny - 1 - jj;
+      long k = (long)j * g.nx + i;
+      if (!g.acc[k] || g.src[k]) continue;
+      double t = node_update(&g, V, i, j);
+      if (t < V[k]) {
+        note_change(V[k], t, &mx, &cnt);
+        V[k] = t;
+      }
+    }
+  }
+  if (max_change) *max_change = mx;
+  if (n_changed) *n_changed = cnt;
+  grid_free(&g);
+  return 0;
+}
+
 int orc_fsm(const orc_problem* p, double* V, int32_t* nsweeps) {
   grid_t g;
   int rc = grid_init(&g, p);
@@ -383,6 +420,69 @@ static int lsm_sweep_box(const grid_t* g, double* V, unsigned char* unl, int d,
     }
   }
   return changed;
+}
+
+/* Locking Sweeping's start: the accessible non-exit neighbours of exit
+   nodes are unlocked, every other node locked. */
+static void lsm_unlock_init(const grid_t* g, unsigned char* unl) {
+  static const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
+  if (g->n > 0) memset(unl, 0, (size_t)g->n);
+  for (long k = 0; k < g->n; ++k) {
+    if (!g->src[k]) continue;
+    int i = (int)(k % g->nx), j = (int)(k / g->nx);
+    for (int e = 0; e < 4; ++e) {
+      int a = i + di[e], b = j + dj[e];
+      if (a < 0 || b < 0 || a >= g->nx || b >= g->ny) continue;
+      long kk = (long)b * g->nx + a;
+      if (g->acc[kk] && !g->src[kk]) unl[kk] = 1;
+    }
+  }
+}
+
+int orc_sweep_init(const orc_problem* p, double* V, uint8_t* unlocked) {
+  grid_t g;
+  int rc = grid_init(&g, p);
+  if (rc) return rc;
+  init_values(&g, V);
+  if (unlocked) lsm_unlock_init(&g, unlocked);
+  grid_free(&g);
+  return 0;
+}
+
+int orc_lsm_sweep(const orc_problem* p, double* V, uint8_t* unlocked, int32_t sweep,
+                  double* max_change, int64_t* n_changed) {
+  grid_t g;
+  int rc = grid_init(&g, p);
+  if (rc) return rc;
+  static const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
+  int sx, sy;
+  double mx = 0.0;
+  int64_t cnt = 0;
+  dir_steps(sweep % 4, &sx, &sy);
+  for (int ii = 0; ii < g.nx; ++ii) {
+    int i = sx > 0 ? ii : g.nx - 1 - ii;
+    for (int jj = 0; jj < g.ny; ++jj) {
+      int j = sy > 0 ? jj : g.ny - 1 - jj;
+      long k = (long)j * g.nx + i;
+      if (!unlocked[k]) continue;
+      unlocked[k] = 0;
+      double t = node_update(&g, V, i, j);
+      if (t < V[k]) {
+        note_change(V[k], t, &mx, &cnt);
+        V[k] = t;
+        for (int e = 0; e < 4; ++e) {
+          int a = i + di[e], b = j + dj[e];
+          if (a < 0 || b < 0 || a >= g.nx || b >= g.ny) continue;
+          long kk = (long)b * g.nx + a;
+          if (g.acc[kk] && !g.src[kk] && V[kk] > V[k]) unlocked[kk] = 1;
+        }
+      }
+    }
+  }
+  if (max_change) *max_change = mx;
+  if (n_changed) *n_changed = cnt;
+  grid_free(&g);
+  return 0;
 }
 
 int orc_lsm(const orc_problem* p, double* V, int32_t* nsweeps) {

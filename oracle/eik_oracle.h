@@ -55,6 +55,20 @@ int orc_fmm(const orc_problem* p, double* V, int64_t* order, int64_t* naccepted)
 int orc_fsm(const orc_problem* p, double* V, int32_t* nsweeps);
 /* Locking Sweeping: the same sweeps, visiting only unlocked nodes. */
 int orc_lsm(const orc_problem* p, double* V, int32_t* nsweeps);
+/* One sweep at a time, for the early-termination study (Section 4 remark on
+   stopping sweeping methods before convergence).  orc_sweep_init sets V to q
+   on exit nodes and +inf elsewhere and, when unlocked is not NULL, unlocks
+   the accessible non-exit neighbours of exit nodes (Locking Sweeping's
+   start).  orc_fsm_sweep performs sweep number `sweep` (direction sweep mod
+   4, as in orc_fsm) over the whole grid; orc_lsm_sweep the same sweep of
+   Locking Sweeping, visiting only unlocked nodes.  Both report the largest
+   decrease of a node (+inf when a node leaves +inf; 0 when none decreased)
+   and the number of nodes that decreased. */
+int orc_sweep_init(const orc_problem* p, double* V, uint8_t* unlocked);
+int orc_fsm_sweep(const orc_problem* p, double* V, int32_t sweep, double* max_change,
+                  int64_t* n_changed);
+int orc_lsm_sweep(const orc_problem* p, double* V, uint8_t* unlocked, int32_t sweep,
+                  double* max_change, int64_t* n_changed);
 /* Value iteration V <- min(V, T V), all nodes at once, to a fixed point. */
 int orc_jacobi(const orc_problem* p, double* V, int32_t* niters);
 /* Fixed-point residual r_k = |T(V)_k - V_k| / V_k on accessible non-source

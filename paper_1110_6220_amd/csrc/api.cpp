@@ -85,7 +85,8 @@ static std::vector<DevBuf*> all_bufs(Workspace* w) {
                       &sv->slot, &sv->head, &sv->tail, &sv->inflight, &sv->cursor, &sv->ctl, &sv->inst})
       v.push_back(b);
   for (DevBuf* b : {&w->F, &w->u, &w->mask, &w->src, &w->q, &w->cF, &w->cmask, &w->cq, &w->cu,
-                    &w->cout, &w->crank, &w->fmm_spill, &w->F64, &w->u64, &w->ready_at, &w->trace,
+                    &w->cout, &w->crank, &w->fmm_spill, &w->sweep_stat, &w->sweep_dirty, &w->F64,
+                    &w->u64, &w->ready_at, &w->trace,
                     &w->trace_n, &w->wall_in, &w->wall_cnt})
     v.push_back(b);
   return v;
@@ -296,9 +297,9 @@ int validate_shape(const eik_problem& p) {
 
 // Sizes the solver's buffers for the instances in `inst` (cell0 filled in
 // here) and fills the engine arguments.
-static int setup_engine(Solver& sv, std::vector<Inst>& inst, int dtype, int method, int dag,
-                        double band, int window, int eager, uint64_t guard, uint64_t timeout,
-                        hipStream_t stream, Engine* out, DevBuf* instbuf = nullptr) {
+int setup_engine(Solver& sv, std::vector<Inst>& inst, int dtype, int method, int dag, double band,
+                 int window, int eager, uint64_t guard, uint64_t timeout, hipStream_t stream,
+                 Engine* out, DevBuf* instbuf) {
   DevBuf& ib = instbuf ? *instbuf : sv.inst;
   int64_t J = 0;
   for (auto& I : inst) {

@@ -162,6 +162,20 @@ hipError_t launch_coarse_inputs(const Engine& fine, const CoarseOut* co_dev, int
 constexpr int kFmmLdsBytesPerCell = 32;
 hipError_t launch_coarse_fmm(const Engine& fine, const CoarseOut* co_dev, int lds_cells,
                              const FmmSpill& spill, hipStream_t stream);
+// Whole-grid sweeping: tiles of kSweepTile x kSweepTile nodes (standard
+// tiling, Inst.s = kSweepTile).  One launch sweeps the tiles of anti-diagonal
+// `diag` (in the sweep's own order) of ordering `dir`; `tiles` = their count.
+constexpr int kSweepTile = 64;
+struct SweepArgs {
+  unsigned long long* stat;  // this sweep: [0] largest decrease (bits of a
+                             // non-negative double), [1] nodes decreased,
+                             // [2] tiles swept, [3] tiles skipped
+  uint8_t* dirty;            // per tile (locking): 1 = may change
+  int32_t dir, diag, locking, pad;
+};
+hipError_t launch_sweep_diag(const Engine& e, const SweepArgs& a, int tiles, hipStream_t stream);
+// locking: marks the tiles holding exit nodes and their neighbours
+hipError_t launch_sweep_seed(const Engine& e, int nsrc, uint8_t* dirty, hipStream_t stream);
 // Largest coarse grid the Fast Marching kernel keeps in LDS on this device.
 int coarse_fmm_lds_cells();
 // dependency counts and order bits from the coarse solutions; queues the

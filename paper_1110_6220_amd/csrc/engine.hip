@@ -482,9 +482,14 @@ __device__ uint32_t claim(const Engine& e, int g) {
 // value is the north value read for the step before.  min is v_min_f64, which
 // also maps the NaN that a = b = +inf produces to "no update", as the
 // oracle's explicit test does.
-template <typename T, int P, bool DIRECTIONAL>
-__device__ uint32_t sweep_tile(T* tu, const T* td, int w, int hgt, int dir, int lane) {
+// STATS: also the lane's largest decrease (+inf for a node that left +inf)
+// and number of decreased nodes, into *mx and *cnt.
+template <typename T, int P, bool DIRECTIONAL, bool STATS = false>
+__device__ uint32_t sweep_tile(T* tu, const T* td, int w, int hgt, int dir, int lane,
+                               double* mx = nullptr, int* cnt = nullptr) {
   lane = opaque_lane(lane);
+  double smx = 0.0;
+  int scnt = 0;
   const int sx = (dir == 0 || dir == 1) ? 1 : -1;
   const int sy = (dir == 0 || dir == 3) ? 1 : -1;
   const int rowstep = sy * P;
@@ -517,6 +522,11 @@ __device__ uint32_t sweep_tile(T* tu, const T* td, int w, int hgt, int dir, int 
     changed |= dec;
     back_x |= dec && lane > 0 && r < wv;
     back_y |= dec && t > 0 && r < prev;
+    if constexpr (STATS) {
+      const double chg = (double)uo - (double)r;  // +inf when uo is +inf
+      smx = dec && chg > smx ? chg : smx;
+      scnt += dec ? 1 : 0;
+    }
     tu[valid ? c : dummy] = r;
     prev = valid ? r : prev;
     c = c1;
@@ -525,6 +535,10 @@ __device__ uint32_t sweep_tile(T* tu, const T* td, int w, int hgt, int dir, int 
     nv = nv1;
     dl = dl1;
     hw = hw1;
+  }
+  if constexpr (STATS) {
+    *mx = smx;
+    *cnt = scnt;
   }
   return (ballot(changed) ? 1u : 0u) | (ballot(back_x) ? 2u : 0u) | (ballot(back_y) ? 4u : 0u);
 }
@@ -1577,6 +1591,77 @@ __global__ void k_dag_roots(Engine e) {
   }
 }
 
+// Whole-grid sweeping (Algorithm FSM; Locking Sweeping with tile locks):
+// the tiles of one anti-diagonal of sweep ordering `dir`, one wave each.
+// Tiles on one anti-diagonal share no side, and every tile upwind of a tile
+// lies on an earlier anti-diagonal (an earlier launch), so the launches of
+// one sweep reproduce the serial lexicographic sweep bit for bit.
+template <typename T, int S>
+__global__ __launch_bounds__(64) void k_sweep_diag(Engine e, SweepArgs a) {
+  constexpr int P = S + 2;
+  __shared__ T tu[P * P + 64];
+  __shared__ T td[P * P];
+  const int lane = threadIdx.x;
+  if (get_err(e.ctl)) return;
+  const Inst I = inst_at(e, 0);
+  const int sx = (a.dir == 0 || a.dir == 1) ? 1 : -1;
+  const int sy = (a.dir == 0 || a.dir == 3) ? 1 : -1;
+  const int ta = (a.diag - (I.ky - 1) > 0 ? a.diag - (I.ky - 1) : 0) + (int)blockIdx.x;
+  const int tb = a.diag - ta;
+  if (ta >= I.kx || tb < 0 || tb >= I.ky) return;
+  const int cx = sx > 0 ? ta : I.kx - 1 - ta;
+  const int cy = sy > 0 ? tb : I.ky - 1 - tb;
+  const int g = cy * I.kx + cx;
+  if (a.locking && !a.dirty[g]) {
+    if (lane == 0) atomic_add_relaxed(&a.stat[3], 1ull);
+    return;
+  }
+  const CellBox B = cell_box(I, g);
+  load_tile<T, P>(tu, td, I, B, lane, true);
+  double mx = 0.0;
+  int cnt = 0;
+  sweep_tile<T, P, false, true>(tu, td, B.w, B.hgt, a.dir, lane, &mx, &cnt);
+  for (int off = 32; off > 0; off >>= 1) {
+    const double om = __shfl_xor(mx, off, 64);
+    mx = om > mx ? om : mx;
+    cnt += __shfl_xor(cnt, off, 64);
+  }
+  if (cnt) store_tile<T, P>(tu, I, B, lane);
+  if (lane == 0) {
+    // a non-negative double orders like its bit pattern
+    __hip_atomic_fetch_max(&a.stat[0], __builtin_bit_cast(unsigned long long, mx), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    atomic_add_relaxed(&a.stat[1], (unsigned long long)cnt);
+    atomic_add_relaxed(&a.stat[2], 1ull);
+    if (a.locking) {
+      a.dirty[g] = cnt ? 1 : 0;
+      if (cnt) {
+        if (cx > 0) a.dirty[g - 1] = 1;
+        if (cx + 1 < I.kx) a.dirty[g + 1] = 1;
+        if (cy > 0) a.dirty[g - I.kx] = 1;
+        if (cy + 1 < I.ky) a.dirty[g + I.kx] = 1;
+      }
+    }
+  }
+}
+
+// Locking start: the tiles holding exit nodes and their neighbours may
+// change (every other tile is +inf with a +inf halo).
+__global__ void k_sweep_seed(Engine e, uint8_t* dirty) {
+  const Inst I = inst_at(e, 0);
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < I.nsrc; s += gridDim.x * blockDim.x) {
+    const long long k = I.src[s];
+    if (k < 0 || k >= (long long)I.nx * I.ny) continue;  // reported by k_check_sources
+    const int g = cell_of_node(I, (int)(k % I.nx), (int)(k / I.nx));
+    const int cx = g % I.kx, cy = g / I.kx;
+    dirty[g] = 1;
+    if (cx > 0) dirty[g - 1] = 1;
+    if (cx + 1 < I.kx) dirty[g + 1] = 1;
+    if (cy > 0) dirty[g - I.kx] = 1;
+    if (cy + 1 < I.ky) dirty[g + I.kx] = 1;
+  }
+}
+
 // Fixed-point residual max |T(u)_k - u_k| / u_k in FP64 over accessible,
 // non-exit nodes with finite u (inf where u is inf but T(u) is finite).
 template <typename T>
@@ -1725,6 +1810,17 @@ int coarse_fmm_lds_cells() {
     return lim / kFmmLdsBytesPerCell;
   }();
   return cells;
+}
+
+hipError_t launch_sweep_diag(const Engine& e, const SweepArgs& a, int tiles, hipStream_t stream) {
+  if (e.dtype == 0) hipLaunchKernelGGL((k_sweep_diag<double, kSweepTile>), dim3(tiles), dim3(64), 0, stream, e, a);
+  else hipLaunchKernelGGL((k_sweep_diag<float, kSweepTile>), dim3(tiles), dim3(64), 0, stream, e, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_seed(const Engine& e, int nsrc, uint8_t* dirty, hipStream_t stream) {
+  hipLaunchKernelGGL(k_sweep_seed, dim3(grid_for(nsrc, 256, 1024)), dim3(256), 0, stream, e, dirty);
+  return hipGetLastError();
 }
 
 hipError_t launch_coarse_fmm(const Engine& fine, const CoarseOut* co_dev, int lds_cells,

@@ -68,6 +68,7 @@ struct Workspace {
   DevBuf F, u, mask, src, q;          // staging of host inputs
   DevBuf cF, cmask, cq, cu, cout;     // coarse problems
   DevBuf crank, fmm_spill;            // coarse Fast Marching (FMSM)
+  DevBuf sweep_stat, sweep_dirty;     // whole-grid sweeping
   DevBuf F64, u64;                    // FP64 re-solve of FP32 problems
   DevBuf ready_at, trace, trace_n;    // diagnostic trace (EIK_TRACE)
   DevBuf wall_in, wall_cnt;           // wall density of masked problems
@@ -115,6 +116,11 @@ struct RunCtx {
   int share = 1;                 // the run gets 1/share of the default waves
   const double* density = nullptr;  // per problem: wall density, if known
 };
+// Sizes the solver's buffers for the instances in `inst` (cell0 filled in)
+// and fills the engine arguments.
+int setup_engine(Solver& sv, std::vector<Inst>& inst, int dtype, int method, int dag, double band,
+                 int window, int eager, uint64_t guard, uint64_t timeout, hipStream_t stream,
+                 Engine* out, DevBuf* instbuf = nullptr);
 eik_opts default_opts();
 int check_opts(const eik_opts& o);
 int std_cells(int n, int s);

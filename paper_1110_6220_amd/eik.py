@@ -24,7 +24,7 @@ SCHEDULES = {"auto": 0, "coarse": 1, "bands": 2, "fifo": 3}
 # Every function include/eik.h declares.
 EXPORTS = ("eik_solve", "eik_solve_batched", "eik_serve_create", "eik_serve_submit",
            "eik_serve_poll", "eik_serve_wait", "eik_serve_cancel", "eik_serve_destroy",
-           "eik_last_error")
+           "eik_sweep_solve", "eik_last_error")
 
 
 class EikError(RuntimeError):
@@ -67,6 +67,18 @@ class Problem(ctypes.Structure):
                 ("src", ctypes.c_void_p), ("q", ctypes.c_void_p), ("u_out", ctypes.c_void_p)]
 
 
+class SweepOpts(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int), ("locking", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
+                ("threshold", ctypes.c_double), ("device_ptrs", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
+
+
+class SweepStats(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("seconds", ctypes.c_double), ("tiles_swept", ctypes.c_int64),
+                ("tiles_skipped", ctypes.c_int64)]
+
+
 class ServeCfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int32),
                 ("lanes", ctypes.c_int32), ("opts", Opts)]
@@ -88,6 +100,8 @@ def _load() -> ctypes.CDLL:
     L.eik_serve_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(Stats)]
     L.eik_serve_cancel.argtypes = [vp, ctypes.c_uint64]
     L.eik_serve_destroy.argtypes = [vp]
+    L.eik_sweep_solve.argtypes = [i32, i32, ctypes.c_double, vp, vp, i32, vp, vp, vp,
+                                  ctypes.POINTER(SweepOpts), vp, vp, ctypes.POINTER(SweepStats)]
     L.eik_last_error.restype = ctypes.c_char_p
     return L
 
@@ -205,6 +219,26 @@ def eik_solve_batched(problems, *, dtype="f64", method="exact", cell=0, band=0.0
     _check(lib.eik_solve_batched(len(ps), arr, ctypes.byref(o), st))
     del keeps
     return outs, [s.as_dict() for s in st]
+
+
+def eik_sweep(F, h, src, q=None, mask=None, u_out=None, *, dtype="f64", locking=False,
+              max_sweeps=0, threshold=0.0):
+    """Whole-grid Fast Sweeping (locking=False) or Locking Sweeping with tile
+    locks (eik_sweep_solve of include/eik.h).  Returns (u, largest decrease
+    per sweep, decreased nodes per sweep, stats dict); the per-sweep arrays
+    hold one entry per sweep performed."""
+    p, keep, u_out, device = _marshal(F, h, src, q, mask, u_out, dtype)
+    o = SweepOpts(F64 if dtype == "f64" else F32, int(bool(locking)), int(max_sweeps),
+                  float(threshold), int(device), _stream_of(device))
+    cap = int(max_sweeps) if max_sweeps > 0 else 65536
+    mx = np.zeros(cap, dtype=np.float64)
+    cnt = np.zeros(cap, dtype=np.int64)
+    st = SweepStats()
+    _check(lib.eik_sweep_solve(p.nx, p.ny, p.h, p.F, p.mask, p.nsrc, p.src, p.q, p.u_out,
+                               ctypes.byref(o), mx.ctypes.data, cnt.ctypes.data, ctypes.byref(st)))
+    del keep
+    k = st.sweeps
+    return u_out, mx[:k].copy(), cnt[:k].copy(), {f: getattr(st, f) for f, _ in st._fields_}
 
 
 class Server:

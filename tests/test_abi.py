@@ -60,6 +60,33 @@ def test_invalid_arguments_are_rejected_before_device_work():
     assert (u == 7.0).all()  # untouched
 
 
+def test_sweep_arguments_are_rejected_before_device_work():
+    """Whole-grid sweeping: option and input checks that need no device."""
+    import numpy as np
+    from paper_1110_6220_amd import eik
+    F = np.ones((4, 4))
+    u = np.full((4, 4), 7.0)
+    bad = F.copy()
+    bad[2, 3] = -1.0
+    cases = [dict(F=F, src=[0], max_sweeps=-1), dict(F=F, src=[0], threshold=float("nan")),
+             dict(F=bad, src=[0]), dict(F=F, src=[16]), dict(F=F, src=[])]
+    for kw in cases:
+        F_, src = kw.pop("F"), kw.pop("src")
+        try:
+            eik.eik_sweep(F_, 0.1, src, u_out=u, **kw)
+        except eik.EikError as e:
+            assert e.code == eik.EIK_EINVAL, kw
+        else:
+            raise AssertionError(kw)
+    o = eik.SweepOpts(eik.F64, 2, 0, 0.0, 0, None)  # locking must be 0 or 1
+    src = np.array([0], dtype=np.int64)
+    st = eik.SweepStats()
+    rc = eik.lib.eik_sweep_solve(4, 4, 0.1, F.ctypes.data, None, 1, src.ctypes.data, None,
+                                 u.ctypes.data, o, None, None, st)
+    assert rc == eik.EIK_EINVAL
+    assert (u == 7.0).all()
+
+
 def test_serving_arguments_are_checked_before_device_work():
     """Server entry points reject missing handles and invalid configurations
     without touching a device."""
@@ -83,13 +110,15 @@ def test_serving_arguments_are_checked_before_device_work():
 
 
 def test_struct_layouts_match_header(tmp_path):
-    """The ctypes mirrors of eik_opts, eik_stats, eik_problem and
-    eik_serve_cfg have the sizes and field offsets the C header gives them
-    (compiled with the host compiler; no device needed)."""
+    """The ctypes mirrors of eik_opts, eik_stats, eik_problem,
+    eik_serve_cfg, eik_sweep_opts and eik_sweep_stats have the sizes and
+    field offsets the C header gives them (compiled with the host compiler;
+    no device needed)."""
     import subprocess
     from paper_1110_6220_amd import eik
     structs = {"eik_opts": eik.Opts, "eik_stats": eik.Stats, "eik_problem": eik.Problem,
-               "eik_serve_cfg": eik.ServeCfg}
+               "eik_serve_cfg": eik.ServeCfg, "eik_sweep_opts": eik.SweepOpts,
+               "eik_sweep_stats": eik.SweepStats}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "eik.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
