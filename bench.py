@@ -14,7 +14,15 @@ Beside the headline line's own fields it reports, from the same run:
   serving  Kruskal-maze requests (sides 129..2049, FP32 with the FP64 residual
            recheck) through the continuous-batching server under a 64 GiB
            budget: saturated throughput, then p50/p99 latency of Poisson
-           arrivals at half that request rate.
+           arrivals at half that request rate;
+  early_termination
+           the sweeping-method comparison of the Section 4 remark on stopping
+           sweeping methods early, on this GPU: the 41 x 41 checkerboard at
+           1312^2, FMSM with 41, 82 and 164 cells per side against whole-grid
+           Fast Sweeping and Locking Sweeping stopped after the sweep count at
+           which their error ratio R first reaches FMSM's (28 and 38 sweeps:
+           table tab:check41_sweepMaxChange B, which the oracle reproduces in
+           tests/test_oracle_sweeps.py), and run to convergence.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras]
 """
@@ -190,6 +198,7 @@ def main():
     if not args.no_extras:
         line["batched"] = bench_batched("f64", graph=not args.no_graph)
         line["serving"] = bench_serving(args.serve_requests)
+        line["early_termination"] = bench_early_termination()
     print(json.dumps(line), flush=True)
 
 
@@ -268,6 +277,55 @@ def bench_batched(dtype, reps=5, graph=True):
         "kernel_ms": st["kernel_seconds"] * 1e3, "AvHR": st["AvHR"], "AvS": st["AvS"],
         "accuracy": {"max_rel_err_vs_fmm_sampled": worst, "sampled": len(pick), "passed": passed},
     }
+
+
+def bench_early_termination(reps=3):
+    """Question 4 of the Section 4 remark on stopping sweeping methods early,
+    on this GPU (FP64, inputs resident on the device, median wall time of
+    `reps` calls, preparation included for every method)."""
+    import statistics
+
+    import torch
+
+    from paper_1110_6220_amd import eik, workloads
+    w = workloads.checkerboard_point(1312, 41)
+    d = _to_dev(w, "f64")
+    u = torch.empty_like(d["F"])
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        return statistics.median(ts) * 1e3, r
+
+    out = {"workload": "41 x 41 checkerboard (F = 1 / 2), 1312 x 1312, exit set at the centre, FP64",
+           "fmsm": [], "fsm": {}, "lsm": {}}
+    # FMSM's R on this grid (table tab:checker_41) and the first Fast Sweeping
+    # sweep whose R is at most that (table tab:check41_sweepMaxChange B)
+    for cells, r_fmsm, k in ((41, 3.3991, 28), (82, 1.7662, 38), (164, 1.7123, 38)):
+        ms, _ = timed(lambda: eik.eik_solve(d["F"], d["h"], d["src"], d["q"], None, u_out=u,
+                                            method="fmsm", cell=1312 // cells))
+        out["fmsm"].append({"cells_per_side": cells, "cell": 1312 // cells, "ms": ms,
+                            "R_fmsm": r_fmsm, "sweeps_to_same_R": k})
+    for k in (28, 38, 0):
+        for name, lock in (("fsm", False), ("lsm", True)):
+            ms, r = timed(lambda: eik.eik_sweep(d["F"], d["h"], d["src"], d["q"], None, u_out=u,
+                                                locking=lock, max_sweeps=k, threshold=-1.0 if k else 0.0))
+            key = str(k) if k else f"converged ({r[3]['sweeps']} sweeps)"
+            out[name][key] = {"ms": ms, "tiles_swept": r[3]["tiles_swept"],
+                              "tiles_skipped": r[3]["tiles_skipped"]}
+    ms, _ = timed(lambda: eik.eik_solve(d["F"], d["h"], d["src"], d["q"], None, u_out=u))
+    out["exact_ms"] = ms
+    best = min(f["ms"] for f in out["fmsm"][1:])
+    out["fmsm_82_vs_early_fsm_38"] = out["fsm"]["38"]["ms"] / out["fmsm"][1]["ms"]
+    out["fmsm_82_vs_early_lsm_38"] = out["lsm"]["38"]["ms"] / out["fmsm"][1]["ms"]
+    out["fmsm_best_of_82_164_ms"] = best
+    return out
 
 
 def _hop_depth(w):

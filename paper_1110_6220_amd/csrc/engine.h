@@ -159,7 +159,7 @@ hipError_t launch_coarse_inputs(const Engine& fine, const CoarseOut* co_dev, int
 // into co[k].u, acceptance ranks into co[k].rank.  Problems with at most
 // lds_cells coarse cells work in LDS (kFmmLdsBytesPerCell bytes per cell),
 // the others in `spill`.
-constexpr int kFmmLdsBytesPerCell = 32;
+constexpr int kFmmLdsBytesPerCell = 20;
 hipError_t launch_coarse_fmm(const Engine& fine, const CoarseOut* co_dev, int lds_cells,
                              const FmmSpill& spill, hipStream_t stream);
 // Whole-grid sweeping: tiles of kSweepTile x kSweepTile nodes (standard

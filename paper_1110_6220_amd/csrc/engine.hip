@@ -1383,66 +1383,91 @@ __global__ void k_coarse_sources(Engine e, const CoarseOut* co) {
 // front is accepted, one at a time, and its neighbours relaxed.  The four
 // neighbours of a cell are pairwise non-adjacent, so four lanes relax them at
 // once with the same result as one after the other.  The front is an
-// unordered array; each acceptance takes a wave-wide argmin over it.
-// Values, the front and the cell states live in LDS when the coarse grid
-// fits (lds_cells), else in the spill workspace.
+// unordered array of cells; each acceptance takes a wave-wide argmin over it.
+// Values, step sizes, cell states and the front live in LDS when the coarse
+// grid fits (lds_cells: 16-bit states and front entries, front values read
+// through the front's cell index), else in the spill workspace (32-bit, with
+// a copy of the front values next to the front).
 constexpr int kFmmFar = -1, kFmmObst = -2, kFmmAcc = -3;
 
-__device__ __forceinline__ double bcast_d(double v, int src_lane) {
+// Cross-lane moves within 16-lane rows (DPP) and reductions to a
+// wave-uniform minimum: min over quads, half rows, rows, then the four row
+// results read from lanes 0, 16, 32 and 48.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
   const long long b = __builtin_bit_cast(long long, v);
-  const int lo = bcast((int)b, src_lane), hi = bcast((int)(b >> 32), src_lane);
+  const int lo = dpp_i<CTRL>((int)b), hi = dpp_i<CTRL>((int)(b >> 32));
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
-
-// Wave-wide minimum of (v, c) in lexicographic order; the winning lane's
-// (v, c, slot) is returned, wave-uniform.
-__device__ __forceinline__ void wave_argmin(double& v, int& c, int& slot) {
-  for (int off = 32; off > 0; off >>= 1) {
-    const double ov = __shfl_xor(v, off, 64);
-    const int oc = __shfl_xor(c, off, 64), os = __shfl_xor(slot, off, 64);
-    if (ov < v || (ov == v && oc < c)) {
-      v = ov;
-      c = oc;
-      slot = os;
-    }
-  }
-  v = bcast_d(v, 0);
-  c = bcast(c, 0);
-  slot = bcast(slot, 0);
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+__device__ __forceinline__ double wave_min_d(double v) {
+  v = vmin(v, dpp_d<kDppXor1>(v));
+  v = vmin(v, dpp_d<kDppXor2>(v));
+  v = vmin(v, dpp_d<kDppHalfMirror>(v));
+  v = vmin(v, dpp_d<kDppMirror>(v));
+  return vmin(vmin(readlane_d(v, 0), readlane_d(v, 16)), vmin(readlane_d(v, 32), readlane_d(v, 48)));
+}
+__device__ __forceinline__ int wave_min_i(int v) {
+  v = min(v, dpp_i<kDppXor1>(v));
+  v = min(v, dpp_i<kDppXor2>(v));
+  v = min(v, dpp_i<kDppHalfMirror>(v));
+  v = min(v, dpp_i<kDppMirror>(v));
+  return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+             min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
 
-__global__ __launch_bounds__(64) void k_coarse_fmm(Engine e, const CoarseOut* co, int lds_cells,
-                                                   FmmSpill spill) {
-  extern __shared__ __align__(16) unsigned char fmm_lds[];
-  const int k = blockIdx.x;
-  const Inst I = inst_at(e, k);
-  const CoarseOut C = co[k];
-  const int lane = threadIdx.x, kx = I.kx, ky = I.ky, J = kx * ky;
-  const double INF = __builtin_huge_val();
-  const double hc = (double)I.s * I.h;
-  double *V, *dl, *fv;
-  int *st, *fi;
-  const bool in_lds = J <= lds_cells;
-  if (in_lds) {
-    V = reinterpret_cast<double*>(fmm_lds);
-    dl = V + J;
-    fv = dl + J;
-    st = reinterpret_cast<int*>(fv + J);
-    fi = st + J;
-  } else {
-    V = C.u;
-    dl = spill.delta + I.cell0;
-    fv = spill.fval + I.cell0;
-    st = spill.st + I.cell0;
-    fi = spill.fidx + I.cell0;
+// Wave-wide minimum of the lanes' (v, c) in lexicographic order (values are
+// never NaN; lanes without an entry hold (+inf, INT_MAX)); returns the
+// winning lane's (v, c, slot), wave-uniform.
+__device__ __forceinline__ void wave_argmin(double& v, int& c, int& slot, int lane) {
+  const double vm = wave_min_d(v);
+  const unsigned long long tie = ballot(v == vm);
+  int win = __builtin_ctzll(tie);
+  if (tie & (tie - 1)) {  // equal values: the smallest cell index
+    const bool in = (tie >> lane) & 1ull;
+    const int cm = wave_min_i(in ? c : 0x7fffffff);
+    win = __builtin_ctzll(ballot(in && c == cm));
   }
+  v = vm;
+  c = __builtin_amdgcn_readlane(c, win);
+  slot = __builtin_amdgcn_readlane(slot, win);
+}
+
+// FV: the spill layout (global memory, front values kept beside the front).
+// In the LDS layout every access inside the acceptance loop is an LDS access
+// of this one wave, which the LDS performs in order, so lanes see each
+// other's writes without waiting (the acceptance ranks go to global memory
+// and are never read back); the spill layout waits for its global accesses.
+template <typename IdxT, bool FV>
+__device__ void coarse_fmm(const CoarseOut& C, int kx, int ky, double hc, int lane, double* V,
+                           double* dl, double* fv, IdxT* st, IdxT* fi) {
+  const int J = kx * ky;
+  const double INF = __builtin_huge_val();
+  auto fval = [&](int t) { return FV ? fv[t] : V[fi[t]]; };
+  auto step_sync = [] {
+    if constexpr (FV) {
+      __syncthreads();
+    } else {
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
+  };
   for (int c = lane; c < J; c += 64) {
     const bool acc = C.mask[c] != 0;
     const double q = C.q[c];
     const bool exit = acc && q < INF;
     V[c] = exit ? q : INF;
     dl[c] = acc ? hc / C.F[c] : INF;
-    st[c] = !acc ? kFmmObst : exit ? kFmmAcc : kFmmFar;
+    st[c] = (IdxT)(!acc ? kFmmObst : exit ? kFmmAcc : kFmmFar);
     C.rank[c] = J + c;  // cells the front never reaches: after all others, by index
   }
   __syncthreads();
@@ -1455,8 +1480,8 @@ __global__ __launch_bounds__(64) void k_coarse_fmm(Engine e, const CoarseOut* co
     if (is) {
       const int slot = J - 1 - ns - (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
                                                                   __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-      fv[slot] = V[c];
-      fi[slot] = c;
+      if constexpr (FV) fv[slot] = V[c];
+      fi[slot] = (IdxT)c;
     }
     ns += __builtin_popcountll(m);
   }
@@ -1466,73 +1491,105 @@ __global__ __launch_bounds__(64) void k_coarse_fmm(Engine e, const CoarseOut* co
     const bool exits = rs > 0;
     const int lo = exits ? J - rs : 0, hi = exits ? J : nf;
     if (lo == hi) break;
-    // accept the (value, index) minimum of [lo, hi)
+    // accept the (value, index) minimum of [lo, hi); each lane takes four of
+    // its slots per round so that their loads are in flight together
     double bv = INF;
     int bc = 0x7fffffff, bs = -1;
-    for (int t = lo + lane; t < hi; t += 64) {
-      const double v = fv[t];
-      const int c = fi[t];
-      if (v < bv || (v == bv && c < bc)) {
-        bv = v;
-        bc = c;
-        bs = t;
+    for (int t0 = lo + lane; t0 < hi; t0 += 256) {
+      int cq[4];
+      double vq[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) cq[u] = t0 + 64 * u < hi ? (int)fi[t0 + 64 * u] : 0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) vq[u] = t0 + 64 * u < hi ? (FV ? fv[t0 + 64 * u] : V[cq[u]]) : INF;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const bool take = t0 + 64 * u < hi && (vq[u] < bv || (vq[u] == bv && cq[u] < bc));
+        bv = take ? vq[u] : bv;
+        bc = take ? cq[u] : bc;
+        bs = take ? t0 + 64 * u : bs;
       }
     }
-    wave_argmin(bv, bc, bs);
+    wave_argmin(bv, bc, bs, lane);
     if (lane == 0) {
       if (exits) {  // the exit list shrinks from below
-        fv[bs] = fv[lo];
+        if constexpr (FV) fv[bs] = fv[lo];
         fi[bs] = fi[lo];
       } else {
         const int last = nf - 1;
         if (bs != last) {
           const int mv = fi[last];
-          fv[bs] = fv[last];
-          fi[bs] = mv;
-          st[mv] = bs;
+          if constexpr (FV) fv[bs] = fv[last];
+          fi[bs] = (IdxT)mv;
+          st[mv] = (IdxT)bs;
         }
-        st[bc] = kFmmAcc;
+        st[bc] = (IdxT)kFmmAcc;
       }
-      C.rank[bc] = na;
+      to_global(C.rank)[bc] = na;  // a global store: LDS waits do not wait for it
     }
     if (exits) rs--;
     else nf--;
     na++;
-    __syncthreads();
+    step_sync();
     // relax the four neighbours W, E, S, N of the accepted cell
     const int cx = bc % kx, cy = bc / kx;
     const int nx = cx + (lane == 0 ? -1 : lane == 1 ? 1 : 0);
     const int ny = cy + (lane == 2 ? -1 : lane == 3 ? 1 : 0);
-    bool live = lane < 4 && nx >= 0 && nx < kx && ny >= 0 && ny < ky;
-    const int nb = ny * kx + nx;
-    const int sn = live ? st[nb] : kFmmObst;
-    live = live && sn != kFmmObst && sn != kFmmAcc;
+    const bool inb = lane < 4 && nx >= 0 && nx < kx && ny >= 0 && ny < ky;
+    // every load of the relaxation at once (indices outside the grid are
+    // replaced by the accepted cell's and their values by +inf)
+    const int nb = inb ? ny * kx + nx : bc;
+    const int sn = inb ? (int)st[nb] : kFmmObst;
+    const double vW = V[inb && nx > 0 ? nb - 1 : bc], vE = V[inb && nx + 1 < kx ? nb + 1 : bc];
+    const double vS = V[inb && ny > 0 ? nb - kx : bc], vN = V[inb && ny + 1 < ky ? nb + kx : bc];
+    const double dn = dl[nb], v0 = V[nb];
+    const bool live = inb && sn != kFmmObst && sn != kFmmAcc;
     double vn = INF;
     if (live) {
-      const double uW = nx > 0 ? V[nb - 1] : INF, uE = nx + 1 < kx ? V[nb + 1] : INF;
-      const double uS = ny > 0 ? V[nb - kx] : INF, uN = ny + 1 < ky ? V[nb + kx] : INF;
+      const double uW = nx > 0 ? vW : INF, uE = nx + 1 < kx ? vE : INF;
+      const double uS = ny > 0 ? vS : INF, uN = ny + 1 < ky ? vN : INF;
       const double a = uW < uE ? uW : uE, b = uS < uN ? uS : uN;
-      const double t = (a < b ? a : b) == INF ? INF : local_update(a, b, dl[nb]);
-      vn = V[nb];
+      const double t = (a < b ? a : b) == INF ? INF : local_update(a, b, dn);
+      vn = v0;
       if (t < vn) {
         vn = t;
         V[nb] = t;
       }
-      if (sn >= 0) fv[sn] = vn;
+      if constexpr (FV)
+        if (sn >= 0) fv[sn] = vn;
     }
     const bool push = live && sn == kFmmFar;
     const unsigned long long m = ballot(push);
     if (push) {
       const int slot = nf + (int)__builtin_amdgcn_mbcnt_lo((unsigned)m, 0u);
-      fv[slot] = vn;
-      fi[slot] = nb;
-      st[nb] = slot;
+      if constexpr (FV) fv[slot] = vn;
+      fi[slot] = (IdxT)nb;
+      st[nb] = (IdxT)slot;
     }
     nf += __builtin_popcountll(m);
-    __syncthreads();
+    step_sync();
   }
-  if (in_lds)
+}
+
+__global__ __launch_bounds__(64) void k_coarse_fmm(Engine e, const CoarseOut* co, int lds_cells,
+                                                   FmmSpill spill) {
+  extern __shared__ __align__(16) unsigned char fmm_lds[];
+  const int k = blockIdx.x;
+  const Inst I = inst_at(e, k);
+  const CoarseOut C = co[k];
+  const int lane = threadIdx.x, J = I.kx * I.ky;
+  const double hc = (double)I.s * I.h;
+  if (J <= lds_cells) {  // lds_cells < 2^15: states and front entries fit 16 bits
+    double* V = reinterpret_cast<double*>(fmm_lds);
+    double* dl = V + J;
+    int16_t* st = reinterpret_cast<int16_t*>(dl + J);
+    int16_t* fi = st + J;
+    coarse_fmm<int16_t, false>(C, I.kx, I.ky, hc, lane, V, dl, nullptr, st, fi);
     for (int c = lane; c < J; c += 64) C.u[c] = V[c];
+  } else {
+    coarse_fmm<int32_t, true>(C, I.kx, I.ky, hc, lane, C.u, spill.delta + I.cell0,
+                              spill.fval + I.cell0, spill.st + I.cell0, spill.fidx + I.cell0);
+  }
 }
 
 // Order of the cells: exit cells first by (q, index), then by (coarse value,
@@ -1807,7 +1864,8 @@ int coarse_fmm_lds_cells() {
         hipFuncSetAttribute(reinterpret_cast<const void*>(&k_coarse_fmm),
                             hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess)
       lim = 65536;
-    return lim / kFmmLdsBytesPerCell;
+    const int c = lim / kFmmLdsBytesPerCell;
+    return c < 32767 ? c : 32767;
   }();
   return cells;
 }

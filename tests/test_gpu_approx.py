@@ -51,11 +51,13 @@ def fmsm_cases():
     cases += [(W.sinusoid_point(352, 0.5, 10.0), 16), (W.sinusoid_point(704, 0.5, 10.0), 32),
               (W.sinusoid_boundary(352, 0.5, 10.0), 16), (W.sinusoid_boundary(704, 0.99, 1.0), 32),
               (W.sinusoid_boundary(1408, 0.5, 10.0), 64),
-              (W.checkerboard_point(352, 11), 16), (W.checkerboard_point(656, 41), 8)]
+              (W.checkerboard_point(352, 11), 16), (W.checkerboard_point(656, 41), 8),
+              # 164^2 coarse cells: the coarse Fast Marching works outside LDS
+              (W.checkerboard_point(1312, 41), 8)]
     return cases
 
 
-@pytest.mark.parametrize("case", range(16))
+@pytest.mark.parametrize("case", range(17))
 def test_fmsm_bitwise(eik, case):
     w, s = fmsm_cases()[case]
     V, info = O.fmsm(O.Problem.from_workload(w), s)
