@@ -627,9 +627,12 @@ __device__ __forceinline__ CellBox cell_box(const Inst& I, int local) {
 // (one element per row) go through registers.  One wait at the end.
 // fresh: the cell has never been processed and holds no exit node, so its
 // interior values are all +inf and only delta and the halo are read.
+// part / nparts: this wave loads rows r with (r + 1) mod nparts == part and,
+// as part 0, the west and east halo columns (several waves of a workgroup
+// share one tile load).
 template <typename T, int P>
 __device__ void load_tile(T* tu, T* td, const Inst& I, const CellBox& B, int lane,
-                          bool with_interior, bool fresh = false) {
+                          bool with_interior, bool fresh = false, int part = 0, int nparts = 1) {
   lane = opaque_lane(lane);
   using lds_ptr = __attribute__((address_space(3))) void*;
   constexpr int kCohPolicy = 16;             // sc1
@@ -646,6 +649,7 @@ __device__ void load_tile(T* tu, T* td, const Inst& I, const CellBox& B, int lan
       r = B.hgt - 1;  // skip to the north halo row
       continue;
     }
+    if (nparts > 1 && (r + 1) % nparts != part) continue;
     const int j = B.y0 + r;
     T* lu = tu + (r + 1) * P + 1;
     T* ld = td + (r + 1) * P + 1;
@@ -675,7 +679,7 @@ __device__ void load_tile(T* tu, T* td, const Inst& I, const CellBox& B, int lan
     }
     if (skip_u && lane < B.w) lu[lane] = INF;
   }
-  {
+  if (part == 0) {
     const gptr<const T> u = to_global(static_cast<const T*>(I.u));
     const gptr<const T> dl = to_global(static_cast<const T*>(I.delta));
     const int jr = B.y0 + (lane < B.hgt ? lane : 0);
@@ -697,13 +701,23 @@ __device__ void load_tile(T* tu, T* td, const Inst& I, const CellBox& B, int lan
 
 // Writes the whole tile back to u.
 template <typename T, int P>
-__device__ void store_tile(const T* tu, const Inst& I, const CellBox& B, int lane) {
+__device__ void store_tile(const T* tu, const Inst& I, const CellBox& B, int lane, int part = 0,
+                           int nparts = 1) {
   lane = opaque_lane(lane);
   T* u = static_cast<T*>(I.u);
   if (lane < B.w)
-    for (int r = 0; r < B.hgt; ++r)
+    for (int r = part; r < B.hgt; r += nparts)
       st_coh(u + (size_t)(B.y0 + r) * I.nx + B.x0 + lane, tu[(r + 1) * P + lane + 1]);
 }
+
+// Work that the helper waves of a multi-wave workgroup share with wave 0:
+// op 0 = leave, 1 = load cell g's tile (flags bit 0 with_interior, bit 1
+// fresh), 2 = store cell g's tile.  Wave 0 writes the job, then every wave
+// passes barrier A, does its share, waits for its own transfers and passes
+// barrier B; each job is exactly one A-B pair for every wave (leave: A only).
+struct TileJob {
+  int op, g, flags;
+};
 
 // Speed at y_i for eq. cell_value: at the node (integer offset) or the mean of
 // the two straddling accessible nodes (half-integer offset); 0 = undefined.
@@ -896,14 +910,62 @@ __device__ void release_later(const Engine& e, int g, const Inst& I, const CellB
   }
 }
 
-template <typename T, int S, int M>
-__global__ __launch_bounds__(64) void k_solve(Engine e) {
+// NW waves per workgroup: wave 0 runs the worker; with NW > 1 (single
+// problems, where compute units are plentiful) waves 1..NW-1 only share the
+// tile loads and stores, which one wave issues at one row transfer per
+// ~70-90 cycles.
+constexpr int kSolveWaves1 = 4;  // waves per worker for single problems
+
+template <typename T, int S, int M, int NW>
+__global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
   constexpr int P = S + 2;
   __shared__ T tu[P * P + 64];  // tile + per-lane dummy slots
   __shared__ T td[P * P];
-  const int lane = threadIdx.x;
+  __shared__ TileJob job;
+  const int lane = threadIdx.x & 63;
+  if constexpr (NW > 1) {
+    if (threadIdx.x >= 64) {  // helper wave
+      const int part = threadIdx.x >> 6;
+      for (;;) {
+        __syncthreads();  // A
+        const int op = __builtin_amdgcn_readfirstlane(job.op);
+        const int g = __builtin_amdgcn_readfirstlane(job.g);
+        const int flags = __builtin_amdgcn_readfirstlane(job.flags);
+        if (op == 0) return;
+        const Inst I = inst_of(e, g);
+        const CellBox B = cell_box(I, g - I.cell0);
+        if (op == 1) {
+          load_tile<T, P>(tu, td, I, B, lane, (flags & 1) != 0, (flags & 2) != 0, part, NW);
+        } else {
+          store_tile<T, P>(tu, I, B, lane, part, NW);
+          __builtin_amdgcn_s_waitcnt(0);
+        }
+        __syncthreads();  // B
+      }
+    }
+  }
+  auto tile_load = [&](const Inst& I, const CellBox& B, int g, bool with_interior, bool fresh) {
+    if constexpr (NW == 1) {
+      load_tile<T, P>(tu, td, I, B, lane, with_interior, fresh);
+    } else {
+      if (lane == 0) job = TileJob{1, g, (with_interior ? 1 : 0) | (fresh ? 2 : 0)};
+      __syncthreads();  // A
+      load_tile<T, P>(tu, td, I, B, lane, with_interior, fresh, 0, NW);
+      __syncthreads();  // B: every part has landed
+    }
+  };
+  auto tile_store = [&](const Inst& I, const CellBox& B, int g) {
+    if constexpr (NW == 1) {
+      store_tile<T, P>(tu, I, B, lane);
+    } else {
+      if (lane == 0) job = TileJob{2, g, 0};
+      __syncthreads();  // A
+      store_tile<T, P>(tu, I, B, lane, 0, NW);
+      __syncthreads();  // B: the helpers' stores have completed
+    }
+  };
   Ctl* ctl = e.ctl;
-  if (get_err(ctl)) return;
+  if (!get_err(ctl)) {
   int backoff = 0;
   unsigned long long t0 = e.profile ? wall_clock64() : 0ull;
   unsigned long long nsweeps = 0, nchecks = 0;  // this wave's totals
@@ -955,7 +1017,7 @@ __global__ __launch_bounds__(64) void k_solve(Engine e) {
     tick(e, &ctl->t_claim, &t0, lane);
     if (e.trace) tr[3] = wall_clock64();
     // a cell's interior is written only by its own processing
-    load_tile<T, P>(tu, td, I, B, lane, true, e.dag && is_first && !(ordb & kOrdSource));
+    tile_load(I, B, g, true, e.dag && is_first && !(ordb & kOrdSource));
     T pub[4];
     pub[0] = lane < B.hgt ? tu[(lane + 1) * P + 1] : inf_v<T>();
     pub[1] = lane < B.hgt ? tu[(lane + 1) * P + B.w] : inf_v<T>();
@@ -1053,7 +1115,7 @@ __global__ __launch_bounds__(64) void k_solve(Engine e) {
         // while the interior is written back
         if (lane == 0 && e.dag && !done1) release_later(e, g, I, B, ordb);
       }
-      store_tile<T, P>(tu, I, B, lane);
+      tile_store(I, B, g);
       order_release();
       int again = 0;
       if (lane == 0) {
@@ -1118,6 +1180,11 @@ __global__ __launch_bounds__(64) void k_solve(Engine e) {
     if (!get_err(ctl) && ld64(&ctl->active) != 0ull) set_err(ctl, kErrDeadline);
     atomic_add_relaxed(&ctl->sweeps, nsweeps);
     atomic_add_relaxed(&ctl->checks, nchecks);
+  }
+  }  // !get_err at entry
+  if constexpr (NW > 1) {  // release the helper waves
+    if (lane == 0) job.op = 0;
+    __syncthreads();  // A
   }
 }
 
@@ -1792,11 +1859,17 @@ hipError_t launch_prepare(const Engine& e, int64_t max_nodes, hipStream_t stream
   return hipGetLastError();
 }
 
+template <typename T, int M, int NW>
+static void launch_solve_w(const Engine& e, dim3 g, int tile, hipStream_t stream) {
+  if (tile <= 16) hipLaunchKernelGGL((k_solve<T, 16, M, NW>), g, dim3(64 * NW), 0, stream, e);
+  else if (tile <= 32) hipLaunchKernelGGL((k_solve<T, 32, M, NW>), g, dim3(64 * NW), 0, stream, e);
+  else hipLaunchKernelGGL((k_solve<T, 64, M, NW>), g, dim3(64 * NW), 0, stream, e);
+}
+// single problems: four waves per worker share the tile transfers
 template <typename T, int M>
 static void launch_solve_t(const Engine& e, dim3 g, int tile, hipStream_t stream) {
-  if (tile <= 16) hipLaunchKernelGGL((k_solve<T, 16, M>), g, dim3(64), 0, stream, e);
-  else if (tile <= 32) hipLaunchKernelGGL((k_solve<T, 32, M>), g, dim3(64), 0, stream, e);
-  else hipLaunchKernelGGL((k_solve<T, 64, M>), g, dim3(64), 0, stream, e);
+  if (e.ninst == 1) launch_solve_w<T, M, kSolveWaves1>(e, g, tile, stream);
+  else launch_solve_w<T, M, 1>(e, g, tile, stream);
 }
 
 template <typename T>
@@ -1811,11 +1884,11 @@ static int occupancy_t(int tile) {
   int n = 0;
   hipError_t err;
   if (tile <= 16)
-    err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_solve<T, 16, M>, 64, 0);
+    err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_solve<T, 16, M, 1>, 64, 0);
   else if (tile <= 32)
-    err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_solve<T, 32, M>, 64, 0);
+    err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_solve<T, 32, M, 1>, 64, 0);
   else
-    err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_solve<T, 64, M>, 64, 0);
+    err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_solve<T, 64, M, 1>, 64, 0);
   return err == hipSuccess && n > 0 ? n : 1;
 }
 
