@@ -196,8 +196,11 @@ def main():
         },
     }
     if not args.no_extras:
+        print("[bench] headline done; batched", file=sys.stderr, flush=True)
         line["batched"] = bench_batched("f64", graph=not args.no_graph)
+        print("[bench] batched done; serving", file=sys.stderr, flush=True)
         line["serving"] = bench_serving(args.serve_requests)
+        print("[bench] serving done; early termination", file=sys.stderr, flush=True)
         line["early_termination"] = bench_early_termination()
     print(json.dumps(line), flush=True)
 
