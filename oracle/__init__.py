@@ -44,6 +44,14 @@ class _Problem(ctypes.Structure):
     ]
 
 
+class _Problem3(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("h", ctypes.c_double), ("F", ctypes.c_void_p), ("mask", ctypes.c_void_p),
+        ("nsrc", ctypes.c_int32), ("src", ctypes.c_void_p), ("q", ctypes.c_void_p),
+    ]
+
+
 class CellStats(ctypes.Structure):
     _fields_ = [
         ("cells", ctypes.c_int64), ("removals", ctypes.c_int64), ("sweeps", ctypes.c_int64),
@@ -76,6 +84,14 @@ def lib() -> ctypes.CDLL:
         L.orc_fmm.argtypes = [P, vp, vp, i64p]
         L.orc_fsm.argtypes = [P, vp, ctypes.POINTER(i32)]
         L.orc_lsm.argtypes = [P, vp, ctypes.POINTER(i32)]
+        P3 = ctypes.POINTER(_Problem3)
+        L.orc3_update.restype = ctypes.c_double
+        L.orc3_update.argtypes = [ctypes.c_double] * 4
+        L.orc3_fmm.argtypes = [P3, vp, vp, ctypes.POINTER(ctypes.c_int64)]
+        L.orc3_fsm.argtypes = [P3, vp, ctypes.POINTER(i32)]
+        L.orc3_jacobi.argtypes = [P3, vp, ctypes.POINTER(i32)]
+        L.orc3_residual.restype = ctypes.c_double
+        L.orc3_residual.argtypes = [P3, vp, vp]
         L.orc_sweep_init.argtypes = [P, vp, vp]
         L.orc_fsm_sweep.argtypes = [P, vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         L.orc_lsm_sweep.argtypes = [P, vp, vp, i32, ctypes.POINTER(ctypes.c_double),
@@ -149,6 +165,68 @@ def lsm(p: Problem):
     n = ctypes.c_int32(0)
     _check(lib().orc_lsm(p.c, V.ctypes.data, ctypes.byref(n)), "orc_lsm")
     return V, n.value
+
+
+class Problem3:
+    """A 3-D boundary-value problem; F has shape (nz, ny, nx) (x fastest)."""
+
+    def __init__(self, F, h, src, q=None, mask=None):
+        F = np.ascontiguousarray(F, dtype=np.float64)
+        self.nz, self.ny, self.nx = F.shape
+        self.h = float(h)
+        self.F = F
+        self.mask = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+        self.src = np.ascontiguousarray(np.atleast_1d(src), dtype=np.int64)
+        self.q = None if q is None else np.ascontiguousarray(np.atleast_1d(q), dtype=np.float64)
+        self._c = _Problem3(
+            self.nx, self.ny, self.nz, self.h, self.F.ctypes.data,
+            None if self.mask is None else self.mask.ctypes.data,
+            len(self.src), self.src.ctypes.data,
+            None if self.q is None else self.q.ctypes.data)
+
+    @classmethod
+    def from_workload(cls, w: dict) -> "Problem3":
+        return cls(w["F"], w["h"], w["src"], w.get("q"), w.get("mask"))
+
+    @property
+    def c(self):
+        return ctypes.byref(self._c)
+
+
+def update3(a: float, b: float, c: float, delta: float) -> float:
+    return lib().orc3_update(a, b, c, delta)
+
+
+def fmm3(p: Problem3, want_order: bool = False):
+    V = np.empty((p.nz, p.ny, p.nx))
+    order = np.empty(p.nx * p.ny * p.nz, dtype=np.int64) if want_order else None
+    na = ctypes.c_int64(0)
+    _check(lib().orc3_fmm(p.c, V.ctypes.data, None if order is None else order.ctypes.data,
+                          ctypes.byref(na)), "orc3_fmm")
+    return (V, order[: na.value]) if want_order else V
+
+
+def fsm3(p: Problem3):
+    V = np.empty((p.nz, p.ny, p.nx))
+    n = ctypes.c_int32(0)
+    _check(lib().orc3_fsm(p.c, V.ctypes.data, ctypes.byref(n)), "orc3_fsm")
+    return V, n.value
+
+
+def jacobi3(p: Problem3):
+    V = np.empty((p.nz, p.ny, p.nx))
+    n = ctypes.c_int32(0)
+    _check(lib().orc3_jacobi(p.c, V.ctypes.data, ctypes.byref(n)), "orc3_jacobi")
+    return V, n.value
+
+
+def residual3(p: Problem3, V):
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    r = np.empty_like(V)
+    m = lib().orc3_residual(p.c, V.ctypes.data, r.ctypes.data)
+    if m < 0:
+        raise ValueError("orc3_residual: invalid problem")
+    return m, r
 
 
 def sweep_init(p: Problem, locking: bool = False):

@@ -1069,3 +1069,260 @@ done:
   grid_free(&g);
   return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Three dimensions: the same methods on a 3-D grid with six neighbours      */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  int nx, ny, nz;
+  long n;
+  double* delta;
+  unsigned char* acc;
+  unsigned char* src;
+  double* qv;
+} grid3_t;
+
+static void grid3_free(grid3_t* g) {
+  free(g->delta);
+  free(g->acc);
+  free(g->src);
+  free(g->qv);
+}
+
+static int grid3_init(grid3_t* g, const orc3_problem* p) {
+  memset(g, 0, sizeof *g);
+  if (!p || p->nx < 1 || p->ny < 1 || p->nz < 1 || !(p->h > 0.0) || !isfinite(p->h) || !p->F ||
+      p->nsrc < 1 || !p->src)
+    return -1;
+  g->nx = p->nx;
+  g->ny = p->ny;
+  g->nz = p->nz;
+  g->n = (long)p->nx * p->ny * p->nz;
+  g->delta = (double*)malloc(sizeof(double) * g->n);
+  g->acc = (unsigned char*)malloc(g->n);
+  g->src = (unsigned char*)calloc(g->n, 1);
+  g->qv = (double*)malloc(sizeof(double) * g->n);
+  if (!g->delta || !g->acc || !g->src || !g->qv) {
+    grid3_free(g);
+    return -2;
+  }
+  for (long k = 0; k < g->n; ++k) {
+    g->acc[k] = p->mask ? (p->mask[k] != 0) : 1;
+    g->qv[k] = INF;
+    if (g->acc[k]) {
+      double f = p->F[k];
+      if (!(f > 0.0) || !isfinite(f)) {
+        grid3_free(g);
+        return -1;
+      }
+      g->delta[k] = p->h / f;
+    } else {
+      g->delta[k] = INF;
+    }
+  }
+  for (int s = 0; s < p->nsrc; ++s) {
+    long k = (long)p->src[s];
+    double q = p->q ? p->q[s] : 0.0;
+    if (k < 0 || k >= g->n || !g->acc[k] || !isfinite(q)) {
+      grid3_free(g);
+      return -1;
+    }
+    g->src[k] = 1;
+    if (q < g->qv[k]) g->qv[k] = q;
+  }
+  return 0;
+}
+
+double orc3_update(double a, double b, double c, double delta) {
+  double lo = a < b ? a : b, hi = a < b ? b : a;
+  double m1 = lo < c ? lo : c, mid = lo < c ? c : lo;
+  double m2 = hi < mid ? hi : mid, m3 = hi < mid ? mid : hi;
+  if (m1 == INF) return INF;
+  double d = m1 - m2;
+  if (fabs(d) >= delta) return m1 + delta;
+  double u2 = 0.5 * (m1 + m2 + sqrt(2.0 * delta * delta - d * d));
+  if (u2 <= m3) return u2;
+  double d13 = m1 - m3, d23 = m2 - m3;
+  double disc = 3.0 * delta * delta - (d * d + d13 * d13 + d23 * d23);
+  if (!(disc >= 0.0)) return u2; /* rounding guard: the two-sided root */
+  return (m1 + m2 + m3 + sqrt(disc)) / 3.0;
+}
+
+static double nb3(const grid3_t* g, const double* V, int i, int j, int k) {
+  if (i < 0 || j < 0 || k < 0 || i >= g->nx || j >= g->ny || k >= g->nz) return INF;
+  return V[((long)k * g->ny + j) * g->nx + i];
+}
+
+/* Temporary value of node (i,j,k) from its six neighbours. */
+static double node_update3(const grid3_t* g, const double* V, int i, int j, int k) {
+  double uW = nb3(g, V, i - 1, j, k), uE = nb3(g, V, i + 1, j, k);
+  double uS = nb3(g, V, i, j - 1, k), uN = nb3(g, V, i, j + 1, k);
+  double uD = nb3(g, V, i, j, k - 1), uU = nb3(g, V, i, j, k + 1);
+  double a = uW < uE ? uW : uE;
+  double b = uS < uN ? uS : uN;
+  double c = uD < uU ? uD : uU;
+  return orc3_update(a, b, c, g->delta[((long)k * g->ny + j) * g->nx + i]);
+}
+
+static void init_values3(const grid3_t* g, double* V) {
+  for (long k = 0; k < g->n; ++k) V[k] = g->src[k] ? g->qv[k] : INF;
+}
+
+/* Fast Marching: as in two dimensions (sources accepted first in (q, index)
+   order, then the smallest (value, index) considered node). */
+int orc3_fmm(const orc3_problem* p, double* V, int64_t* order, int64_t* nacc) {
+  grid3_t g;
+  int rc = grid3_init(&g, p);
+  if (rc) return rc;
+  unsigned char* lab = (unsigned char*)calloc(g.n, 1);
+  long* srcs = (long*)malloc(sizeof(long) * g.n);
+  heap_t H, Q;
+  if (!lab || !srcs || heap_init(&H, g.n, V)) {
+    free(lab);
+    free(srcs);
+    grid3_free(&g);
+    return -2;
+  }
+  if (heap_init(&Q, g.n, g.qv)) {
+    free(lab);
+    free(srcs);
+    heap_free(&H);
+    grid3_free(&g);
+    return -2;
+  }
+  init_values3(&g, V);
+  long ns = 0, na = 0;
+  for (long k = 0; k < g.n; ++k)
+    if (g.src[k]) heap_push(&Q, k);
+  while (Q.n > 0) srcs[ns++] = heap_pop(&Q);
+  heap_free(&Q);
+  for (long s = 0; s < ns; ++s) {
+    lab[srcs[s]] = ACCEPTED;
+    if (order) order[na] = srcs[s];
+    na++;
+  }
+  static const int di[6] = {-1, 1, 0, 0, 0, 0}, dj[6] = {0, 0, -1, 1, 0, 0}, dk[6] = {0, 0, 0, 0, -1, 1};
+  long pos = 0;  /* sources first, then the heap */
+  for (;;) {
+    long x;
+    if (pos < ns) {
+      x = srcs[pos++];
+    } else {
+      if (H.n == 0) break;
+      x = heap_pop(&H);
+      lab[x] = ACCEPTED;
+      if (order) order[na] = x;
+      na++;
+    }
+    int i = (int)(x % g.nx), j = (int)((x / g.nx) % g.ny), k = (int)(x / ((long)g.nx * g.ny));
+    for (int e = 0; e < 6; ++e) {
+      int a = i + di[e], b = j + dj[e], c = k + dk[e];
+      if (a < 0 || b < 0 || c < 0 || a >= g.nx || b >= g.ny || c >= g.nz) continue;
+      long kk = ((long)c * g.ny + b) * g.nx + a;
+      if (!g.acc[kk] || lab[kk] == ACCEPTED) continue;
+      double t = node_update3(&g, V, a, b, c);
+      if (t < V[kk]) V[kk] = t;
+      if (lab[kk] == FAR) {
+        lab[kk] = CONSIDERED;
+        heap_push(&H, kk);
+      } else {
+        heap_up(&H, H.pos[kk]);
+      }
+    }
+  }
+  if (nacc) *nacc = na;
+  free(lab);
+  free(srcs);
+  heap_free(&H);
+  grid3_free(&g);
+  return 0;
+}
+
+int orc3_fsm(const orc3_problem* p, double* V, int32_t* nsweeps) {
+  grid3_t g;
+  int rc = grid3_init(&g, p);
+  if (rc) return rc;
+  init_values3(&g, V);
+  int sweep = 0, changed;
+  do {
+    int d = sweep % 8;
+    int sx = (d & 1) ? -1 : 1, sy = (d & 2) ? -1 : 1, sz = (d & 4) ? -1 : 1;
+    changed = 0;
+    for (int kk = 0; kk < g.nz; ++kk) {
+      int k = sz > 0 ? kk : g.nz - 1 - kk;
+      for (int jj = 0; jj < g.ny; ++jj) {
+        int j = sy > 0 ? jj : g.ny - 1 - jj;
+        for (int ii = 0; ii < g.nx; ++ii) {
+          int i = sx > 0 ? ii : g.nx - 1 - ii;
+          long x = ((long)k * g.ny + j) * g.nx + i;
+          if (!g.acc[x] || g.src[x]) continue;
+          double t = node_update3(&g, V, i, j, k);
+          if (t < V[x]) {
+            V[x] = t;
+            changed = 1;
+          }
+        }
+      }
+    }
+    sweep++;
+  } while (changed);
+  if (nsweeps) *nsweeps = sweep;
+  grid3_free(&g);
+  return 0;
+}
+
+int orc3_jacobi(const orc3_problem* p, double* V, int32_t* niters) {
+  grid3_t g;
+  int rc = grid3_init(&g, p);
+  if (rc) return rc;
+  double* W = (double*)malloc(sizeof(double) * g.n);
+  if (!W) {
+    grid3_free(&g);
+    return -2;
+  }
+  init_values3(&g, V);
+  int it = 0, changed;
+  do {
+    changed = 0;
+    for (int k = 0; k < g.nz; ++k)
+      for (int j = 0; j < g.ny; ++j)
+        for (int i = 0; i < g.nx; ++i) {
+          long x = ((long)k * g.ny + j) * g.nx + i;
+          W[x] = V[x];
+          if (!g.acc[x] || g.src[x]) continue;
+          double t = node_update3(&g, V, i, j, k);
+          if (t < W[x]) {
+            W[x] = t;
+            changed = 1;
+          }
+        }
+    memcpy(V, W, sizeof(double) * g.n);
+    it++;
+  } while (changed);
+  if (niters) *niters = it;
+  free(W);
+  grid3_free(&g);
+  return 0;
+}
+
+double orc3_residual(const orc3_problem* p, const double* V, double* r) {
+  grid3_t g;
+  if (grid3_init(&g, p)) return -1.0;
+  double mx = 0.0;
+  for (int k = 0; k < g.nz; ++k)
+    for (int j = 0; j < g.ny; ++j)
+      for (int i = 0; i < g.nx; ++i) {
+        long x = ((long)k * g.ny + j) * g.nx + i;
+        double res = 0.0;
+        if (g.acc[x] && !g.src[x]) {
+          double t = node_update3(&g, V, i, j, k);
+          if (V[x] == INF) res = t == INF ? 0.0 : INF;
+          else res = fabs(t - V[x]) / V[x];
+        }
+        if (r) r[x] = res;
+        if (res > mx) mx = res;
+      }
+  grid3_free(&g);
+  return mx;
+}

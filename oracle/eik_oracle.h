@@ -94,6 +94,35 @@ int32_t orc_tiling(int32_t n, int32_t s, int32_t* lo);
    (bit 0 W, 1 E, 2 S, 3 N). */
 int32_t orc_fmsm_dirs(int32_t sides);
 
+/* ---------------------------------------------------------------------- */
+/* Three dimensions (the extension the paper names for its cell methods):  */
+/* node (i, j, k) <-> (k*ny + j)*nx + i, six neighbours.                   */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t nx, ny, nz;
+  double h;
+  const double* F;
+  const uint8_t* mask;
+  int32_t nsrc;
+  const int64_t* src;
+  const double* q;
+} orc3_problem;
+
+/* First-order upwind update from a = min(U_W,U_E), b = min(U_S,U_N),
+   c = min(U_D,U_U) with delta = h/F: sorted m1 <= m2 <= m3, one-sided
+   m1 + delta when m2 - m1 >= delta, else the two-sided root of
+   (U-m1)^2 + (U-m2)^2 = delta^2 when it does not exceed m3, else the
+   three-sided root of (U-m1)^2 + (U-m2)^2 + (U-m3)^2 = delta^2.  With
+   c = +inf it equals orc_update(a, b, delta) bit for bit. */
+double orc3_update(double a, double b, double c, double delta);
+int orc3_fmm(const orc3_problem* p, double* V, int64_t* order, int64_t* naccepted);
+/* Gauss-Seidel sweeps in the eight orderings (sweep number mod 8: bit 0
+   x descending, bit 1 y descending, bit 2 z descending) until a sweep
+   changes nothing. */
+int orc3_fsm(const orc3_problem* p, double* V, int32_t* nsweeps);
+int orc3_jacobi(const orc3_problem* p, double* V, int32_t* niters);
+double orc3_residual(const orc3_problem* p, const double* V, double* r);
+
 #ifdef __cplusplus
 }
 #endif
