@@ -24,8 +24,10 @@
  * Ownership: the caller owns every buffer passed in; the library never frees
  * caller memory.  With device_ptrs = 1 every pointer (F, mask, src, q, u_out)
  * is device memory of the current HIP device and the work is ordered on
- * `stream`; the call returns once that work has completed.  With
- * device_ptrs = 0 they are host memory and the library stages them through
+ * `stream`; the call returns once that work has completed.  Such arrays must
+ * be aligned to their element size (the kernels update u_out with atomics,
+ * which the hardware requires to be naturally aligned): EIK_EINVAL otherwise.
+ * With device_ptrs = 0 they are host memory and the library stages them through
  * device buffers of its own.  Library workspace (per device) is allocated on
  * first use, grows when a larger problem arrives and is kept until the
  * process ends; calls on one device are serialised by a lock.
@@ -248,6 +250,38 @@ int eik_sweep_solve(int32_t nx, int32_t ny, double h, const void* F, const uint8
                     int32_t nsrc, const int64_t* src, const double* q, void* u_out,
                     const eik_sweep_opts* opts, double* max_change, int64_t* n_changed,
                     eik_sweep_stats* stats);
+
+/* Three dimensions: the exact method (label-correcting on cells, the
+   Theorem of Section 3.2.1) on an nx x ny x nz grid, the extension to 3-D
+   the paper proposes for its cell methods.  Node (i, j, k) <-> linear index
+   (k*ny + j)*nx + i (x fastest); six neighbours; the upwind update takes the
+   three axis minima a = min(U_W,U_E), b = min(U_S,U_N), c = min(U_D,U_U),
+   sorted m1 <= m2 <= m3: one-sided m1 + h/F when m2 - m1 >= h/F, else the
+   two-sided root of eq. two_sided_update when it does not exceed m3, else the
+   root of (U-m1)^2 + (U-m2)^2 + (U-m3)^2 = (h/F)^2.  Cells of 8 x 8 x 8 nodes
+   (the last ones ragged) are processed in rounds: all queued cells at once,
+   one wave each, and a cell is queued again when a node on a shared face
+   decreased below the node across.  FP64 only.  F, mask, src, q, u_out are
+   host arrays (device_ptrs = 0: copied in and out, validated before any
+   device work) or device arrays on the current device (device_ptrs = 1:
+   8-byte aligned, else EINVAL; values validated on the device, EINVAL with
+   u_out unspecified); work is ordered
+   on `stream` (hipStream_t or NULL) and the call returns when it is done.
+   Errors as eik_solve; ENOTCONV if the round guard (16 J + 64 rounds) trips;
+   EDEVICE if a round queues more than J cells (a cell is queued at most once
+   per round, so this signals a device fault). */
+typedef struct {
+  double seconds;         /* wall time of the call after argument checks */
+  double rounds_seconds;  /* device time of the rounds */
+  int32_t rounds;         /* rounds performed */
+  int64_t cells;          /* cells J */
+  int64_t cell_visits;    /* cell processings over all rounds */
+  int64_t sweeps;         /* sweeps over all processings (incl. the final ones) */
+} eik3_stats;
+
+int eik_solve3(int32_t nx, int32_t ny, int32_t nz, double h, const double* F, const uint8_t* mask,
+               int32_t nsrc, const int64_t* src, const double* q, double* u_out,
+               int32_t device_ptrs, void* stream, eik3_stats* stats);
 
 /* Message for the last failed call on this thread ("" if none). */
 const char* eik_last_error(void);

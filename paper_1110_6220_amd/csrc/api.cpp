@@ -85,7 +85,7 @@ static std::vector<DevBuf*> all_bufs(Workspace* w) {
                       &sv->slot, &sv->head, &sv->tail, &sv->inflight, &sv->cursor, &sv->ctl, &sv->inst})
       v.push_back(b);
   for (DevBuf* b : {&w->F, &w->u, &w->mask, &w->src, &w->q, &w->cF, &w->cmask, &w->cq, &w->cu,
-                    &w->cout, &w->crank, &w->fmm_spill, &w->sweep_stat, &w->sweep_dirty, &w->F64,
+                    &w->cout, &w->crank, &w->fmm_spill, &w->sweep_stat, &w->sweep_dirty, &w->grid3, &w->F64,
                     &w->u64, &w->ready_at, &w->trace,
                     &w->trace_n, &w->wall_in, &w->wall_cnt})
     v.push_back(b);
@@ -279,6 +279,18 @@ int validate_host(const eik_problem& p, int dtype) {
     if (p.mask && !p.mask[k]) return fail(EIK_EINVAL, "source %d lies on an obstacle", s);
     if (p.q && !std::isfinite(p.q[s])) return fail(EIK_EINVAL, "source %d has non-finite q", s);
   }
+  return EIK_OK;
+}
+
+// Device-resident inputs are read and written in place, u_out with 64-bit
+// (FP64) or 32-bit atomics, which the hardware requires to be naturally
+// aligned: every array must sit on a multiple of its element size.
+int validate_device(const eik_problem& p, int dtype) {
+  const auto off = [](const void* q, size_t a) { return reinterpret_cast<uintptr_t>(q) % a != 0; };
+  if (off(p.F, dsize(dtype)) || off(p.u_out, dsize(dtype)))
+    return fail(EIK_EINVAL, "F and u_out must be aligned to their element size");
+  if (off(p.src, sizeof(int64_t)) || (p.q && off(p.q, sizeof(double))))
+    return fail(EIK_EINVAL, "src and q must be 8-byte aligned");
   return EIK_OK;
 }
 
@@ -939,6 +951,7 @@ int eik_solve(int32_t nx, int32_t ny, double h, const void* F, const uint8_t* ma
   eik_problem p{nx, ny, h, F, mask, nsrc, src, q, u_out};
   if ((rc = validate_shape(p))) return rc;
   if (!o.device_ptrs && (rc = validate_host(p, o.dtype))) return rc;
+  if (o.device_ptrs && (rc = validate_device(p, o.dtype))) return rc;
   return run(1, &p, o, stats, nullptr);
 }
 
@@ -951,6 +964,8 @@ int eik_solve_batched(int32_t n, const eik_problem* probs, const eik_opts* opts,
   for (int k = 0; k < n; ++k) {
     if ((rc = validate_shape(probs[k]))) return fail(rc, "problem %d: %s", k, g_err.c_str());
     if (!o.device_ptrs && (rc = validate_host(probs[k], o.dtype)))
+      return fail(rc, "problem %d: %s", k, g_err.c_str());
+    if (o.device_ptrs && (rc = validate_device(probs[k], o.dtype)))
       return fail(rc, "problem %d: %s", k, g_err.c_str());
   }
   return run(n, probs, o, stats, nullptr);

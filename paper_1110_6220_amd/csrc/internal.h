@@ -69,6 +69,7 @@ struct Workspace {
   DevBuf cF, cmask, cq, cu, cout;     // coarse problems
   DevBuf crank, fmm_spill;            // coarse Fast Marching (FMSM)
   DevBuf sweep_stat, sweep_dirty;     // whole-grid sweeping
+  DevBuf grid3;                       // 3-D solver: cell marks, round lists, counters
   DevBuf F64, u64;                    // FP64 re-solve of FP32 problems
   DevBuf ready_at, trace, trace_n;    // diagnostic trace (EIK_TRACE)
   DevBuf wall_in, wall_cnt;           // wall density of masked problems
@@ -129,6 +130,7 @@ int default_cell(int nx, int ny, int method);
 size_t dsize(int dtype);
 int validate_host(const eik_problem& p, int dtype);
 int validate_shape(const eik_problem& p);
+int validate_device(const eik_problem& p, int dtype);
 // Solves n problems (validated) with one persistent launch.
 int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, RunInfo* info,
         const RunCtx* ctx = nullptr);

@@ -1,0 +1,161 @@
+// eik_solve3: the 3-D exact solver's host side -- validation, staging,
+// preparation and the rounds of cell processing (engine3.hip).
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+
+#include "engine3.h"
+#include "internal.h"
+
+namespace eik {
+namespace {
+
+int validate3_host(int64_t n, const double* F, const uint8_t* mask, int32_t nsrc, const int64_t* src,
+                   const double* q) {
+  for (int64_t x = 0; x < n; ++x) {
+    if (mask && !mask[x]) continue;
+    if (!(F[x] > 0.0) || !std::isfinite(F[x]))
+      return fail(EIK_EINVAL, "speed F[%lld] = %g is not positive and finite", (long long)x, F[x]);
+  }
+  for (int s = 0; s < nsrc; ++s) {
+    if (src[s] < 0 || src[s] >= n) return fail(EIK_EINVAL, "source %d index %lld out of range", s, (long long)src[s]);
+    if (mask && !mask[src[s]]) return fail(EIK_EINVAL, "source %d lies on an obstacle", s);
+    if (q && !std::isfinite(q[s])) return fail(EIK_EINVAL, "source %d has non-finite q", s);
+  }
+  return EIK_OK;
+}
+
+int solve3(int32_t nx, int32_t ny, int32_t nz, double h, const double* F, const uint8_t* mask,
+           int32_t nsrc, const int64_t* src, const double* q, double* u_out, bool dev,
+           hipStream_t stream, eik3_stats* stats) {
+  Workspace* ws = nullptr;
+  int rc = workspace(&ws);
+  if (rc) return rc;
+  std::unique_lock<std::mutex> lk(ws->mu);
+  const int64_t n = (int64_t)nx * ny * nz;
+  Grid3 g;
+  std::memset(&g, 0, sizeof g);
+  g.h = h;
+  g.nx = nx;
+  g.ny = ny;
+  g.nz = nz;
+  g.nsrc = nsrc;
+  g.kx = (nx + kCell3 - 1) / kCell3;
+  g.ky = (ny + kCell3 - 1) / kCell3;
+  g.kz = (nz + kCell3 - 1) / kCell3;
+  const int64_t J = (int64_t)g.kx * g.ky * g.kz;
+  if (J > (1ll << 30)) return fail(EIK_EINVAL, "too many cells");
+  if (dev) {
+    g.u = u_out;
+    g.F = F;
+    g.mask = mask;
+    g.src = src;
+    g.q = q;
+  } else {
+    HIP_TRY(ws->F.ensure(n * sizeof(double)));
+    HIP_TRY(ws->u.ensure(n * sizeof(double)));
+    HIP_TRY(ws->src.ensure(nsrc * sizeof(int64_t)));
+    HIP_TRY(hipMemcpyAsync(ws->F.p, F, n * sizeof(double), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(ws->src.p, src, nsrc * sizeof(int64_t), hipMemcpyHostToDevice, stream));
+    g.u = ws->u.as<double>();
+    g.F = ws->F.as<double>();
+    g.src = ws->src.as<int64_t>();
+    if (mask) {
+      HIP_TRY(ws->mask.ensure(n));
+      HIP_TRY(hipMemcpyAsync(ws->mask.p, mask, n, hipMemcpyHostToDevice, stream));
+      g.mask = ws->mask.as<uint8_t>();
+    }
+    if (q) {
+      HIP_TRY(ws->q.ensure(nsrc * sizeof(double)));
+      HIP_TRY(hipMemcpyAsync(ws->q.p, q, nsrc * sizeof(double), hipMemcpyHostToDevice, stream));
+      g.q = ws->q.as<double>();
+    }
+  }
+  HIP_TRY(ws->fine.delta.ensure(n * sizeof(double)));
+  g.delta = ws->fine.delta.as<double>();
+  // statistics (two 64-bit words, first so that their atomics are 8-byte
+  // aligned: the allocation is 256-byte aligned), the counter and the error
+  // word; then per cell the mark and the two lists
+  constexpr size_t kHead = 64;
+  HIP_TRY(ws->grid3.ensure(kHead + (size_t)J * 3 * sizeof(int32_t)));
+  char* base = static_cast<char*>(ws->grid3.p);
+  if (reinterpret_cast<uintptr_t>(base) % 8) return fail(EIK_EDEVICE, "workspace is not 8-byte aligned");
+  g.stats = reinterpret_cast<unsigned long long*>(base);
+  int32_t* counter = reinterpret_cast<int32_t*>(base + 16);
+  g.err = reinterpret_cast<unsigned*>(base + 20);
+  g.mark = reinterpret_cast<int32_t*>(base + kHead);
+  int32_t* lists[2] = {g.mark + J, g.mark + 2 * J};
+  HIP_TRY(hipMemsetAsync(base, 0, kHead + (size_t)J * 3 * sizeof(int32_t), stream));
+  g.count_next = counter;
+  g.list_next = lists[0];
+  g.list_cur = lists[1];
+  const double t0 = now_s();
+  HIP_TRY(launch3_prepare(g, stream));
+  int32_t cnt = 0;
+  unsigned err = 0;
+  HIP_TRY(hipMemcpyAsync(&cnt, counter, sizeof cnt, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipMemcpyAsync(&err, g.err, sizeof err, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  if (err & (kErr3Speed | kErr3Source))
+    return fail(EIK_EINVAL, "%s", (err & kErr3Speed) ? "a speed value is not positive and finite"
+                                                    : "a source is out of range, on an obstacle or has non-finite q");
+  const int64_t max_rounds = 16 * J + 64;
+  int rounds = 0;
+  HIP_TRY(hipEventRecord(ws->ev0, stream));
+  while (cnt > 0) {
+    // a cell is queued at most once per round (its mark)
+    if (cnt > J) return fail(EIK_EDEVICE, "round %d queued %d cells of %lld", rounds + 1, cnt, (long long)J);
+    if (++rounds > max_rounds) return fail(EIK_ENOTCONV, "round guard tripped after %d rounds", rounds - 1);
+    std::swap(g.list_cur, g.list_next);
+    HIP_TRY(hipMemsetAsync(counter, 0, sizeof(int32_t), stream));
+    HIP_TRY(launch3_round(g, cnt, rounds, stream));
+    HIP_TRY(hipMemcpyAsync(&cnt, counter, sizeof cnt, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+  }
+  HIP_TRY(hipEventRecord(ws->ev1, stream));
+  unsigned long long st[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(&err, g.err, sizeof err, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipMemcpyAsync(st, g.stats, sizeof st, hipMemcpyDeviceToHost, stream));
+  if (!dev) HIP_TRY(hipMemcpyAsync(u_out, g.u, n * sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  if (err & kErr3Guard) return fail(EIK_ENOTCONV, "a cell's sweeps did not terminate");
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, ws->ev0, ws->ev1));
+  if (stats) {
+    stats->seconds = now_s() - t0;
+    stats->rounds_seconds = ms * 1e-3;
+    stats->rounds = rounds;
+    stats->cells = J;
+    stats->cell_visits = (int64_t)st[0];
+    stats->sweeps = (int64_t)st[1];
+  }
+  return EIK_OK;
+}
+
+}  // namespace
+}  // namespace eik
+
+using namespace eik;
+
+extern "C" int eik_solve3(int32_t nx, int32_t ny, int32_t nz, double h, const double* F,
+                          const uint8_t* mask, int32_t nsrc, const int64_t* src, const double* q,
+                          double* u_out, int32_t device_ptrs, void* stream, eik3_stats* stats) {
+  g_err.clear();
+  if (nx < 1 || ny < 1 || nz < 1) return fail(EIK_EINVAL, "grid %d x %d x %d is empty", nx, ny, nz);
+  if ((long long)nx * ny * nz > (1ll << 31) - 1) return fail(EIK_EINVAL, "grid too large");
+  if (!(h > 0.0) || !std::isfinite(h)) return fail(EIK_EINVAL, "h = %g must be positive and finite", h);
+  if (!F || !u_out) return fail(EIK_EINVAL, "F and u_out are required");
+  if (nsrc < 1 || !src) return fail(EIK_EINVAL, "at least one source is required");
+  if (device_ptrs != 0 && device_ptrs != 1) return fail(EIK_EINVAL, "device_ptrs must be 0 or 1");
+  if (device_ptrs) {
+    const auto off = [](const void* p, size_t a) { return reinterpret_cast<uintptr_t>(p) % a != 0; };
+    if (off(F, 8) || off(u_out, 8) || off(src, 8) || (q && off(q, 8)))
+      return fail(EIK_EINVAL, "F, u_out, src and q must be 8-byte aligned");
+  } else {
+    const int rc = validate3_host((int64_t)nx * ny * nz, F, mask, nsrc, src, q);
+    if (rc) return rc;
+  }
+  return solve3(nx, ny, nz, h, F, mask, nsrc, src, q, u_out, device_ptrs != 0,
+                static_cast<hipStream_t>(stream), stats);
+}

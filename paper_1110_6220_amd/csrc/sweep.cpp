@@ -160,5 +160,6 @@ extern "C" int eik_sweep_solve(int32_t nx, int32_t ny, double h, const void* F, 
   eik_problem p{nx, ny, h, F, mask, nsrc, src, q, u_out};
   if ((rc = validate_shape(p))) return rc;
   if (!o.device_ptrs && (rc = validate_host(p, o.dtype))) return rc;
+  if (o.device_ptrs && (rc = validate_device(p, o.dtype))) return rc;
   return sweep_solve(p, o, max_change, n_changed, stats);
 }

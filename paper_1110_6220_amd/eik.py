@@ -24,7 +24,7 @@ SCHEDULES = {"auto": 0, "coarse": 1, "bands": 2, "fifo": 3}
 # Every function include/eik.h declares.
 EXPORTS = ("eik_solve", "eik_solve_batched", "eik_serve_create", "eik_serve_submit",
            "eik_serve_poll", "eik_serve_wait", "eik_serve_cancel", "eik_serve_destroy",
-           "eik_sweep_solve", "eik_last_error")
+           "eik_sweep_solve", "eik_solve3", "eik_last_error")
 
 
 class EikError(RuntimeError):
@@ -79,6 +79,12 @@ class SweepStats(ctypes.Structure):
                 ("tiles_skipped", ctypes.c_int64)]
 
 
+class Stats3(ctypes.Structure):
+    _fields_ = [("seconds", ctypes.c_double), ("rounds_seconds", ctypes.c_double),
+                ("rounds", ctypes.c_int32), ("cells", ctypes.c_int64),
+                ("cell_visits", ctypes.c_int64), ("sweeps", ctypes.c_int64)]
+
+
 class ServeCfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int32),
                 ("lanes", ctypes.c_int32), ("opts", Opts)]
@@ -100,6 +106,8 @@ def _load() -> ctypes.CDLL:
     L.eik_serve_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(Stats)]
     L.eik_serve_cancel.argtypes = [vp, ctypes.c_uint64]
     L.eik_serve_destroy.argtypes = [vp]
+    L.eik_solve3.argtypes = [i32, i32, i32, ctypes.c_double, vp, vp, i32, vp, vp, vp, i32, vp,
+                             ctypes.POINTER(Stats3)]
     L.eik_sweep_solve.argtypes = [i32, i32, ctypes.c_double, vp, vp, i32, vp, vp, vp,
                                   ctypes.POINTER(SweepOpts), vp, vp, ctypes.POINTER(SweepStats)]
     L.eik_last_error.restype = ctypes.c_char_p
@@ -239,6 +247,40 @@ def eik_sweep(F, h, src, q=None, mask=None, u_out=None, *, dtype="f64", locking=
     del keep
     k = st.sweeps
     return u_out, mx[:k].copy(), cnt[:k].copy(), {f: getattr(st, f) for f, _ in st._fields_}
+
+
+def eik_solve3(F, h, src, q=None, mask=None, u_out=None):
+    """3-D exact solve (eik_solve3 of include/eik.h); F has shape (nz, ny, nx),
+    FP64.  numpy arrays are host inputs, torch tensors device inputs.
+    Returns (u, stats dict)."""
+    if _is_torch(F):
+        import torch
+        dev = F.device
+        F_ = F.to(torch.float64).contiguous()
+        src_ = torch.as_tensor(np.asarray(src, dtype=np.int64).ravel() if not _is_torch(src) else src,
+                               device=dev).to(torch.int64).contiguous()
+        q_ = None if q is None else torch.as_tensor(q if _is_torch(q) else np.asarray(q),
+                                                    device=dev).to(torch.float64).contiguous()
+        m_ = None if mask is None else torch.as_tensor(mask if _is_torch(mask) else np.asarray(mask),
+                                                       device=dev).to(torch.uint8).contiguous()
+        u = torch.empty_like(F_) if u_out is None else u_out
+        ptr = lambda t: None if t is None else t.data_ptr()
+        nsrc = src_.numel()
+        device = True
+    else:
+        F_ = np.ascontiguousarray(F, dtype=np.float64)
+        src_ = np.ascontiguousarray(np.atleast_1d(src), dtype=np.int64)
+        q_ = None if q is None else np.ascontiguousarray(np.atleast_1d(q), dtype=np.float64)
+        m_ = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+        u = np.empty_like(F_) if u_out is None else u_out
+        ptr = lambda a: None if a is None else a.ctypes.data
+        nsrc = len(src_)
+        device = False
+    nz, ny, nx = F_.shape
+    st = Stats3()
+    _check(lib.eik_solve3(nx, ny, nz, float(h), ptr(F_), ptr(m_), nsrc, ptr(src_), ptr(q_), ptr(u),
+                          int(device), _stream_of(device), ctypes.byref(st)))
+    return u, {f: getattr(st, f) for f, _ in st._fields_}
 
 
 class Server:

@@ -248,3 +248,35 @@ def config(k: int, **kw):
     if k == 5:
         return maze_requests(kw.pop("count", 64), **kw)
     raise ValueError(k)
+
+
+# ---------------------------------------------------------------------------
+# three dimensions (arrays of shape (nz, ny, nx), node (i, j, k) at
+# (k*ny + j)*nx + i)
+# ---------------------------------------------------------------------------
+
+def sine3(nx: int, ny: int, nz: int, amp: float = 0.5, freq: float = 1.0):
+    """F = 1 + amp sin(2 pi f x) sin(2 pi f y) sin(2 pi f z) on the unit cube
+    (h = 1 / (max side - 1)), exit set at the centre node."""
+    h = 1.0 / max(max(nx, ny, nz) - 1, 1)
+    z, y, x = np.meshgrid(np.arange(nz) * h, np.arange(ny) * h, np.arange(nx) * h, indexing="ij")
+    F = 1.0 + amp * np.sin(2 * math.pi * freq * x) * np.sin(2 * math.pi * freq * y) * np.sin(2 * math.pi * freq * z)
+    c = ((nz // 2) * ny + ny // 2) * nx + nx // 2
+    return dict(name=f"sine3_{nx}x{ny}x{nz}", F=F, h=h, nx=nx, ny=ny, nz=nz,
+                src=np.array([c], dtype=np.int64), q=np.array([0.0]), mask=None)
+
+
+def boxes3(nx: int, ny: int, nz: int, rng: np.random.Generator, nbox: int = 6, nsrc: int = 3):
+    """Speed uniform in [0.5, 2] per node, seeded random axis-aligned box
+    obstacles, nsrc random exit nodes with costs in [0, 0.2]."""
+    h = 1.0 / max(max(nx, ny, nz) - 1, 1)
+    F = rng.uniform(0.5, 2.0, size=(nz, ny, nx))
+    mask = np.ones((nz, ny, nx), dtype=np.uint8)
+    for _ in range(nbox):
+        a = [int(rng.integers(0, s)) for s in (nz, ny, nx)]
+        b = [min(s, a0 + int(rng.integers(1, max(2, s // 3)))) for a0, s in zip(a, (nz, ny, nx))]
+        mask[a[0]:b[0], a[1]:b[1], a[2]:b[2]] = 0
+    acc = np.flatnonzero(mask.ravel())
+    src = rng.choice(acc, size=min(nsrc, len(acc)), replace=False).astype(np.int64)
+    q = rng.uniform(0.0, 0.2, size=len(src))
+    return dict(name=f"boxes3_{nx}x{ny}x{nz}", F=F, h=h, nx=nx, ny=ny, nz=nz, src=src, q=q, mask=mask)

@@ -111,14 +111,14 @@ def test_serving_arguments_are_checked_before_device_work():
 
 def test_struct_layouts_match_header(tmp_path):
     """The ctypes mirrors of eik_opts, eik_stats, eik_problem,
-    eik_serve_cfg, eik_sweep_opts and eik_sweep_stats have the sizes and
+    eik_serve_cfg, eik_sweep_opts, eik_sweep_stats and eik3_stats have the sizes and
     field offsets the C header gives them (compiled with the host compiler;
     no device needed)."""
     import subprocess
     from paper_1110_6220_amd import eik
     structs = {"eik_opts": eik.Opts, "eik_stats": eik.Stats, "eik_problem": eik.Problem,
                "eik_serve_cfg": eik.ServeCfg, "eik_sweep_opts": eik.SweepOpts,
-               "eik_sweep_stats": eik.SweepStats}
+               "eik_sweep_stats": eik.SweepStats, "eik3_stats": eik.Stats3}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "eik.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -162,4 +162,22 @@ def test_negative_timeout_rejected():
         assert e.code == eik.EIK_EINVAL
     else:
         raise AssertionError("negative timeout accepted")
+    assert (u == 7.0).all()
+
+
+def test_solve3_arguments_are_rejected_before_device_work():
+    """3-D: shape, spacing, speed and source checks that need no device."""
+    import numpy as np
+    from paper_1110_6220_amd import eik
+    F = np.ones((3, 4, 5))
+    u = np.full(F.shape, 7.0)
+    bad = F.copy()
+    bad[1, 2, 3] = np.nan
+    for args in [(F, 0.0, [0]), (F, 0.1, [60]), (F, 0.1, [-1]), (bad, 0.1, [0]), (F, 0.1, [])]:
+        try:
+            eik.eik_solve3(args[0], args[1], args[2], u_out=u)
+        except eik.EikError as e:
+            assert e.code == eik.EIK_EINVAL, args[1:]
+        else:
+            raise AssertionError(args[1:])
     assert (u == 7.0).all()

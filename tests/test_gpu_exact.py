@@ -142,6 +142,28 @@ def test_device_validation_leaves_output_untouched(eik):
     assert bool((u == 42.0).all())
 
 
+def test_device_pointers_must_be_aligned(eik):
+    """Device u_out off its element alignment is EINVAL for the cell solver
+    and the whole-grid sweep, rejected on the host before any launch."""
+    import ctypes
+    import torch
+    w = W.random_small(np.random.default_rng(6), 20, 20, obst=0.0, nsrc=1)
+    d = to_dev(w)
+    buf = torch.empty(20 * 20 + 1, dtype=torch.float64, device="cuda:0")
+    o = eik._opts(eik.F64, "exact", 0, 0.0, True, eik._stream_of(True), False, 0, 0, 0, False,
+                  "auto", 0, False)
+    print("[gpu] misaligned u_out", flush=True)
+    rc = eik.lib.eik_solve(20, 20, float(d["h"]), d["F"].data_ptr(), None, d["src"].numel(),
+                           d["src"].data_ptr(), d["q"].data_ptr(), buf.data_ptr() + 4,
+                           ctypes.byref(o), None)
+    assert rc == eik.EIK_EINVAL and b"aligned" in eik.lib.eik_last_error()
+    so = eik.SweepOpts(eik.F64, 0, 0, 0.0, 1, eik._stream_of(True))
+    rc = eik.lib.eik_sweep_solve(20, 20, float(d["h"]), d["F"].data_ptr(), None, d["src"].numel(),
+                                 d["src"].data_ptr(), d["q"].data_ptr(), buf.data_ptr() + 4,
+                                 ctypes.byref(so), None, None, None)
+    assert rc == eik.EIK_EINVAL and b"aligned" in eik.lib.eik_last_error()
+
+
 def test_fp32_within_bound(eik):
     """FP32 storage with the FP64 two-sided branch: max and L1 error against
     the FP64 oracle stay within D * 2^-24 * u_max (D = longest dependency
