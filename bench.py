@@ -202,6 +202,8 @@ def main():
         line["serving"] = bench_serving(args.serve_requests)
         print("[bench] serving done; early termination", file=sys.stderr, flush=True)
         line["early_termination"] = bench_early_termination()
+        print("[bench] early termination done; 3-D", file=sys.stderr, flush=True)
+        line["three_d"] = bench_3d()
     print(json.dumps(line), flush=True)
 
 
@@ -328,6 +330,49 @@ def bench_early_termination(reps=3):
     out["fmsm_82_vs_early_fsm_38"] = out["fsm"]["38"]["ms"] / out["fmsm"][1]["ms"]
     out["fmsm_82_vs_early_lsm_38"] = out["lsm"]["38"]["ms"] / out["fmsm"][1]["ms"]
     out["fmsm_best_of_82_164_ms"] = best
+    return out
+
+
+def bench_3d(sizes=(129, 257), reps=3):
+    """The 3-D exact solver (eik_solve3) on smooth speeds
+    F = 1 + 0.5 sin(2 pi x) sin(2 pi y) sin(2 pi z) over the unit cube with a
+    centre exit node: FP64, inputs resident on the device, median of `reps`
+    calls; every result checked against the oracle's 3-D Fast Marching,
+    whose single-core time is reported beside it."""
+    import statistics
+
+    import torch
+
+    import oracle
+    from paper_1110_6220_amd import eik, workloads
+    out = []
+    for n in sizes:
+        w = workloads.sine3(n, n, n, 0.5)
+        dev = torch.device("cuda:0")
+        F = torch.from_numpy(w["F"]).to(dev)
+        src = torch.from_numpy(w["src"]).to(dev)
+        q = torch.from_numpy(w["q"]).to(dev)
+        u = torch.empty_like(F)
+        eik.eik_solve3(F, w["h"], src, q, None, u_out=u)
+        torch.cuda.synchronize()
+        ts, st = [], None
+        for _ in range(reps):
+            t = time.perf_counter()
+            _, st = eik.eik_solve3(F, w["h"], src, q, None, u_out=u)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        got = u.cpu().numpy()
+        t = time.perf_counter()
+        ref = oracle.fmm3(oracle.Problem3.from_workload(w))
+        t_cpu = time.perf_counter() - t
+        ms = statistics.median(ts) * 1e3
+        out.append({"n": n, "nodes": n ** 3, "ms": ms, "nodes_per_s": n ** 3 / ms * 1e3,
+                    "rounds_ms": st["rounds_seconds"] * 1e3, "rounds": st["rounds"],
+                    "cells": st["cells"], "visits_per_cell": st["cell_visits"] / st["cells"],
+                    "sweeps_per_visit": st["sweeps"] / max(st["cell_visits"], 1),
+                    "max_rel_err_vs_fmm": _max_rel(got, ref),
+                    "cpu_oracle_fmm_nodes_per_s": n ** 3 / t_cpu})
+        print(f"[bench] 3-D {n}^3: {ms:.2f} ms", file=sys.stderr, flush=True)
     return out
 
 
