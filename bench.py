@@ -75,7 +75,15 @@ def main():
     ap.add_argument("--no-graph", action="store_true",
                     help="launch every step's kernels one by one instead of replaying the "
                          "captured HIP graph of the solve")
+    ap.add_argument("--only", choices=["batched", "serving", "early_termination", "three_d"],
+                    help="run one of the extra studies alone and print its JSON (no headline)")
     args = ap.parse_args()
+    if args.only:
+        runs = {"batched": lambda: bench_batched("f64", graph=not args.no_graph),
+                "serving": lambda: bench_serving(args.serve_requests),
+                "early_termination": bench_early_termination, "three_d": bench_3d}
+        print(json.dumps({args.only: runs[args.only]()}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the solver runs on a single device)", file=sys.stderr)
@@ -371,6 +379,8 @@ def bench_3d(sizes=(129, 257), reps=3):
                     "cells": st["cells"], "visits_per_cell": st["cell_visits"] / st["cells"],
                     "sweeps_per_visit": st["sweeps"] / max(st["cell_visits"], 1),
                     "max_rel_err_vs_fmm": _max_rel(got, ref),
+                    # algorithmic bytes: read F, write u once (16 B/node)
+                    "alg_GBps_over_rounds": 16.0 * n ** 3 / st["rounds_seconds"] / 1e9,
                     "cpu_oracle_fmm_nodes_per_s": n ** 3 / t_cpu})
         print(f"[bench] 3-D {n}^3: {ms:.2f} ms", file=sys.stderr, flush=True)
     return out

@@ -260,20 +260,20 @@ int eik_sweep_solve(int32_t nx, int32_t ny, double h, const void* F, const uint8
    two-sided root of eq. two_sided_update when it does not exceed m3, else the
    root of (U-m1)^2 + (U-m2)^2 + (U-m3)^2 = (h/F)^2.  Cells of 8 x 8 x 8 nodes
    (the last ones ragged) are processed in rounds: all queued cells at once,
-   one wave each, and a cell is queued again when a node on a shared face
-   decreased below the node across.  FP64 only.  F, mask, src, q, u_out are
-   host arrays (device_ptrs = 0: copied in and out, validated before any
-   device work) or device arrays on the current device (device_ptrs = 1:
-   8-byte aligned, else EINVAL; values validated on the device, EINVAL with
-   u_out unspecified); work is ordered
-   on `stream` (hipStream_t or NULL) and the call returns when it is done.
-   Errors as eik_solve; ENOTCONV if the round guard (16 J + 64 rounds) trips;
-   EDEVICE if a round queues more than J cells (a cell is queued at most once
-   per round, so this signals a device fault). */
+   one wave each, and a cell is queued for the next round when a node on a
+   shared face decreased below the node across.  FP64 only.  F, mask, src, q,
+   u_out are host arrays (device_ptrs = 0: copied in and out, validated
+   before any device work) or device arrays on the current device
+   (device_ptrs = 1: 8-byte aligned, else EINVAL; values validated on the
+   device, EINVAL with u_out unspecified); work is ordered on `stream`
+   (hipStream_t or NULL) and the call returns when it is done.  Errors as
+   eik_solve; ENOTCONV if the round guard (16 J + 64 rounds) trips or a
+   cell's sweeps do not terminate; EDEVICE if a round lists more than J cells
+   (a cell is listed at most once per round, so this signals a device fault). */
 typedef struct {
   double seconds;         /* wall time of the call after argument checks */
   double rounds_seconds;  /* device time of the rounds */
-  int32_t rounds;         /* rounds performed */
+  int32_t rounds;         /* rounds that processed at least one cell */
   int64_t cells;          /* cells J */
   int64_t cell_visits;    /* cell processings over all rounds */
   int64_t sweeps;         /* sweeps over all processings (incl. the final ones) */

@@ -116,6 +116,8 @@ void workspace_free(Workspace* w) {
   w->graveyard.clear();
   for (DevBuf* b : all_bufs(w)) b->release();
   if (w->ctl_host) (void)hipHostFree(w->ctl_host);
+  if (w->host3) (void)hipHostFree(w->host3);
+  w->host3 = nullptr;
   if (w->ev0) (void)hipEventDestroy(w->ev0);
   if (w->ev1) (void)hipEventDestroy(w->ev1);
   w->ctl_host = nullptr;
@@ -132,6 +134,7 @@ int workspace_init(Workspace* w) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   HIP_TRY(hipHostMalloc((void**)&w->ctl_host, 2 * sizeof(Ctl), hipHostMallocDefault));
+  HIP_TRY(hipHostMalloc((void**)&w->host3, 16 * sizeof(int32_t), hipHostMallocDefault));
   HIP_TRY(hipEventCreate(&w->ev0));
   HIP_TRY(hipEventCreate(&w->ev1));
   HIP_TRY(hipDeviceGetAttribute(&w->cus, hipDeviceAttributeMultiprocessorCount, dev));

@@ -6,7 +6,7 @@
 namespace eik {
 
 constexpr int kCell3 = 8;  // nodes per cell edge
-constexpr unsigned kErr3Speed = 1u, kErr3Source = 2u, kErr3Guard = 4u;
+constexpr unsigned kErr3Speed = 1u, kErr3Source = 2u, kErr3Guard = 4u, kErr3Count = 8u;
 
 // One problem on an nx x ny x nz grid (node (i, j, k) at (k*ny + j)*nx + i),
 // cut into kx x ky x kz cells of kCell3^3 nodes (the last ones ragged).
@@ -20,18 +20,24 @@ struct Grid3 {
   double h;
   int32_t nx, ny, nz, nsrc;
   int32_t kx, ky, kz;
-  int32_t* mark;         // per cell: the last round it was queued for
-  int32_t* list_cur;     // cells of this round
-  int32_t* list_next;    // cells queued for the next round ...
-  int32_t* count_next;   // ... and their number
+  int32_t* mark;         // per cell: the last round it was queued for ...
+  int32_t* entry;        // ... and the faces new values entered through
+  int32_t* lists[2];     // round r processes lists[r & 1], queues into lists[(r + 1) & 1]
+  int32_t* counts;       // [3]: round r's list length is counts[r % 3]
+  int32_t* busy;         // rounds that processed at least one cell
   unsigned* err;         // kErr3* bits
   unsigned long long* stats;  // [0] cell visits, [1] sweeps
 };
 
-// validation, h/F, u = +inf, exit nodes; queues round 1 (mark, list_next,
-// count_next must start at zero)
+// validation, h/F, u = +inf, exit nodes; queues round 1 (mark, entry,
+// lists, counts, busy must start at zero)
 hipError_t launch3_prepare(const Grid3& g, hipStream_t stream);
-// processes the `cells` cells of g.list_cur as round `round`
-hipError_t launch3_round(const Grid3& g, int cells, int round, hipStream_t stream);
+// round `round` (>= 1): its list length is read on the device, so rounds can
+// be enqueued without waiting; an empty round does nothing.  Each round also
+// zeroes the counter the round after it queues into.  `blocks` waves loop
+// over the list.
+hipError_t launch3_round(const Grid3& g, int round, int blocks, hipStream_t stream);
+// resident 64-thread blocks of the round kernel per compute unit
+int round3_blocks_per_cu();
 
 }  // namespace eik

@@ -80,6 +80,7 @@ struct Workspace {
   uint64_t uses = 0;
   bool defer_free = false;            // grow without hipFree (serving lanes)
   Ctl* ctl_host = nullptr;            // pinned: fine and coarse control blocks
+  int32_t* host3 = nullptr;           // pinned: 3-D solver read-back (64 bytes)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int cus = 0;
   int wall_khz = 0;

@@ -75,48 +75,54 @@ int solve3(int32_t nx, int32_t ny, int32_t nz, double h, const double* F, const 
   HIP_TRY(ws->fine.delta.ensure(n * sizeof(double)));
   g.delta = ws->fine.delta.as<double>();
   // statistics (two 64-bit words, first so that their atomics are 8-byte
-  // aligned: the allocation is 256-byte aligned), the counter and the error
-  // word; then per cell the mark and the two lists
+  // aligned: the allocation is 256-byte aligned), the three round counters,
+  // the error word and the busy-round count; then per cell the mark, the
+  // entry faces and the two lists
   constexpr size_t kHead = 64;
-  HIP_TRY(ws->grid3.ensure(kHead + (size_t)J * 3 * sizeof(int32_t)));
+  HIP_TRY(ws->grid3.ensure(kHead + (size_t)J * 4 * sizeof(int32_t)));
   char* base = static_cast<char*>(ws->grid3.p);
   if (reinterpret_cast<uintptr_t>(base) % 8) return fail(EIK_EDEVICE, "workspace is not 8-byte aligned");
   g.stats = reinterpret_cast<unsigned long long*>(base);
-  int32_t* counter = reinterpret_cast<int32_t*>(base + 16);
-  g.err = reinterpret_cast<unsigned*>(base + 20);
+  g.counts = reinterpret_cast<int32_t*>(base + 16);
+  g.err = reinterpret_cast<unsigned*>(base + 28);
+  g.busy = reinterpret_cast<int32_t*>(base + 32);
   g.mark = reinterpret_cast<int32_t*>(base + kHead);
-  int32_t* lists[2] = {g.mark + J, g.mark + 2 * J};
-  HIP_TRY(hipMemsetAsync(base, 0, kHead + (size_t)J * 3 * sizeof(int32_t), stream));
-  g.count_next = counter;
-  g.list_next = lists[0];
-  g.list_cur = lists[1];
+  g.entry = g.mark + J;
+  g.lists[0] = g.mark + 2 * J;
+  g.lists[1] = g.mark + 3 * J;
+  HIP_TRY(hipMemsetAsync(base, 0, kHead + (size_t)J * 4 * sizeof(int32_t), stream));
   const double t0 = now_s();
   HIP_TRY(launch3_prepare(g, stream));
-  int32_t cnt = 0;
-  unsigned err = 0;
-  HIP_TRY(hipMemcpyAsync(&cnt, counter, sizeof cnt, hipMemcpyDeviceToHost, stream));
-  HIP_TRY(hipMemcpyAsync(&err, g.err, sizeof err, hipMemcpyDeviceToHost, stream));
+  int32_t* hb = ws->host3;  // pinned: [0] a round's list length, [1] error word, [2] busy rounds
+  HIP_TRY(hipMemcpyAsync(hb, &g.counts[1], sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipMemcpyAsync(hb + 1, g.err, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
+  unsigned err = (unsigned)hb[1];
   if (err & (kErr3Speed | kErr3Source))
     return fail(EIK_EINVAL, "%s", (err & kErr3Speed) ? "a speed value is not positive and finite"
                                                     : "a source is out of range, on an obstacle or has non-finite q");
+  // rounds are enqueued in batches; only the length of the list after a
+  // batch comes back to the host (rounds past the last one are empty)
   const int64_t max_rounds = 16 * J + 64;
+  const int blocks = (int)std::min<int64_t>(J, (int64_t)ws->cus * round3_blocks_per_cu());
+  constexpr int kBatch = 8;
   int rounds = 0;
+  int32_t pending = hb[0];
   HIP_TRY(hipEventRecord(ws->ev0, stream));
-  while (cnt > 0) {
-    // a cell is queued at most once per round (its mark)
-    if (cnt > J) return fail(EIK_EDEVICE, "round %d queued %d cells of %lld", rounds + 1, cnt, (long long)J);
-    if (++rounds > max_rounds) return fail(EIK_ENOTCONV, "round guard tripped after %d rounds", rounds - 1);
-    std::swap(g.list_cur, g.list_next);
-    HIP_TRY(hipMemsetAsync(counter, 0, sizeof(int32_t), stream));
-    HIP_TRY(launch3_round(g, cnt, rounds, stream));
-    HIP_TRY(hipMemcpyAsync(&cnt, counter, sizeof cnt, hipMemcpyDeviceToHost, stream));
+  while (pending > 0) {
+    if (rounds > max_rounds) return fail(EIK_ENOTCONV, "round guard tripped after %d rounds", rounds);
+    for (int b = 0; b < kBatch; ++b) HIP_TRY(launch3_round(g, ++rounds, blocks, stream));
+    HIP_TRY(hipMemcpyAsync(hb, &g.counts[(rounds + 1) % 3], sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(hb + 1, g.err, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
+    if ((unsigned)hb[1] & kErr3Count) return fail(EIK_EDEVICE, "a round listed more than %lld cells", (long long)J);
+    pending = hb[0];
   }
   HIP_TRY(hipEventRecord(ws->ev1, stream));
   unsigned long long st[2] = {0, 0};
   HIP_TRY(hipMemcpyAsync(&err, g.err, sizeof err, hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipMemcpyAsync(st, g.stats, sizeof st, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipMemcpyAsync(hb + 2, g.busy, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
   if (!dev) HIP_TRY(hipMemcpyAsync(u_out, g.u, n * sizeof(double), hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
   if (err & kErr3Guard) return fail(EIK_ENOTCONV, "a cell's sweeps did not terminate");
@@ -125,7 +131,7 @@ int solve3(int32_t nx, int32_t ny, int32_t nz, double h, const double* F, const 
   if (stats) {
     stats->seconds = now_s() - t0;
     stats->rounds_seconds = ms * 1e-3;
-    stats->rounds = rounds;
+    stats->rounds = hb[2];
     stats->cells = J;
     stats->cell_visits = (int64_t)st[0];
     stats->sweeps = (int64_t)st[1];
