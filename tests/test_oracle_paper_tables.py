@@ -7,8 +7,11 @@ Sweeping's sweep counts, and the error ratios, sweep counts and
 monotonicity rates of FMSM and FHCM.  These fix the grid and exit-set
 readings, the update, and the two approximate methods (coarse speed and
 order, sweep directions, monotonicity flags) on smooth and piecewise-constant
-speeds.  Slow: seven Fast Marching solves of ~30M nodes for the ground
-truths."""
+speeds.  The same quantities on the coarse grids of the subsection on
+coarser grids (tables tab:checker_11_c1, tab:checker_41_c1, tab:sinu_1_c1,
+tab:sinu_2_c2; fixture tests/golden/paper_tables_coarse.txt) pin them again
+where the cells hold only 2 to 16 nodes per side.  Slow: seven Fast Marching
+solves of ~30M nodes for the ground truths."""
 import os
 
 import numpy as np
@@ -18,11 +21,13 @@ import oracle as O
 from paper_1110_6220_amd import workloads as W
 
 pytestmark = pytest.mark.slow
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "paper_tables_1408.txt")
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = os.path.join(HERE, "golden", "paper_tables_1408.txt")
+GOLDEN_COARSE = os.path.join(HERE, "golden", "paper_tables_coarse.txt")
 
 
-def rows():
-    return [ln.split() for ln in open(GOLDEN) if ln.strip() and not ln.startswith("#")]
+def rows(path=GOLDEN):
+    return [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
 
 
 def within_last_digit(value, printed):
@@ -47,10 +52,10 @@ def workload(family, amp, freq, n):
 _cache = {}
 
 
-def case(family, amp, freq):
-    key = (family, amp, freq)
+def case(family, amp, freq, n=None):
+    n = SIZE[family] if n is None else n
+    key = (family, amp, freq, n)
     if key not in _cache:
-        n = SIZE[family]
         p = O.Problem.from_workload(workload(family, amp, freq, n))
         fine = workload(family, amp, freq, 4 * (n - 1) + 1)
         truth = O.fmm(O.Problem.from_workload(fine))[::4, ::4]
@@ -89,3 +94,34 @@ def test_paper_tables(family):
             if got is None:
                 got = ratios(V, U, truth)[what]
             assert within_last_digit(got, row[5]), (row, got)
+
+
+COARSE = [("chk11", 176), ("chk11", 352), ("chk41", 164), ("chk41", 328), ("pt", 176), ("pt", 352)]
+
+
+@pytest.mark.parametrize("family,n", COARSE)
+def test_paper_tables_coarse_grids(family, n):
+    checked = 0
+    for row in rows(GOLDEN_COARSE):
+        if row[0] != family or int(row[1]) != n:
+            continue
+        kind, amp, freq = row[2], float(row[3]), float(row[4])
+        p, truth, U = case(family, amp, freq, n)
+        if kind == "fmm_linf":
+            got = np.abs(U - truth).max()
+        elif kind == "fmm_l1":
+            got = np.abs(U - truth).mean()
+        elif kind == "fsm":
+            assert O.fsm(p)[1] == int(row[5]), row
+            checked += 1
+            continue
+        else:
+            method, what = kind.split("_")
+            cells = int(row[5])
+            V, st = (O.fmsm if method == "fmsm" else O.fhcm)(p, n // cells)
+            got = {"avs": st["AvS"], "mon": st["Mon%"], "avhr": st["AvHR"]}.get(what)
+            if got is None:
+                got = ratios(V, U, truth)[what]
+        assert within_last_digit(got, row[-1]), (row, got)
+        checked += 1
+    assert checked >= 10
