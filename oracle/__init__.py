@@ -92,6 +92,9 @@ def lib() -> ctypes.CDLL:
         L.orc3_jacobi.argtypes = [P3, vp, ctypes.POINTER(i32)]
         L.orc3_residual.restype = ctypes.c_double
         L.orc3_residual.argtypes = [P3, vp, vp]
+        L.orc3_fmsm.argtypes = [P3, i32, vp, vp, vp, ctypes.POINTER(CellStats)]
+        L.orc3_fmsm_orderings.restype = i32
+        L.orc3_fmsm_orderings.argtypes = [i32, i32]
         L.orc_sweep_init.argtypes = [P, vp, vp]
         L.orc_fsm_sweep.argtypes = [P, vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         L.orc_lsm_sweep.argtypes = [P, vp, vp, i32, ctypes.POINTER(ctypes.c_double),
@@ -211,6 +214,24 @@ def fsm3(p: Problem3):
     n = ctypes.c_int32(0)
     _check(lib().orc3_fsm(p.c, V.ctypes.data, ctypes.byref(n)), "orc3_fsm")
     return V, n.value
+
+
+def fmsm3(p: Problem3, s: int):
+    """3-D FMSM on cells of s^3 nodes; returns (V, stats with the coarse
+    order, coarse values, AvS)."""
+    V = np.empty((p.nz, p.ny, p.nx))
+    K = [(n + s - 1) // s for n in (p.nx, p.ny, p.nz)]
+    J = K[0] * K[1] * K[2]
+    order = np.empty(J, dtype=np.int64)
+    cu = np.empty(J)
+    st = CellStats()
+    _check(lib().orc3_fmsm(p.c, int(s), V.ctypes.data, order.ctypes.data, cu.ctypes.data,
+                           ctypes.byref(st)), "orc3_fmsm")
+    return V, {"order": order, "coarse_u": cu.reshape(K[2], K[1], K[0]), **st.as_dict()}
+
+
+def fmsm3_orderings(faces: int, thin_axes: int = 0) -> int:
+    return lib().orc3_fmsm_orderings(int(faces), int(thin_axes))
 
 
 def jacobi3(p: Problem3):

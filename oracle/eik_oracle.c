@@ -1272,6 +1272,216 @@ int orc3_fsm(const orc3_problem* p, double* V, int32_t* nsweeps) {
   return 0;
 }
 
+/* Fast Marching-Sweeping in three dimensions (Algorithm FMSM extended as
+   Section 5 proposes).  Cells of s x s x s nodes, cell c covering
+   [c s, min((c + 1) s, n)) along each axis (no merging of a last one-node
+   cell).  Part I: Fast Marching on the grid of cell centres.  Part II: the
+   cells in that acceptance order, each swept once in every ordering its
+   earlier-accepted neighbours allow, with the update restricted to the
+   sweep's upwind neighbours; cells holding exit nodes and cells the coarse
+   front never reaches are swept to convergence with the standard update. */
+
+/* Canonical order of the eight orderings (bit 0 x descending, bit 1 y
+   descending, bit 2 z descending): z ascending first, and within a z
+   direction the two-dimensional order SW, NW, NE, SE. */
+static const int fmsm3_seq[8] = {0, 2, 3, 1, 4, 6, 7, 5};
+
+static void cell3_box(long c, const int* K, int s, const grid3_t* g, int* lo, int* hi) {
+  int ci[3] = {(int)(c % K[0]), (int)((c / K[0]) % K[1]), (int)(c / ((long)K[0] * K[1]))};
+  int n[3] = {g->nx, g->ny, g->nz};
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = ci[a] * s;
+    hi[a] = (ci[a] + 1) * s < n[a] ? (ci[a] + 1) * s : n[a];
+  }
+}
+
+/* One Gauss-Seidel sweep of the box in ordering d; directional: the update
+   from the three upwind neighbours of the ordering only. */
+static int sweep3_box(const grid3_t* g, double* V, int d, const int* lo, const int* hi,
+                      int directional) {
+  int sx = (d & 1) ? -1 : 1, sy = (d & 2) ? -1 : 1, sz = (d & 4) ? -1 : 1, changed = 0;
+  for (int kk = 0; kk < hi[2] - lo[2]; ++kk) {
+    int k = sz > 0 ? lo[2] + kk : hi[2] - 1 - kk;
+    for (int jj = 0; jj < hi[1] - lo[1]; ++jj) {
+      int j = sy > 0 ? lo[1] + jj : hi[1] - 1 - jj;
+      for (int ii = 0; ii < hi[0] - lo[0]; ++ii) {
+        int i = sx > 0 ? lo[0] + ii : hi[0] - 1 - ii;
+        long x = ((long)k * g->ny + j) * g->nx + i;
+        if (!g->acc[x] || g->src[x]) continue;
+        double t = directional ? orc3_update(nb3(g, V, i - sx, j, k), nb3(g, V, i, j - sy, k),
+                                             nb3(g, V, i, j, k - sz), g->delta[x])
+                               : node_update3(g, V, i, j, k);
+        if (t < V[x]) {
+          V[x] = t;
+          changed = 1;
+        }
+      }
+    }
+  }
+  return changed;
+}
+
+/* READING of the sweep choice in three dimensions (the figure on coarse
+   sweep choice, per axis): an axis with an earlier-accepted neighbour on its
+   low (high) face contributes the ascending (descending) direction, both when
+   both; an axis without one contributes both directions; an axis along which
+   the grid is one node thick contributes the ascending one only (both visit
+   its node in the same order from the same neighbours).  The orderings are
+   the combinations, in canonical order.  Returns a mask over ordering codes. */
+int32_t orc3_fmsm_orderings(int32_t faces, int32_t thin_axes) {
+  int allow[3];
+  for (int a = 0; a < 3; ++a) {
+    int lo = (faces >> (2 * a)) & 1, hi = (faces >> (2 * a + 1)) & 1;
+    if ((thin_axes >> a) & 1) allow[a] = 1;
+    else if (lo || hi) allow[a] = (lo ? 1 : 0) | (hi ? 2 : 0);
+    else allow[a] = 3;
+  }
+  int32_t m = 0;
+  for (int d = 0; d < 8; ++d) {
+    int ok = 1;
+    for (int a = 0; a < 3; ++a) ok &= (allow[a] >> ((d >> a) & 1)) & 1;
+    if (ok) m |= 1 << d;
+  }
+  return m;
+}
+
+int orc3_fmsm(const orc3_problem* p, int32_t s, double* V, int64_t* order_out, double* coarse_u,
+              orc_cell_stats* st) {
+  grid3_t g;
+  int rc = grid3_init(&g, p);
+  if (rc) return rc;
+  if (s < 1) {
+    grid3_free(&g);
+    return -1;
+  }
+  int K[3] = {(g.nx + s - 1) / s, (g.ny + s - 1) / s, (g.nz + s - 1) / s};
+  long J = (long)K[0] * K[1] * K[2];
+  double* Fc = (double*)malloc(sizeof(double) * J);
+  uint8_t* mc = (uint8_t*)calloc(J, 1);
+  int64_t* csrc = (int64_t*)malloc(sizeof(int64_t) * J);
+  double* cq = (double*)malloc(sizeof(double) * J);
+  double* Uc = (double*)malloc(sizeof(double) * J);
+  int64_t* P = (int64_t*)malloc(sizeof(int64_t) * J);
+  long* rank = (long*)malloc(sizeof(long) * J);
+  unsigned char* issrc = (unsigned char*)calloc(J, 1);
+  if (!Fc || !mc || !csrc || !cq || !Uc || !P || !rank || !issrc) {
+    rc = -2;
+    goto done3;
+  }
+  {
+    /* Part I.  Coarse speed (READING, as in two dimensions): F at the cell
+       centre -- the centre node along an axis of odd extent, the two around
+       it otherwise -- the mean of those that are accessible, added x
+       outermost, then y, then z; if none is, the mean of F over the cell's
+       accessible nodes, summed plane by plane (each x-plane y outer, z
+       inner, then the plane sums x ascending).  Coarse exit cost: min q of
+       the cell's exit nodes; all-obstacle cells are coarse obstacles. */
+    long nsc = 0;
+    int thin = (g.nx == 1 ? 1 : 0) | (g.ny == 1 ? 2 : 0) | (g.nz == 1 ? 4 : 0);
+    for (long c = 0; c < J; ++c) {
+      int lo[3], hi[3], cnt = 0, has = 0;
+      double sum = 0.0, qmin = INF;
+      cell3_box(c, K, s, &g, lo, hi);
+      for (int i = lo[0]; i < hi[0]; ++i) {
+        double pl = 0.0;
+        for (int j = lo[1]; j < hi[1]; ++j)
+          for (int k = lo[2]; k < hi[2]; ++k) {
+            long x = ((long)k * g.ny + j) * g.nx + i;
+            if (!g.acc[x]) continue;
+            pl += p->F[x];
+            cnt++;
+            if (g.src[x]) {
+              has = 1;
+              if (g.qv[x] < qmin) qmin = g.qv[x];
+            }
+          }
+        sum += pl;
+      }
+      mc[c] = cnt > 0;
+      Fc[c] = cnt > 0 ? sum / cnt : 1.0;
+      int is[2] = {(lo[0] + hi[0] - 1) / 2, (lo[0] + hi[0]) / 2};
+      int js[2] = {(lo[1] + hi[1] - 1) / 2, (lo[1] + hi[1]) / 2};
+      int ks[2] = {(lo[2] + hi[2] - 1) / 2, (lo[2] + hi[2]) / 2};
+      int ni = is[0] == is[1] ? 1 : 2, nj = js[0] == js[1] ? 1 : 2, nk = ks[0] == ks[1] ? 1 : 2;
+      int nc = 0;
+      double sc = 0.0;
+      for (int a = 0; a < ni; ++a)
+        for (int b = 0; b < nj; ++b)
+          for (int e = 0; e < nk; ++e) {
+            long x = ((long)ks[e] * g.ny + js[b]) * g.nx + is[a];
+            if (!g.acc[x]) continue;
+            sc += p->F[x];
+            nc++;
+          }
+      if (nc > 0) Fc[c] = sc / nc;
+      if (has) {
+        csrc[nsc] = c;
+        cq[nsc] = qmin;
+        nsc++;
+        issrc[c] = 1;
+      }
+    }
+    orc3_problem cp;
+    cp.nx = K[0];
+    cp.ny = K[1];
+    cp.nz = K[2];
+    cp.h = (double)s * p->h;
+    cp.F = Fc;
+    cp.mask = mc;
+    cp.nsrc = (int32_t)nsc;
+    cp.src = csrc;
+    cp.q = cq;
+    int64_t na = 0;
+    if ((rc = orc3_fmm(&cp, Uc, P, &na))) goto done3;
+    for (long c = 0; c < J; ++c)
+      if (mc[c] && Uc[c] == INF) P[na++] = c;
+    for (long c = 0; c < J; ++c) rank[c] = -1;
+    for (long t = 0; t < na; ++t) rank[P[t]] = t;
+    /* Part II */
+    init_values3(&g, V);
+    orc_cell_stats S;
+    memset(&S, 0, sizeof S);
+    S.cells = J;
+    for (long t = 0; t < na; ++t) {
+      long c = P[t];
+      int lo[3], hi[3];
+      cell3_box(c, K, s, &g, lo, hi);
+      S.removals++;
+      if (issrc[c] || Uc[c] == INF) {
+        int sw = 0, ch;
+        do {
+          ch = sweep3_box(&g, V, fmsm3_seq[sw % 8], lo, hi, 0);
+          sw++;
+        } while (ch);
+        S.sweeps += sw;
+      } else {
+        int ci[3] = {(int)(c % K[0]), (int)((c / K[0]) % K[1]), (int)(c / ((long)K[0] * K[1]))};
+        long stride[3] = {1, K[0], (long)K[0] * K[1]};
+        int faces = 0;
+        for (int a = 0; a < 3; ++a) {
+          if (ci[a] > 0 && rank[c - stride[a]] >= 0 && rank[c - stride[a]] < t) faces |= 1 << (2 * a);
+          if (ci[a] + 1 < K[a] && rank[c + stride[a]] >= 0 && rank[c + stride[a]] < t)
+            faces |= 1 << (2 * a + 1);
+        }
+        int32_t m = orc3_fmsm_orderings(faces, thin);
+        for (int q = 0; q < 8; ++q)
+          if (m & (1 << fmsm3_seq[q])) {
+            sweep3_box(&g, V, fmsm3_seq[q], lo, hi, 1);
+            S.sweeps++;
+          }
+      }
+    }
+    if (order_out)
+      for (long t = 0; t < J; ++t) order_out[t] = t < na ? P[t] : -1;
+    if (coarse_u) memcpy(coarse_u, Uc, sizeof(double) * J);
+    if (st) *st = S;
+  }
+done3:
+  free(Fc); free(mc); free(csrc); free(cq); free(Uc); free(P); free(rank); free(issrc);
+  grid3_free(&g);
+  return rc;
+}
+
 int orc3_jacobi(const orc3_problem* p, double* V, int32_t* niters) {
   grid3_t g;
   int rc = grid3_init(&g, p);

@@ -122,6 +122,19 @@ int orc3_fmm(const orc3_problem* p, double* V, int64_t* order, int64_t* naccepte
 int orc3_fsm(const orc3_problem* p, double* V, int32_t* nsweeps);
 int orc3_jacobi(const orc3_problem* p, double* V, int32_t* niters);
 double orc3_residual(const orc3_problem* p, const double* V, double* r);
+/* Fast Marching-Sweeping on cells of s x s x s nodes (cell c covering
+   [c s, min((c+1) s, n)) per axis): Fast Marching on the grid of cell
+   centres (h^c = s h, coarse speed F at the centre), then the cells in its
+   acceptance order, each swept once in the orderings of
+   orc3_fmsm_orderings (directional update); cells holding exit nodes and
+   cells the coarse front never reaches are swept to convergence.
+   order_out: J cell indices (-1 after the processed ones); coarse_u: J. */
+int orc3_fmsm(const orc3_problem* p, int32_t s, double* V, int64_t* order_out, double* coarse_u,
+              orc_cell_stats* st);
+/* Orderings (mask over codes 0..7) for a cell whose earlier-accepted
+   neighbours lie on `faces` (bit 2 axis + side, side 1 = high face) in a
+   grid that is one node thick along the axes of `thin_axes` (bit axis). */
+int32_t orc3_fmsm_orderings(int32_t faces, int32_t thin_axes);
 
 #ifdef __cplusplus
 }

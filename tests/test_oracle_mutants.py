@@ -26,13 +26,21 @@ MUTANTS = {
     "source_first_removal": ("(first && g.src[ki])", "(0 && g.src[ki])"),
 }
 
+# Mistakes in the 3-D FMSM (checked against the 3-D pins)
+MUTANTS3 = {
+    "fmsm3_upwind_z": ("nb3(g, V, i, j, k - sz), g->delta[x])", "nb3(g, V, i, j, k + sz), g->delta[x])"),
+    "fmsm3_direction_swap": ("allow[a] = (lo ? 1 : 0) | (hi ? 2 : 0);", "allow[a] = (lo ? 2 : 0) | (hi ? 1 : 0);"),
+    "fmsm3_centre_z": ("int ks[2] = {(lo[2] + hi[2] - 1) / 2, (lo[2] + hi[2]) / 2};",
+                       "int ks[2] = {lo[2], lo[2]};"),
+    "fmsm3_thin_axis_doubled": ("if ((thin_axes >> a) & 1) allow[a] = 1;", "if (0) allow[a] = 1;"),
+    "fmsm3_source_cells_one_sweep": ("        } while (ch);\n        S.sweeps += sw;\n      } else {\n        int ci[3]",
+                                     "        } while (0);\n        S.sweeps += sw;\n      } else {\n        int ci[3]"),
+}
 
-@pytest.mark.slow
-@pytest.mark.parametrize("name", sorted(MUTANTS))
-def test_pins_reject_mutant(name, tmp_path):
-    old, new = MUTANTS[name]
+
+def run_pins_against(old, new, tmp_path, test_file):
     text = open(SRC).read()
-    assert text.count(old) >= 1, f"mutation site for {name} not found"
+    assert text.count(old) >= 1, "mutation site not found"
     mutated = text.replace(old, new, 1)
     c = tmp_path / "eik_oracle.c"
     c.write_text(mutated)
@@ -41,7 +49,20 @@ def test_pins_reject_mutant(name, tmp_path):
     subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
                     "-o", str(so), str(c), "-lm"], check=True)
     env = dict(os.environ, EIK_ORACLE_LIB=str(so))
-    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle.py")],
-                       env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
+    return subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                           os.path.join(ROOT, "tests", test_file)],
+                          env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_reject_mutant(name, tmp_path):
+    r = run_pins_against(*MUTANTS[name], tmp_path, "test_oracle.py")
     assert r.returncode != 0, f"mutant {name} passed every pin:\n{r.stdout[-2000:]}"
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(MUTANTS3))
+def test_3d_pins_reject_mutant(name, tmp_path):
+    r = run_pins_against(*MUTANTS3[name], tmp_path, "test_oracle3d.py")
+    assert r.returncode != 0, f"mutant {name} passed every 3-D pin:\n{r.stdout[-2000:]}"
