@@ -283,6 +283,29 @@ int eik_solve3(int32_t nx, int32_t ny, int32_t nz, double h, const double* F, co
                int32_t nsrc, const int64_t* src, const double* q, double* u_out,
                int32_t device_ptrs, void* stream, eik3_stats* stats);
 
+/* Three dimensions, FMSM (Algorithm FMSM, Section 3.1, extended to 3-D as
+   Section 5 proposes): the approximate Fast Marching-Sweeping method on the
+   same grid, cells and update as eik_solve3.  Part I: Fast Marching on the
+   grid of cell centres (h^c = 8 h, coarse speed F at the cell centre: the mean
+   of the accessible ones among the one or two middle nodes per axis, else the
+   cell mean; coarse exit cost min q), on the device in one wave.  Part II: the
+   cells in that acceptance order (processed level by level: the cells of a
+   level are pairwise non-adjacent, which gives the same result as one at a
+   time), each swept once in every ordering its earlier neighbours allow (per
+   axis: ascending from an earlier low face, descending from an earlier high
+   face, both for both or none; ascending only along an axis one node thick),
+   with the update from the ordering's three upwind neighbours; cells holding
+   exit nodes and cells the coarse front never reaches are swept to
+   convergence.  The result bounds the exact solution from above and may stay
+   +inf behind obstacles that a cell's sweeps cannot go around.  Arguments,
+   pointer kinds and errors as eik_solve3; in addition ENOMEM if the coarse
+   front exceeds 12288 cells.  stats: rounds = levels, cell_visits = cells
+   processed, sweeps = sweeps over all cells, rounds_seconds = device time of
+   both parts. */
+int eik_fmsm3(int32_t nx, int32_t ny, int32_t nz, double h, const double* F, const uint8_t* mask,
+              int32_t nsrc, const int64_t* src, const double* q, double* u_out,
+              int32_t device_ptrs, void* stream, eik3_stats* stats);
+
 /* Message for the last failed call on this thread ("" if none). */
 const char* eik_last_error(void);
 

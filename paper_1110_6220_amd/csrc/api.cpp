@@ -85,7 +85,7 @@ static std::vector<DevBuf*> all_bufs(Workspace* w) {
                       &sv->slot, &sv->head, &sv->tail, &sv->inflight, &sv->cursor, &sv->ctl, &sv->inst})
       v.push_back(b);
   for (DevBuf* b : {&w->F, &w->u, &w->mask, &w->src, &w->q, &w->cF, &w->cmask, &w->cq, &w->cu,
-                    &w->cout, &w->crank, &w->fmm_spill, &w->sweep_stat, &w->sweep_dirty, &w->grid3, &w->F64,
+                    &w->cout, &w->crank, &w->fmm_spill, &w->sweep_stat, &w->sweep_dirty, &w->grid3, &w->fmsm3, &w->F64,
                     &w->u64, &w->ready_at, &w->trace,
                     &w->trace_n, &w->wall_in, &w->wall_cnt})
     v.push_back(b);

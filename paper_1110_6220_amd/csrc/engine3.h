@@ -40,4 +40,33 @@ hipError_t launch3_round(const Grid3& g, int round, int blocks, hipStream_t stre
 // resident 64-thread blocks of the round kernel per compute unit
 int round3_blocks_per_cu();
 
+// ---- FMSM in three dimensions (cells as in Grid3) --------------------------
+constexpr int kFront3 = 12288;  // coarse Fast Marching front held in LDS
+constexpr unsigned kErr3Front = 16u;
+
+struct Fmsm3 {
+  double* Uc;        // coarse values
+  double* dc;        // coarse h^c / F^c (+inf on coarse obstacles)
+  double* cq;        // coarse exit cost: min q of the cell's exit nodes (+inf: none)
+  uint8_t* lab;      // 0 far, 1 considered, 2 accepted
+  uint8_t* cacc;     // the cell holds an accessible node
+  int32_t* rank;     // processing position (-1: never processed)
+  int32_t* level;    // level of the processing order's dependency graph (-1: never)
+  int32_t* posf;     // position in the front
+  int32_t* srcs;     // coarse exit cells, unordered ...
+  int32_t* sorted;   // ... and by (cq, index)
+  int32_t* ctl;      // [0] coarse exit cells, [1] levels, [2] processed cells
+  unsigned long long* stats;  // [0] cells processed, [1] sweeps
+  double hc;         // coarse spacing 8 h
+};
+
+// fine preparation (h/F, u = +inf, exit nodes), the coarse problem, the
+// order of the coarse exit cells, and Fast Marching on the coarse grid (one
+// wave): cell ranks and levels; f.ctl[1] = number of levels.  g.err and the
+// f.ctl words must start at zero.
+hipError_t launch3f_prepare(const Grid3& g, const Fmsm3& f, hipStream_t stream);
+// Part II for the cells of one level (pairwise non-adjacent): `blocks` waves
+hipError_t launch3f_level(const Grid3& g, const Fmsm3& f, int level, int blocks, hipStream_t stream);
+int fmsm3_blocks_per_cu();
+
 }  // namespace eik

@@ -293,6 +293,423 @@ __global__ __launch_bounds__(64) void k3_round(Grid3 g, int round) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// FMSM in three dimensions (Algorithm FMSM extended as Section 5 proposes)
+// ---------------------------------------------------------------------------
+
+// Canonical order of the eight orderings (bit 0 x descending, bit 1 y
+// descending, bit 2 z descending): z ascending first, each z direction with
+// the 2-D order SW, NW, NE, SE: 0, 2, 3, 1, 4, 6, 7, 5.
+__device__ __forceinline__ int seq3(int q) { return (0x57641320u >> (4 * q)) & 7; }
+
+// Orderings allowed for a cell whose earlier-processed neighbours lie on
+// `faces` (bit 2 axis + side), in a grid one node thick along `thin` (bit
+// axis): per axis the ascending direction for a low face, the descending
+// one for a high face, both for both or none; ascending only on a thin axis.
+__device__ __forceinline__ uint32_t orderings3(int faces, int thin) {
+  int allow[3];
+  for (int a = 0; a < 3; ++a) {
+    const int lo = (faces >> (2 * a)) & 1, hi = (faces >> (2 * a + 1)) & 1;
+    allow[a] = (thin >> a) & 1 ? 1 : (lo || hi) ? (lo ? 1 : 0) | (hi ? 2 : 0) : 3;
+  }
+  uint32_t m = 0;
+  for (int d = 0; d < 8; ++d)
+    if (((allow[0] >> (d & 1)) & (allow[1] >> ((d >> 1) & 1)) & (allow[2] >> ((d >> 2) & 1)) & 1) != 0)
+      m |= 1u << d;
+  return m;
+}
+
+// One Gauss-Seidel sweep of the cell in LDS in ordering dir, anti-diagonal
+// planes (lane = (i, j) column); DIRECTIONAL: the update from the ordering's
+// three upwind neighbours only.  Returns whether a node decreased (wave-wide).
+template <bool DIRECTIONAL>
+__device__ __forceinline__ bool sweep_cell3(double* tu, const double* td, uint8_t* dec, int dir, int w,
+                                            int hg, int dp, int lane) {
+  const int ii = lane % C3, jj = lane / C3;
+  const int sx = (dir & 1) ? -1 : 1, sy = (dir & 2) ? -1 : 1, sz = (dir & 4) ? -1 : 1;
+  const int i = sx > 0 ? ii : w - 1 - ii, j = sy > 0 ? jj : hg - 1 - jj;
+  const bool col = ii < w && jj < hg;
+  bool changed = false;
+  for (int d = 0; d < w + hg + dp - 2; ++d) {
+    const int kk = d - ii - jj;
+    if (col && kk >= 0 && kk < dp) {
+      const int k = sz > 0 ? kk : dp - 1 - kk;
+      const int t = ((k + 1) * P3 + j + 1) * P3 + i + 1, ci = (k * C3 + j) * C3 + i;
+      double dl = td[ci];
+      double a, b, cc;
+      const double uo = tu[t];
+      if constexpr (DIRECTIONAL) {
+        a = tu[t - sx];
+        b = tu[t - sy * P3];
+        cc = tu[t - sz * P3 * P3];
+      } else {
+        const double uW = tu[t - 1], uE = tu[t + 1], uS = tu[t - P3], uN = tu[t + P3];
+        const double uD = tu[t - P3 * P3], uU = tu[t + P3 * P3];
+        a = uW < uE ? uW : uE;
+        b = uS < uN ? uS : uN;
+        cc = uD < uU ? uD : uU;
+      }
+      asm volatile("" : "+v"(dl));  // h/F joins the neighbours' LDS round trip
+      const double U = update3(a, b, cc, dl);
+      if (U < uo) {
+        tu[t] = U;
+        dec[ci] = 1;
+        changed = true;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+  return __ballot(changed) != 0ull;
+}
+
+__device__ __forceinline__ int nb_cell3(const Grid3& g, int c, int e) {
+  const int cx = c % g.kx, cy = (c / g.kx) % g.ky, cz = c / (g.kx * g.ky);
+  switch (e) {
+    case 0: return cx > 0 ? c - 1 : -1;
+    case 1: return cx + 1 < g.kx ? c + 1 : -1;
+    case 2: return cy > 0 ? c - g.kx : -1;
+    case 3: return cy + 1 < g.ky ? c + g.kx : -1;
+    case 4: return cz > 0 ? c - g.kx * g.ky : -1;
+    default: return cz + 1 < g.kz ? c + g.kx * g.ky : -1;
+  }
+}
+
+__device__ __forceinline__ int wave_max_i(int v) {
+  for (int off = 32; off >= 1; off >>= 1) {
+    const int o = __shfl_xor(v, off);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+__global__ void k3f_init(Grid3 g, Fmsm3 f) {
+  const int J = g.kx * g.ky * g.kz;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < J; c += gridDim.x * blockDim.x)
+    f.cq[c] = __builtin_huge_val();
+}
+
+// Exit nodes: validation, u = min q, frozen (h/F = +inf); the coarse exit
+// cost of their cell (min q).
+__global__ void k3f_sources(Grid3 g, Fmsm3 f) {
+  const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < g.nsrc; s += gridDim.x * blockDim.x) {
+    const int64_t x = g.src[s];
+    const double q = g.q ? g.q[s] : 0.0;
+    if (x < 0 || x >= n || (g.mask && !g.mask[x]) || !isfinite(q)) {
+      __hip_atomic_fetch_or(g.err, kErr3Source, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      continue;
+    }
+    atomic_min_d(g.u + x, q);
+    g.delta[x] = __builtin_huge_val();
+    const int i = (int)(x % g.nx), j = (int)((x / g.nx) % g.ny), k = (int)(x / ((int64_t)g.nx * g.ny));
+    atomic_min_d(f.cq + ((k / C3) * g.ky + j / C3) * g.kx + i / C3, q);
+  }
+}
+
+// The coarse problem, one thread per cell: accessible or not; coarse speed F
+// at the cell centre (the mean of the accessible ones among the one or two
+// middle nodes per axis, added x outermost, then y, then z), else the mean of
+// F over the cell (each x-plane y outer, z inner, then the planes x
+// ascending); h^c / F^c; coarse exit cells listed.
+__global__ void k3f_coarse(Grid3 g, Fmsm3 f) {
+  const int J = g.kx * g.ky * g.kz;
+  const int64_t sxy = (int64_t)g.nx * g.ny;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < J; c += gridDim.x * blockDim.x) {
+    const int cx = c % g.kx, cy = (c / g.kx) % g.ky, cz = c / (g.kx * g.ky);
+    const int lo[3] = {cx * C3, cy * C3, cz * C3};
+    const int hi[3] = {cell_lo3(cx + 1, g.nx), cell_lo3(cy + 1, g.ny), cell_lo3(cz + 1, g.nz)};
+    double sum = 0.0;
+    int cnt = 0;
+    for (int i = lo[0]; i < hi[0]; ++i) {
+      double pl = 0.0;
+      for (int j = lo[1]; j < hi[1]; ++j)
+        for (int k = lo[2]; k < hi[2]; ++k) {
+          const int64_t x = k * sxy + (int64_t)j * g.nx + i;
+          if (g.mask && !g.mask[x]) continue;
+          pl += g.F[x];
+          cnt++;
+        }
+      sum += pl;
+    }
+    double Fc = cnt > 0 ? sum / cnt : 1.0;
+    const int is0 = (lo[0] + hi[0] - 1) / 2, is1 = (lo[0] + hi[0]) / 2;
+    const int js0 = (lo[1] + hi[1] - 1) / 2, js1 = (lo[1] + hi[1]) / 2;
+    const int ks0 = (lo[2] + hi[2] - 1) / 2, ks1 = (lo[2] + hi[2]) / 2;
+    double sc = 0.0;
+    int nc = 0;
+    for (int a = 0; a < (is0 == is1 ? 1 : 2); ++a)
+      for (int b = 0; b < (js0 == js1 ? 1 : 2); ++b)
+        for (int e = 0; e < (ks0 == ks1 ? 1 : 2); ++e) {
+          const int64_t x = (e ? ks1 : ks0) * sxy + (int64_t)(b ? js1 : js0) * g.nx + (a ? is1 : is0);
+          if (g.mask && !g.mask[x]) continue;
+          sc += g.F[x];
+          nc++;
+        }
+    if (nc > 0) Fc = sc / nc;
+    const double q = f.cq[c];
+    f.cacc[c] = cnt > 0;
+    f.dc[c] = cnt > 0 ? f.hc / Fc : __builtin_huge_val();
+    f.Uc[c] = q;  // +inf unless an exit cell
+    f.lab[c] = 0;
+    f.rank[c] = -1;
+    f.level[c] = -1;
+    if (q < __builtin_huge_val()) {
+      const int slot = __hip_atomic_fetch_add(&f.ctl[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      f.srcs[slot] = c;
+    }
+  }
+}
+
+// Coarse exit cells by (q, index): the position of each is the number of
+// cells before it.
+__global__ void k3f_src_rank(Grid3 g, Fmsm3 f) {
+  const int ns = f.ctl[0];
+  for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < ns; a += gridDim.x * blockDim.x) {
+    const int ca = f.srcs[a];
+    const double qa = f.cq[ca];
+    int r = 0;
+    for (int b = 0; b < ns; ++b) {
+      const int cb = f.srcs[b];
+      const double qb = f.cq[cb];
+      r += (qb < qa || (qb == qa && cb < ca)) ? 1 : 0;
+    }
+    f.sorted[r] = ca;
+  }
+}
+
+// Fast Marching on the coarse grid (one wave), in the CPU oracle's order: the
+// exit cells first, accepted together and then relaxed in (q, index) order;
+// then the smallest (value, index) cell of the front, whose six neighbours
+// are relaxed with the update from all six of their current neighbour values.
+// The front is unordered in LDS; each acceptance is a wave-wide argmin.  The
+// rank of a cell is its acceptance position, its level one more than the
+// highest level among its earlier neighbours; accessible cells the front
+// never reaches follow in index order.
+__global__ __launch_bounds__(64) void k3f_fmm(Grid3 g, Fmsm3 f) {
+  __shared__ double fv[kFront3];
+  __shared__ int32_t fi[kFront3];
+  const int lane = threadIdx.x;
+  if (ld_coh(g.err)) return;  // invalid input: reported by the host
+  const int J = g.kx * g.ky * g.kz;
+  const int ns = ld_coh(&f.ctl[0]);
+  const double INF = __builtin_huge_val();
+  int maxlv = -1, na = 0, nf = 0;
+  // level of cell c at position r: one more than the highest level among
+  // neighbours with a smaller position
+  auto place = [&](int c, int r) {
+    int lv = -1;
+    if (lane < 6) {
+      const int nb = nb_cell3(g, c, lane);
+      if (nb >= 0) {
+        const int rn = ld_coh(&f.rank[nb]);
+        if (rn >= 0 && rn < r) lv = ld_coh(&f.level[nb]);
+      }
+    }
+    lv = wave_max_i(lv) + 1;
+    if (lane == 0) {
+      st_coh(&f.rank[c], r);
+      st_coh(&f.level[c], lv);
+      st_coh(&f.lab[c], (uint8_t)2);
+    }
+    maxlv = lv > maxlv ? lv : maxlv;
+    __builtin_amdgcn_s_waitcnt(0);
+  };
+  // relaxes the six neighbours of cell x (pairwise non-adjacent: one lane each)
+  auto relax = [&](int x) -> bool {
+    int nb = -1;
+    bool fresh = false;
+    double u = INF;
+    if (lane < 6) {
+      nb = nb_cell3(g, x, lane);
+      if (nb >= 0 && (!f.cacc[nb] || ld_coh(&f.lab[nb]) == 2)) nb = -1;
+      if (nb >= 0) {
+        double v[6];
+        for (int e = 0; e < 6; ++e) {
+          const int m = nb_cell3(g, nb, e);
+          v[e] = m >= 0 ? ld_coh(&f.Uc[m]) : INF;
+        }
+        const double a = v[0] < v[1] ? v[0] : v[1], b = v[2] < v[3] ? v[2] : v[3],
+                     cc = v[4] < v[5] ? v[4] : v[5];
+        const double t = update3(a, b, cc, f.dc[nb]);
+        u = ld_coh(&f.Uc[nb]);
+        if (t < u) {
+          u = t;
+          st_coh(&f.Uc[nb], t);
+        }
+        if (ld_coh(&f.lab[nb]) == 0) {
+          st_coh(&f.lab[nb], (uint8_t)1);
+          fresh = true;
+        } else {
+          fv[ld_coh(&f.posf[nb])] = u;
+        }
+      }
+    }
+    const unsigned long long m = __ballot(fresh);
+    const int add = __popcll(m);
+    if (nf + add > kFront3) return false;
+    if (fresh) {
+      const int p = nf + __popcll(m & ((1ull << lane) - 1ull));
+      fv[p] = u;
+      fi[p] = nb;
+      st_coh(&f.posf[nb], p);
+    }
+    nf += add;
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    return true;
+  };
+  bool ok = true;
+  for (int s = 0; s < ns; ++s) place(f.sorted[s], s);
+  na = ns;
+  for (int s = 0; s < ns && ok; ++s) ok = relax(f.sorted[s]);
+  while (ok && nf > 0) {
+    double bv = INF;
+    int bi = 0x7fffffff, bp = -1;
+    for (int p = lane; p < nf; p += 64) {
+      const double v = fv[p];
+      const int c = fi[p];
+      if (v < bv || (v == bv && c < bi)) {
+        bv = v;
+        bi = c;
+        bp = p;
+      }
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+      const double ov = __shfl_xor(bv, off);
+      const int oi = __shfl_xor(bi, off), op = __shfl_xor(bp, off);
+      if (ov < bv || (ov == bv && oi < bi)) {
+        bv = ov;
+        bi = oi;
+        bp = op;
+      }
+    }
+    if (lane == 0 && bp != nf - 1) {  // the last entry fills the hole
+      fv[bp] = fv[nf - 1];
+      fi[bp] = fi[nf - 1];
+      st_coh(&f.posf[fi[bp]], bp);
+    }
+    --nf;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    place(bi, na++);
+    ok = relax(bi);
+  }
+  if (!ok) {
+    if (lane == 0) __hip_atomic_fetch_or(g.err, kErr3Front, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
+  // accessible cells the coarse front never reached, in index order
+  for (int base = 0; base < J; base += 64) {
+    const int c = base + lane;
+    const bool left = c < J && f.cacc[c] && ld_coh(&f.lab[c]) != 2;
+    unsigned long long m = __ballot(left);
+    while (m) {
+      const int k = __builtin_ctzll(m);
+      m &= m - 1ull;
+      place(base + k, na++);
+    }
+  }
+  if (lane == 0) {
+    st_coh(&f.ctl[1], maxlv + 1);
+    st_coh(&f.ctl[2], na);
+  }
+}
+
+// Part II for the cells of one level, one wave per cell: cells holding exit
+// nodes and cells the coarse front never reached are swept to convergence
+// cycling the orderings with the standard update; the others are swept once
+// in each ordering their earlier neighbours allow, with the directional
+// update.
+__global__ __launch_bounds__(64) void k3f_level(Grid3 g, Fmsm3 f, int level) {
+  __shared__ double tu[P3 * P3 * P3];
+  __shared__ double td[C3 * C3 * C3];
+  __shared__ uint8_t dec[C3 * C3 * C3];
+  const int lane = threadIdx.x;
+  const double INF = __builtin_huge_val();
+  const int J = g.kx * g.ky * g.kz;
+  const int64_t sxy = (int64_t)g.nx * g.ny;
+  const int thin = (g.nx == 1 ? 1 : 0) | (g.ny == 1 ? 2 : 0) | (g.nz == 1 ? 4 : 0);
+  unsigned long long nvis = 0, nsw = 0;
+  for (int c = blockIdx.x; c < J; c += gridDim.x) {
+    if (f.level[c] != level) continue;
+    const int rc = f.rank[c];
+    const bool conv = f.cq[c] < INF || f.Uc[c] == INF;
+    int faces = 0;
+    if (lane < 6) {
+      const int nb = nb_cell3(g, c, lane);
+      if (nb >= 0) {
+        const int rn = f.rank[nb];
+        if (rn >= 0 && rn < rc) faces = 1 << lane;
+      }
+    }
+    for (int off = 32; off >= 1; off >>= 1) faces |= __shfl_xor(faces, off);
+    const uint32_t mask = orderings3(faces, thin);
+    const int cx = c % g.kx, cy = (c / g.kx) % g.ky, cz = c / (g.kx * g.ky);
+    const int x0 = cx * C3, y0 = cy * C3, z0 = cz * C3;
+    const int w = cell_lo3(cx + 1, g.nx) - x0, hg = cell_lo3(cy + 1, g.ny) - y0,
+              dp = cell_lo3(cz + 1, g.nz) - z0;
+    constexpr int NT = (P3 * P3 * P3 + 63) / 64, ND = C3 * C3 * C3 / 64;
+    double vu[NT], vd[ND];
+#pragma unroll
+    for (int r = 0; r < NT; ++r) {
+      const int t = lane + 64 * r;
+      const int a = t % P3 - 1, b = (t / P3) % P3 - 1, e = t / (P3 * P3) - 1;
+      const int i = x0 + a, j = y0 + b, k = z0 + e;
+      const bool in = t < P3 * P3 * P3 && a <= w && b <= hg && e <= dp && i >= 0 && j >= 0 &&
+                      k >= 0 && i < g.nx && j < g.ny && k < g.nz;
+      vu[r] = in ? ld_coh(g.u + (k * sxy + (int64_t)j * g.nx + i)) : INF;
+    }
+#pragma unroll
+    for (int r = 0; r < ND; ++r) {
+      const int t = lane + 64 * r;
+      const int a = t % C3, b = (t / C3) % C3, e = t / (C3 * C3);
+      const bool in = a < w && b < hg && e < dp;
+      vd[r] = in ? g.delta[(z0 + e) * sxy + (int64_t)(y0 + b) * g.nx + x0 + a] : INF;
+    }
+#pragma unroll
+    for (int r = 0; r < NT; ++r)
+      if (lane + 64 * r < P3 * P3 * P3) tu[lane + 64 * r] = vu[r];
+#pragma unroll
+    for (int r = 0; r < ND; ++r) {
+      td[lane + 64 * r] = vd[r];
+      dec[lane + 64 * r] = 0;
+    }
+    __syncthreads();
+    if (conv) {
+      for (int sw = 0;; ++sw) {
+        ++nsw;
+        if (!sweep_cell3<false>(tu, td, dec, seq3(sw & 7), w, hg, dp, lane)) break;
+        if (sw > 4096) {
+          if (lane == 0) __hip_atomic_fetch_or(g.err, kErr3Guard, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+    } else {
+      for (int qq = 0; qq < 8; ++qq) {
+        const int d = seq3(qq);
+        if (!((mask >> d) & 1u)) continue;
+        ++nsw;
+        sweep_cell3<true>(tu, td, dec, d, w, hg, dp, lane);
+      }
+    }
+    ++nvis;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ND; ++r) {
+      const int t = lane + 64 * r;
+      const int a = t % C3, b = (t / C3) % C3, e = t / (C3 * C3);
+      if (a < w && b < hg && e < dp && dec[t])
+        st_coh(g.u + (z0 + e) * sxy + (int64_t)(y0 + b) * g.nx + x0 + a,
+               tu[((e + 1) * P3 + b + 1) * P3 + a + 1]);
+    }
+    __syncthreads();  // the next cell reuses the LDS arrays
+  }
+  if (lane == 0 && nvis) {
+    __hip_atomic_fetch_add(&f.stats[0], nvis, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&f.stats[1], nsw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 int grid_for3(int64_t n, int block, int cap) {
   int64_t b = (n + block - 1) / block;
   if (b < 1) b = 1;
@@ -312,6 +729,31 @@ hipError_t launch3_prepare(const Grid3& g, hipStream_t stream) {
 hipError_t launch3_round(const Grid3& g, int round, int blocks, hipStream_t stream) {
   hipLaunchKernelGGL(k3_round, dim3(blocks), dim3(64), 0, stream, g, round);
   return hipGetLastError();
+}
+
+hipError_t launch3f_prepare(const Grid3& g, const Fmsm3& f, hipStream_t stream) {
+  const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+  const int J = g.kx * g.ky * g.kz;
+  hipLaunchKernelGGL(k3_prep, dim3(grid_for3(n, 256, 8192)), dim3(256), 0, stream, g);
+  hipLaunchKernelGGL(k3f_init, dim3(grid_for3(J, 256, 4096)), dim3(256), 0, stream, g, f);
+  hipLaunchKernelGGL(k3f_sources, dim3(grid_for3(g.nsrc, 256, 1024)), dim3(256), 0, stream, g, f);
+  hipLaunchKernelGGL(k3f_coarse, dim3(grid_for3(J, 64, 4096)), dim3(64), 0, stream, g, f);
+  hipLaunchKernelGGL(k3f_src_rank, dim3(grid_for3(J, 256, 4096)), dim3(256), 0, stream, g, f);
+  hipLaunchKernelGGL(k3f_fmm, dim3(1), dim3(64), 0, stream, g, f);
+  return hipGetLastError();
+}
+
+hipError_t launch3f_level(const Grid3& g, const Fmsm3& f, int level, int blocks, hipStream_t stream) {
+  hipLaunchKernelGGL(k3f_level, dim3(blocks), dim3(64), 0, stream, g, f, level);
+  return hipGetLastError();
+}
+
+int fmsm3_blocks_per_cu() {
+  int b = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, reinterpret_cast<const void*>(k3f_level), 64, 0) !=
+          hipSuccess || b < 1)
+    b = 1;
+  return b;
 }
 
 int round3_blocks_per_cu() {

@@ -70,6 +70,7 @@ struct Workspace {
   DevBuf crank, fmm_spill;            // coarse Fast Marching (FMSM)
   DevBuf sweep_stat, sweep_dirty;     // whole-grid sweeping
   DevBuf grid3;                       // 3-D solver: cell marks, round lists, counters
+  DevBuf fmsm3;                       // 3-D FMSM: coarse grid, ranks, levels
   DevBuf F64, u64;                    // FP64 re-solve of FP32 problems
   DevBuf ready_at, trace, trace_n;    // diagnostic trace (EIK_TRACE)
   DevBuf wall_in, wall_cnt;           // wall density of masked problems

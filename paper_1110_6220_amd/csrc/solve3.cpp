@@ -26,15 +26,11 @@ int validate3_host(int64_t n, const double* F, const uint8_t* mask, int32_t nsrc
   return EIK_OK;
 }
 
-int solve3(int32_t nx, int32_t ny, int32_t nz, double h, const double* F, const uint8_t* mask,
-           int32_t nsrc, const int64_t* src, const double* q, double* u_out, bool dev,
-           hipStream_t stream, eik3_stats* stats) {
-  Workspace* ws = nullptr;
-  int rc = workspace(&ws);
-  if (rc) return rc;
-  std::unique_lock<std::mutex> lk(ws->mu);
+// Fills the grid description and stages host inputs (device_ptrs = 0).
+int stage3(Workspace* ws, int32_t nx, int32_t ny, int32_t nz, double h, const double* F,
+           const uint8_t* mask, int32_t nsrc, const int64_t* src, const double* q, double* u_out,
+           bool dev, hipStream_t stream, Grid3& g) {
   const int64_t n = (int64_t)nx * ny * nz;
-  Grid3 g;
   std::memset(&g, 0, sizeof g);
   g.h = h;
   g.nx = nx;
@@ -44,8 +40,7 @@ int solve3(int32_t nx, int32_t ny, int32_t nz, double h, const double* F, const 
   g.kx = (nx + kCell3 - 1) / kCell3;
   g.ky = (ny + kCell3 - 1) / kCell3;
   g.kz = (nz + kCell3 - 1) / kCell3;
-  const int64_t J = (int64_t)g.kx * g.ky * g.kz;
-  if (J > (1ll << 30)) return fail(EIK_EINVAL, "too many cells");
+  if ((int64_t)g.kx * g.ky * g.kz > (1ll << 30)) return fail(EIK_EINVAL, "too many cells");
   if (dev) {
     g.u = u_out;
     g.F = F;
@@ -74,6 +69,20 @@ int solve3(int32_t nx, int32_t ny, int32_t nz, double h, const double* F, const 
   }
   HIP_TRY(ws->fine.delta.ensure(n * sizeof(double)));
   g.delta = ws->fine.delta.as<double>();
+  return EIK_OK;
+}
+
+int solve3(int32_t nx, int32_t ny, int32_t nz, double h, const double* F, const uint8_t* mask,
+           int32_t nsrc, const int64_t* src, const double* q, double* u_out, bool dev,
+           hipStream_t stream, eik3_stats* stats) {
+  Workspace* ws = nullptr;
+  int rc = workspace(&ws);
+  if (rc) return rc;
+  std::unique_lock<std::mutex> lk(ws->mu);
+  const int64_t n = (int64_t)nx * ny * nz;
+  Grid3 g;
+  if ((rc = stage3(ws, nx, ny, nz, h, F, mask, nsrc, src, q, u_out, dev, stream, g))) return rc;
+  const int64_t J = (int64_t)g.kx * g.ky * g.kz;
   // statistics (two 64-bit words, first so that their atomics are 8-byte
   // aligned: the allocation is 256-byte aligned), the three round counters,
   // the error word and the busy-round count; then per cell the mark, the
@@ -139,14 +148,86 @@ int solve3(int32_t nx, int32_t ny, int32_t nz, double h, const double* F, const 
   return EIK_OK;
 }
 
+// FMSM in three dimensions: preparation and coarse Fast Marching, then one
+// launch per level of the processing order.
+int fmsm3(int32_t nx, int32_t ny, int32_t nz, double h, const double* F, const uint8_t* mask,
+          int32_t nsrc, const int64_t* src, const double* q, double* u_out, bool dev,
+          hipStream_t stream, eik3_stats* stats) {
+  Workspace* ws = nullptr;
+  int rc = workspace(&ws);
+  if (rc) return rc;
+  std::unique_lock<std::mutex> lk(ws->mu);
+  const int64_t n = (int64_t)nx * ny * nz;
+  Grid3 g;
+  if ((rc = stage3(ws, nx, ny, nz, h, F, mask, nsrc, src, q, u_out, dev, stream, g))) return rc;
+  const int64_t J = (int64_t)g.kx * g.ky * g.kz;
+  // head (statistics first: 8-byte aligned, the allocation is 256-byte
+  // aligned; counters; error word), then per cell Uc, dc, cq (doubles), rank,
+  // level, posf, srcs, sorted (int32), lab, cacc (bytes)
+  constexpr size_t kHead = 64;
+  const size_t bytes = kHead + (size_t)J * (3 * sizeof(double) + 5 * sizeof(int32_t) + 2);
+  HIP_TRY(ws->fmsm3.ensure(bytes));
+  char* base = static_cast<char*>(ws->fmsm3.p);
+  if (reinterpret_cast<uintptr_t>(base) % 8) return fail(EIK_EDEVICE, "workspace is not 8-byte aligned");
+  Fmsm3 f;
+  f.stats = reinterpret_cast<unsigned long long*>(base);
+  f.ctl = reinterpret_cast<int32_t*>(base + 16);
+  g.err = reinterpret_cast<unsigned*>(base + 28);
+  double* d = reinterpret_cast<double*>(base + kHead);
+  f.Uc = d;
+  f.dc = d + J;
+  f.cq = d + 2 * J;
+  int32_t* w = reinterpret_cast<int32_t*>(d + 3 * J);
+  f.rank = w;
+  f.level = w + J;
+  f.posf = w + 2 * J;
+  f.srcs = w + 3 * J;
+  f.sorted = w + 4 * J;
+  f.lab = reinterpret_cast<uint8_t*>(w + 5 * J);
+  f.cacc = f.lab + J;
+  f.hc = (double)kCell3 * h;
+  HIP_TRY(hipMemsetAsync(base, 0, kHead, stream));
+  const double t0 = now_s();
+  HIP_TRY(hipEventRecord(ws->ev0, stream));
+  HIP_TRY(launch3f_prepare(g, f, stream));
+  int32_t* hb = ws->host3;  // pinned: the 32-byte head
+  HIP_TRY(hipMemcpyAsync(hb, base, 32, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  unsigned err = (unsigned)hb[7];
+  if (err & (kErr3Speed | kErr3Source))
+    return fail(EIK_EINVAL, "%s", (err & kErr3Speed) ? "a speed value is not positive and finite"
+                                                    : "a source is out of range, on an obstacle or has non-finite q");
+  if (err & kErr3Front)
+    return fail(EIK_ENOMEM, "the coarse Fast Marching front outgrew its %d entries", kFront3);
+  const int levels = hb[5];
+  const int blocks = (int)std::min<int64_t>(J, (int64_t)ws->cus * fmsm3_blocks_per_cu());
+  for (int L = 0; L < levels; ++L) HIP_TRY(launch3f_level(g, f, L, blocks, stream));
+  HIP_TRY(hipEventRecord(ws->ev1, stream));
+  HIP_TRY(hipMemcpyAsync(hb, base, 32, hipMemcpyDeviceToHost, stream));
+  if (!dev) HIP_TRY(hipMemcpyAsync(u_out, g.u, n * sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  if ((unsigned)hb[7] & kErr3Guard) return fail(EIK_ENOTCONV, "a cell's sweeps did not terminate");
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, ws->ev0, ws->ev1));
+  if (stats) {
+    const unsigned long long* st = reinterpret_cast<const unsigned long long*>(hb);
+    stats->seconds = now_s() - t0;
+    stats->rounds_seconds = ms * 1e-3;
+    stats->rounds = levels;
+    stats->cells = J;
+    stats->cell_visits = (int64_t)st[0];
+    stats->sweeps = (int64_t)st[1];
+  }
+  return EIK_OK;
+}
+
 }  // namespace
 }  // namespace eik
 
 using namespace eik;
 
-extern "C" int eik_solve3(int32_t nx, int32_t ny, int32_t nz, double h, const double* F,
-                          const uint8_t* mask, int32_t nsrc, const int64_t* src, const double* q,
-                          double* u_out, int32_t device_ptrs, void* stream, eik3_stats* stats) {
+static int check3(int32_t nx, int32_t ny, int32_t nz, double h, const double* F, const uint8_t* mask,
+                  int32_t nsrc, const int64_t* src, const double* q, double* u_out, int32_t device_ptrs) {
   g_err.clear();
   if (nx < 1 || ny < 1 || nz < 1) return fail(EIK_EINVAL, "grid %d x %d x %d is empty", nx, ny, nz);
   if ((long long)nx * ny * nz > (1ll << 31) - 1) return fail(EIK_EINVAL, "grid too large");
@@ -158,10 +239,25 @@ extern "C" int eik_solve3(int32_t nx, int32_t ny, int32_t nz, double h, const do
     const auto off = [](const void* p, size_t a) { return reinterpret_cast<uintptr_t>(p) % a != 0; };
     if (off(F, 8) || off(u_out, 8) || off(src, 8) || (q && off(q, 8)))
       return fail(EIK_EINVAL, "F, u_out, src and q must be 8-byte aligned");
-  } else {
-    const int rc = validate3_host((int64_t)nx * ny * nz, F, mask, nsrc, src, q);
-    if (rc) return rc;
+    return EIK_OK;
   }
+  return validate3_host((int64_t)nx * ny * nz, F, mask, nsrc, src, q);
+}
+
+extern "C" int eik_solve3(int32_t nx, int32_t ny, int32_t nz, double h, const double* F,
+                          const uint8_t* mask, int32_t nsrc, const int64_t* src, const double* q,
+                          double* u_out, int32_t device_ptrs, void* stream, eik3_stats* stats) {
+  const int rc = check3(nx, ny, nz, h, F, mask, nsrc, src, q, u_out, device_ptrs);
+  if (rc) return rc;
   return solve3(nx, ny, nz, h, F, mask, nsrc, src, q, u_out, device_ptrs != 0,
                 static_cast<hipStream_t>(stream), stats);
+}
+
+extern "C" int eik_fmsm3(int32_t nx, int32_t ny, int32_t nz, double h, const double* F,
+                         const uint8_t* mask, int32_t nsrc, const int64_t* src, const double* q,
+                         double* u_out, int32_t device_ptrs, void* stream, eik3_stats* stats) {
+  const int rc = check3(nx, ny, nz, h, F, mask, nsrc, src, q, u_out, device_ptrs);
+  if (rc) return rc;
+  return fmsm3(nx, ny, nz, h, F, mask, nsrc, src, q, u_out, device_ptrs != 0,
+               static_cast<hipStream_t>(stream), stats);
 }

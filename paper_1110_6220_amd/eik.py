@@ -24,7 +24,7 @@ SCHEDULES = {"auto": 0, "coarse": 1, "bands": 2, "fifo": 3}
 # Every function include/eik.h declares.
 EXPORTS = ("eik_solve", "eik_solve_batched", "eik_serve_create", "eik_serve_submit",
            "eik_serve_poll", "eik_serve_wait", "eik_serve_cancel", "eik_serve_destroy",
-           "eik_sweep_solve", "eik_solve3", "eik_last_error")
+           "eik_sweep_solve", "eik_solve3", "eik_fmsm3", "eik_last_error")
 
 
 class EikError(RuntimeError):
@@ -107,6 +107,8 @@ def _load() -> ctypes.CDLL:
     L.eik_serve_cancel.argtypes = [vp, ctypes.c_uint64]
     L.eik_serve_destroy.argtypes = [vp]
     L.eik_solve3.argtypes = [i32, i32, i32, ctypes.c_double, vp, vp, i32, vp, vp, vp, i32, vp,
+                             ctypes.POINTER(Stats3)]
+    L.eik_fmsm3.argtypes = [i32, i32, i32, ctypes.c_double, vp, vp, i32, vp, vp, vp, i32, vp,
                              ctypes.POINTER(Stats3)]
     L.eik_sweep_solve.argtypes = [i32, i32, ctypes.c_double, vp, vp, i32, vp, vp, vp,
                                   ctypes.POINTER(SweepOpts), vp, vp, ctypes.POINTER(SweepStats)]
@@ -249,10 +251,12 @@ def eik_sweep(F, h, src, q=None, mask=None, u_out=None, *, dtype="f64", locking=
     return u_out, mx[:k].copy(), cnt[:k].copy(), {f: getattr(st, f) for f, _ in st._fields_}
 
 
-def eik_solve3(F, h, src, q=None, mask=None, u_out=None):
-    """3-D exact solve (eik_solve3 of include/eik.h); F has shape (nz, ny, nx),
-    FP64.  numpy arrays are host inputs, torch tensors device inputs.
-    Returns (u, stats dict)."""
+def eik_solve3(F, h, src, q=None, mask=None, u_out=None, *, method="exact"):
+    """3-D solve (eik_solve3, or eik_fmsm3 with method="fmsm", of
+    include/eik.h); F has shape (nz, ny, nx), FP64.  numpy arrays are host
+    inputs, torch tensors device inputs.  Returns (u, stats dict)."""
+    if method not in ("exact", "fmsm"):
+        raise ValueError(f"method {method!r}: 'exact' or 'fmsm'")
     if _is_torch(F):
         import torch
         dev = F.device
@@ -278,8 +282,9 @@ def eik_solve3(F, h, src, q=None, mask=None, u_out=None):
         device = False
     nz, ny, nx = F_.shape
     st = Stats3()
-    _check(lib.eik_solve3(nx, ny, nz, float(h), ptr(F_), ptr(m_), nsrc, ptr(src_), ptr(q_), ptr(u),
-                          int(device), _stream_of(device), ctypes.byref(st)))
+    fn = lib.eik_solve3 if method == "exact" else lib.eik_fmsm3
+    _check(fn(nx, ny, nz, float(h), ptr(F_), ptr(m_), nsrc, ptr(src_), ptr(q_), ptr(u),
+              int(device), _stream_of(device), ctypes.byref(st)))
     return u, {f: getattr(st, f) for f, _ in st._fields_}
 
 

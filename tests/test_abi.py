@@ -173,11 +173,12 @@ def test_solve3_arguments_are_rejected_before_device_work():
     u = np.full(F.shape, 7.0)
     bad = F.copy()
     bad[1, 2, 3] = np.nan
-    for args in [(F, 0.0, [0]), (F, 0.1, [60]), (F, 0.1, [-1]), (bad, 0.1, [0]), (F, 0.1, [])]:
-        try:
-            eik.eik_solve3(args[0], args[1], args[2], u_out=u)
-        except eik.EikError as e:
-            assert e.code == eik.EIK_EINVAL, args[1:]
-        else:
-            raise AssertionError(args[1:])
+    for method in ("exact", "fmsm"):
+        for args in [(F, 0.0, [0]), (F, 0.1, [60]), (F, 0.1, [-1]), (bad, 0.1, [0]), (F, 0.1, [])]:
+            try:
+                eik.eik_solve3(args[0], args[1], args[2], u_out=u, method=method)
+            except eik.EikError as e:
+                assert e.code == eik.EIK_EINVAL, (method, args[1:])
+            else:
+                raise AssertionError((method, args[1:]))
     assert (u == 7.0).all()

@@ -93,3 +93,37 @@ def test_device_pointers_must_be_aligned(eik):
                             q.data_ptr(), buf.data_ptr() + 4, 1, eik._stream_of(True), None)
     assert rc == eik.EIK_EINVAL
     assert b"aligned" in eik.lib.eik_last_error()
+
+
+# --------------------------------------------------------------------------
+# FMSM in three dimensions: bitwise equal to the oracle's 3-D FMSM (same
+# coarse order, same orderings, same directional update), cells of 8^3 nodes
+# --------------------------------------------------------------------------
+
+def fmsm_cases():
+    rng = np.random.default_rng(33)
+    return [W.sine3(33, 33, 33, 0.5), W.sine3(41, 37, 29, 0.9, 1.5), W.sine3(33, 33, 33, 0.0),
+            W.boxes3(40, 24, 17, rng), W.boxes3(27, 30, 33, np.random.default_rng(5), nbox=10, nsrc=1),
+            boundary_exit(25), W.sine3(64, 64, 16, 0.5), W.sine3(1, 1, 1), W.sine3(2, 2, 70),
+            W.sine3(50, 30, 1, 0.7, 2.0)]
+
+
+@pytest.mark.parametrize("case", range(10))
+def test_fmsm3_matches_oracle_bitwise(eik, case):
+    w = fmsm_cases()[case]
+    V, st_o = O.fmsm3(O.Problem3.from_workload(w), 8)
+    F, src, q, mask = dev(w)
+    print(f"[gpu] 3-D FMSM {w['name']}", flush=True)
+    u, st = eik.eik_solve3(F, w["h"], src, q, mask, method="fmsm")
+    got = u.cpu().numpy()
+    assert np.array_equal(got, V)
+    assert st["sweeps"] == st_o["sweeps"] and st["cell_visits"] == st_o["removals"]
+
+
+def test_fmsm3_host_inputs_match_device_inputs(eik):
+    w = W.boxes3(30, 20, 25, np.random.default_rng(9))
+    print("[gpu] 3-D FMSM host vs device", flush=True)
+    uh, _ = eik.eik_solve3(w["F"], w["h"], w["src"], w["q"], w["mask"], method="fmsm")
+    F, src, q, mask = dev(w)
+    ud, _ = eik.eik_solve3(F, w["h"], src, q, mask, method="fmsm")
+    assert np.array_equal(uh, ud.cpu().numpy())
