@@ -563,6 +563,65 @@ __global__ __launch_bounds__(64) void k3f_fmm(Grid3 g, Fmsm3 f) {
   for (int s = 0; s < ns; ++s) place(f.sorted[s], s);
   na = ns;
   for (int s = 0; s < ns && ok; ++s) ok = relax(f.sorted[s]);
+  // Accepting cell x at position na: its level, then the relaxation of its
+  // six neighbours, with every load of the step issued together (indices
+  // outside the grid are clamped to a valid cell and their values ignored).
+  auto accept = [&](int x) -> bool {
+    int nb = -1;
+    if (lane < 6) nb = nb_cell3(g, x, lane);
+    const int nbs = nb >= 0 ? nb : x;
+    int mm[6];
+    for (int e = 0; e < 6; ++e) mm[e] = nb_cell3(g, nbs, e);
+    const int rn = ld_coh(&f.rank[nbs]);
+    const int lvn = ld_coh(&f.level[nbs]);
+    const uint8_t ln = ld_coh(&f.lab[nbs]);
+    const uint8_t an = f.cacc[nbs];
+    const double dn = f.dc[nbs], un = ld_coh(&f.Uc[nbs]);
+    const int pn = ld_coh(&f.posf[nbs]);
+    double v[6];
+    for (int e = 0; e < 6; ++e) v[e] = ld_coh(&f.Uc[mm[e] >= 0 ? mm[e] : nbs]);
+    for (int e = 0; e < 6; ++e) v[e] = mm[e] >= 0 ? v[e] : INF;
+    // level of x: one more than the highest among its earlier neighbours
+    const int lv = wave_max_i(lane < 6 && nb >= 0 && rn >= 0 ? lvn : -1) + 1;
+    maxlv = lv > maxlv ? lv : maxlv;
+    if (lane == 0) {
+      st_coh(&f.rank[x], na);
+      st_coh(&f.level[x], lv);
+      st_coh(&f.lab[x], (uint8_t)2);
+    }
+    // relaxation (the neighbours are pairwise non-adjacent: one lane each)
+    const bool live = lane < 6 && nb >= 0 && an && ln != 2;
+    bool fresh = false;
+    double u = un;
+    if (live) {
+      const double a = v[0] < v[1] ? v[0] : v[1], b = v[2] < v[3] ? v[2] : v[3],
+                   cc = v[4] < v[5] ? v[4] : v[5];
+      const double t = update3(a, b, cc, dn);
+      if (t < u) {
+        u = t;
+        st_coh(&f.Uc[nb], t);
+      }
+      if (ln == 0) {
+        st_coh(&f.lab[nb], (uint8_t)1);
+        fresh = true;
+      } else {
+        fv[pn] = u;
+      }
+    }
+    const unsigned long long m = __ballot(fresh);
+    const int add = __popcll(m);
+    if (nf + add > kFront3) return false;
+    if (fresh) {
+      const int p = nf + __popcll(m & ((1ull << lane) - 1ull));
+      fv[p] = u;
+      fi[p] = nb;
+      st_coh(&f.posf[nb], p);
+    }
+    nf += add;
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    return true;
+  };
   while (ok && nf > 0) {
     double bv = INF;
     int bi = 0x7fffffff, bp = -1;
@@ -591,8 +650,8 @@ __global__ __launch_bounds__(64) void k3f_fmm(Grid3 g, Fmsm3 f) {
     }
     --nf;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    place(bi, na++);
-    ok = relax(bi);
+    ok = accept(bi);
+    ++na;
   }
   if (!ok) {
     if (lane == 0) __hip_atomic_fetch_or(g.err, kErr3Front, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
