@@ -346,9 +346,11 @@ def bench_3d(sizes=(129, 257), reps=3):
     F = 1 + 0.5 sin(2 pi x) sin(2 pi y) sin(2 pi z) over the unit cube with a
     centre exit node: FP64, inputs resident on the device, median of `reps`
     calls; every result checked against the oracle's 3-D Fast Marching,
-    whose single-core time is reported beside it."""
+    whose single-core time is reported beside it.  At the first size also
+    3-D FMSM (eik_fmsm3), checked bit for bit against the oracle's."""
     import statistics
 
+    import numpy as np
     import torch
 
     import oracle
@@ -383,6 +385,23 @@ def bench_3d(sizes=(129, 257), reps=3):
                     "alg_GBps_over_rounds": 16.0 * n ** 3 / st["rounds_seconds"] / 1e9,
                     "cpu_oracle_fmm_nodes_per_s": n ** 3 / t_cpu})
         print(f"[bench] 3-D {n}^3: {ms:.2f} ms", file=sys.stderr, flush=True)
+        if n == sizes[0]:
+            # FMSM (cells of 8^3 nodes) on the same problem, checked bit for bit
+            eik.eik_solve3(F, w["h"], src, q, None, u_out=u, method="fmsm")
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                t = time.perf_counter()
+                _, sf = eik.eik_solve3(F, w["h"], src, q, None, u_out=u, method="fmsm")
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t)
+            V, so = oracle.fmsm3(oracle.Problem3.from_workload(w), 8)
+            fin = np.isfinite(ref)
+            out[-1]["fmsm"] = {"ms": statistics.median(ts) * 1e3, "levels": sf["rounds"],
+                               "sweeps_per_cell": sf["sweeps"] / sf["cells"],
+                               "bitwise_equal_oracle": bool(np.array_equal(u.cpu().numpy(), V)),
+                               "max_rel_above_exact": float(((V[fin] - ref[fin]) / ref[fin]).max())}
+            print(f"[bench] 3-D FMSM {n}^3: {out[-1]['fmsm']['ms']:.2f} ms", file=sys.stderr, flush=True)
     return out
 
 
