@@ -14,7 +14,8 @@ Beside the headline line's own fields it reports, from the same run:
   serving  Kruskal-maze requests (sides 129..2049, FP32 with the FP64 residual
            recheck) through the continuous-batching server under a 64 GiB
            budget: saturated throughput, then p50/p99 latency of Poisson
-           arrivals at half that request rate;
+           arrivals at 0.25 / 0.5 / 0.75 / 0.9 of that request rate, then all
+           at once under a 256 MiB budget (admission waits);
   early_termination
            the sweeping-method comparison of the Section 4 remark on stopping
            sweeping methods early, on this GPU: the 41 x 41 checkerboard at
@@ -22,7 +23,11 @@ Beside the headline line's own fields it reports, from the same run:
            Fast Sweeping and Locking Sweeping stopped after the sweep count at
            which their error ratio R first reaches FMSM's (28 and 38 sweeps:
            table tab:check41_sweepMaxChange B, which the oracle reproduces in
-           tests/test_oracle_sweeps.py), and run to convergence.
+           tests/test_oracle_sweeps.py), and run to convergence;
+  three_d  the 3-D exact solver at 129^3 and 257^3 and 3-D FMSM at 129^3;
+  cells    the headline workload at cell sides 8, 16, 32, 64 and the tuned
+           one, FP64 and FP32;
+  large    the 4097^2 checkerboard with rectangular obstacles, FP64 and FP32.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras]
 """
@@ -75,13 +80,15 @@ def main():
     ap.add_argument("--no-graph", action="store_true",
                     help="launch every step's kernels one by one instead of replaying the "
                          "captured HIP graph of the solve")
-    ap.add_argument("--only", choices=["batched", "serving", "early_termination", "three_d"],
+    ap.add_argument("--only", choices=["batched", "serving", "early_termination", "three_d", "cells",
+                                       "large"],
                     help="run one of the extra studies alone and print its JSON (no headline)")
     args = ap.parse_args()
     if args.only:
         runs = {"batched": lambda: bench_batched("f64", graph=not args.no_graph),
                 "serving": lambda: bench_serving(args.serve_requests),
-                "early_termination": bench_early_termination, "three_d": bench_3d}
+                "early_termination": bench_early_termination, "three_d": bench_3d,
+                "cells": bench_cells, "large": bench_large}
         print(json.dumps({args.only: runs[args.only]()}), flush=True)
         return
     if args.gpus != 1:
@@ -212,6 +219,10 @@ def main():
         line["early_termination"] = bench_early_termination()
         print("[bench] early termination done; 3-D", file=sys.stderr, flush=True)
         line["three_d"] = bench_3d()
+        print("[bench] 3-D done; cell sides", file=sys.stderr, flush=True)
+        line["cells"] = bench_cells()
+        print("[bench] cell sides done; 4097^2 checkerboard with obstacles", file=sys.stderr, flush=True)
+        line["large"] = bench_large()
     print(json.dumps(line), flush=True)
 
 
@@ -423,8 +434,10 @@ def _hop_depth(w):
 
 def bench_serving(count):
     """Maze requests through the server: saturated throughput, then Poisson
-    arrivals at half the saturated request rate (latency = submission to
-    completion, measured by the library)."""
+    arrivals at 0.25, 0.5, 0.75 and 0.9 times the saturated request rate
+    (latency = submission to completion, measured by the library); then the
+    same requests at once through a 256 MiB budget, which makes admission
+    wait for room."""
     import numpy as np
 
     import oracle
@@ -433,52 +446,167 @@ def bench_serving(count):
     for r in reqs:  # the client holds its speeds in the server's precision
         r["F32"] = np.ascontiguousarray(r["F"], dtype=np.float32)
     nodes = np.array([r["nx"] * r["ny"] for r in reqs], dtype=np.float64)
+
+    def submit_all(srv, arrivals=None):
+        tk = []
+        t0 = time.perf_counter()
+        for k, r in enumerate(reqs):
+            if arrivals is not None:
+                dt = arrivals[k] - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+            tk.append(srv.submit(r["F32"], r["h"], r["src"], r["q"], r["mask"]))
+        res = [srv.wait(x) for x in tk]
+        return res, time.perf_counter() - t0
+
+    points = []
     with eik.Server(64 << 30, dtype="f32", residual_check=True) as srv:
         for r in reqs[:8]:  # warm-up: workspaces of every lane
             srv.wait(srv.submit(r["F32"], r["h"], r["src"], r["q"], r["mask"]))
-        t0 = time.perf_counter()
-        tk = [srv.submit(r["F32"], r["h"], r["src"], r["q"], r["mask"]) for r in reqs]
-        res = [srv.wait(x) for x in tk]
-        t_sat = time.perf_counter() - t0
+        res, t_sat = submit_all(srv)
         rate = len(reqs) / t_sat
-        lam = 0.5 * rate
-        arr = workloads.poisson_arrivals(len(reqs), lam, seed=5)
-        tk = []
-        t0 = time.perf_counter()
-        for a, r in zip(arr, reqs):
-            dt = a - (time.perf_counter() - t0)
-            if dt > 0:
-                time.sleep(dt)
-            tk.append(srv.submit(r["F32"], r["h"], r["src"], r["q"], r["mask"]))
-        res2 = [srv.wait(x) for x in tk]
-        t_poi = time.perf_counter() - t0
-    lat = np.array([st["seconds"] for _, st in res2])
+        allres = list(res)
+        for frac in (0.25, 0.5, 0.75, 0.9):
+            lam = frac * rate
+            res2, t_poi = submit_all(srv, workloads.poisson_arrivals(len(reqs), lam, seed=5))
+            allres += res2
+            lat = np.array([st["seconds"] for _, st in res2])
+            points.append({"load": frac, "rate_per_s": lam, "value": nodes.sum() / t_poi,
+                           "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                           "p99_ms": float(np.percentile(lat, 99) * 1e3)})
+    with eik.Server(256 << 20, dtype="f32", residual_check=True) as srv:
+        res3, t_small = submit_all(srv)
+        allres += res3
+        lat3 = np.array([st["seconds"] for _, st in res3])
     # accuracy: every request certified by the FP64 residual recheck (or
     # re-solved in FP64); two requests against the oracle within the FP32 bound
     certified = all(st["fell_back_to_f64"] or 0.0 <= st["max_residual"] <= 4 * 2.0 ** -24
-                    for _, st in res + res2)
-    checks = []
+                    for _, st in allres)
+    checks, hops = [], []
     for k in (0, int(np.argmax(nodes))):
         U = oracle.fmm(oracle.Problem.from_workload(reqs[k]))
         fin = np.isfinite(U)
         err = float(np.abs(res[k][0].astype(np.float64)[fin] - U[fin]).max())
-        bound = (_hop_depth(reqs[k]) + 2) * 2.0 ** -24 * float(U[fin].max())
+        D = _hop_depth(reqs[k])
+        hops.append({"request": k, "side": reqs[k]["nx"], "hop_depth": D})
+        bound = (D + 2) * 2.0 ** -24 * float(U[fin].max())
         checks.append(err <= bound and np.array_equal(np.isfinite(res[k][0]), fin))
     passed = certified and all(checks)
+    half = points[1]
     return {
         "workload": f"{count} Kruskal-maze requests, sides log-U[129, 2049], corridors 4..16, "
                     "FP32 + FP64 residual recheck, 64 GiB budget",
         "nodes": float(nodes.sum()),
         "saturated_value": nodes.sum() / t_sat if passed else 0.0, "unit": "nodes/s",
         "saturated_requests_per_s": rate,
-        "poisson_rate_per_s": lam,
-        "poisson_value": nodes.sum() / t_poi if passed else 0.0,
-        "p50_ms": float(np.percentile(lat, 50) * 1e3),
-        "p99_ms": float(np.percentile(lat, 99) * 1e3),
-        "fell_back_to_f64": int(sum(st["fell_back_to_f64"] for _, st in res + res2)),
+        "poisson_rate_per_s": half["rate_per_s"],
+        "poisson_value": half["value"] if passed else 0.0,
+        "p50_ms": half["p50_ms"],
+        "p99_ms": half["p99_ms"],
+        "load_points": points,
+        "budget_256MiB": {"value": nodes.sum() / t_small if passed else 0.0,
+                          "requests_per_s": len(reqs) / t_small,
+                          "p50_ms": float(np.percentile(lat3, 50) * 1e3),
+                          "p99_ms": float(np.percentile(lat3, 99) * 1e3)},
+        "checked_requests": hops,
+        "fell_back_to_f64": int(sum(st["fell_back_to_f64"] for _, st in allres)),
         "accuracy": {"residual_certified": certified, "oracle_checks_passed": all(checks)},
     }
 
+
+def bench_cells(reps=5):
+    """The headline workload (1025^2 smooth speed, exit node at the centre) at
+    every cell side 8, 16, 32, 64 and the tuned one (cell = 0), FP64 and FP32:
+    median wall time of `reps` solves with device-resident inputs; FP64 gated
+    at 1e-12 relative against the oracle's Fast Marching, FP32 within
+    (nx + ny) 2^-24 max u."""
+    import statistics
+
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1110_6220_amd import eik, workloads
+    w = workloads.config(2)
+    U = oracle.fmm(oracle.Problem.from_workload(w))
+    fin = np.isfinite(U)
+    n = w["nx"] * w["ny"]
+    out = []
+    for dtype in ("f64", "f32"):
+        d = _to_dev(w, dtype)
+        u = torch.empty_like(d["F"])
+        for cell in (8, 16, 32, 64, 0):
+            def run():
+                return eik.eik_solve(d["F"], d["h"], d["src"], d["q"], None, u_out=u, dtype=dtype,
+                                     cell=cell, graph=True)
+            run()
+            torch.cuda.synchronize()
+            ts, st = [], None
+            for _ in range(reps):
+                t = time.perf_counter()
+                _, st = run()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t)
+            got = u.double().cpu().numpy()
+            if dtype == "f64":
+                ok = _max_rel(got, U) <= 1e-12
+            else:
+                ok = bool(np.abs(got[fin] - U[fin]).max() <= (w["nx"] + w["ny"]) * 2.0 ** -24 * U[fin].max())
+            ms = statistics.median(ts) * 1e3
+            out.append({"dtype": dtype, "cell": cell, "cell_used": int(st["cell_used"]), "ms": ms,
+                        "nodes_per_s": n / ms * 1e3 if ok else 0.0, "AvHR": st["AvHR"], "AvS": st["AvS"],
+                        "passed": ok})
+    return {"workload": "1025x1025 smooth speed F=1+0.5 sin(2pi x) sin(2pi y), centre exit node",
+            "runs": out}
+
+
+def bench_large(reps=3):
+    """The 4097 x 4097 checkerboard (16 x 16 squares, F ~ U[0.5, 2] per square)
+    with rectangular obstacles over >= 20% of the nodes, exit node at a corner,
+    FP64 and FP32 (with the FP64 residual recheck): median wall time with
+    device-resident inputs, gated against the oracle's Fast Marching (FP64:
+    1e-12 relative; FP32: (nx + ny) 2^-24 max u)."""
+    import statistics
+
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1110_6220_amd import eik, workloads
+    w = workloads.config(3)
+    U = oracle.fmm(oracle.Problem.from_workload(w))
+    fin = np.isfinite(U)
+    n = w["nx"] * w["ny"]
+    out = {"workload": "4097x4097 checkerboard of 16x16 squares with rectangular obstacles, "
+                       "exit node at a corner",
+           "obstacle_share": float(1.0 - w["mask"].mean()),
+           "unreachable_accessible_nodes": int((~fin & (w["mask"] != 0)).sum()), "runs": []}
+    for dtype in ("f64", "f32"):
+        d = _to_dev(w, dtype)
+        u = torch.empty_like(d["F"])
+        def run():
+            return eik.eik_solve(d["F"], d["h"], d["src"], d["q"], d["mask"], u_out=u, dtype=dtype,
+                                 residual_check=dtype == "f32")
+        run()
+        torch.cuda.synchronize()
+        ts, st = [], None
+        for _ in range(reps):
+            t = time.perf_counter()
+            _, st = run()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        got = u.double().cpu().numpy()
+        same_inf = bool(np.array_equal(np.isfinite(got), fin))
+        if dtype == "f64":
+            ok = same_inf and _max_rel(got, U) <= 1e-12
+        else:
+            ok = same_inf and bool(np.abs(got[fin] - U[fin]).max()
+                                   <= (w["nx"] + w["ny"]) * 2.0 ** -24 * U[fin].max())
+        ms = statistics.median(ts) * 1e3
+        out["runs"].append({"dtype": dtype, "ms": ms, "nodes_per_s": n / ms * 1e3 if ok else 0.0,
+                            "cell_used": int(st["cell_used"]), "AvHR": st["AvHR"], "AvS": st["AvS"],
+                            "passed": ok})
+    return out
 
 if __name__ == "__main__":
     main()
