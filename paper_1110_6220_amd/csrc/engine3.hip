@@ -26,6 +26,7 @@
 #include <stdint.h>
 
 #include "engine3.h"
+#include "wave.h"
 
 namespace eik {
 namespace {
@@ -375,13 +376,8 @@ __device__ __forceinline__ int nb_cell3(const Grid3& g, int c, int e) {
   }
 }
 
-__device__ __forceinline__ int wave_max_i(int v) {
-  for (int off = 32; off >= 1; off >>= 1) {
-    const int o = __shfl_xor(v, off);
-    v = o > v ? o : v;
-  }
-  return v;
-}
+// wave-wide maximum of small integers (DPP row exchanges)
+__device__ __forceinline__ int wave_max_i(int v) { return -wave::min_i(-v); }
 
 __global__ void k3f_init(Grid3 g, Fmsm3 f) {
   const int J = g.kx * g.ky * g.kz;
@@ -484,112 +480,153 @@ __global__ void k3f_src_rank(Grid3 g, Fmsm3 f) {
 // are relaxed with the update from all six of their current neighbour values.
 // The front is unordered in LDS; each acceptance is a wave-wide argmin.  The
 // rank of a cell is its acceptance position, its level one more than the
-// highest level among its earlier neighbours; accessible cells the front
-// never reaches follow in index order.
+// highest level among the neighbours accepted before it; accessible cells the
+// front never reaches follow in index order.  LOCAL: the coarse values,
+// states, levels and front positions live in LDS too (up to kLocal3 cells;
+// the front then holds every cell), else in device memory with coherent
+// accesses.
+constexpr int kLocal3 = 4928;  // 32 bytes of LDS per cell
+
+template <bool LOCAL>
+struct FmmSmem;
+template <>
+struct FmmSmem<false> {
+  double fv[kFront3];
+  int32_t fi[kFront3];
+};
+template <>
+struct FmmSmem<true> {
+  double fv[kLocal3];
+  double U[kLocal3];
+  double dc[kLocal3];
+  int16_t fi[kLocal3];
+  int16_t lvl[kLocal3];
+  int16_t pos[kLocal3];
+  uint8_t lab[kLocal3];
+  uint8_t acc[kLocal3];
+};
+
+template <bool LOCAL>
 __global__ __launch_bounds__(64) void k3f_fmm(Grid3 g, Fmsm3 f) {
-  __shared__ double fv[kFront3];
-  __shared__ int32_t fi[kFront3];
+  __shared__ FmmSmem<LOCAL> sm;
+  constexpr int CAP = LOCAL ? kLocal3 : kFront3;
   const int lane = threadIdx.x;
   if (ld_coh(g.err)) return;  // invalid input: reported by the host
   const int J = g.kx * g.ky * g.kz;
   const int ns = ld_coh(&f.ctl[0]);
   const double INF = __builtin_huge_val();
+  // state accessors (LDS, or device memory with coherent accesses)
+  auto ldU = [&](int c) -> double {
+    if constexpr (LOCAL) return sm.U[c]; else return ld_coh(&f.Uc[c]);
+  };
+  auto stU = [&](int c, double v) {
+    if constexpr (LOCAL) sm.U[c] = v; else st_coh(&f.Uc[c], v);
+  };
+  auto ldLab = [&](int c) -> int {
+    if constexpr (LOCAL) return sm.lab[c]; else return ld_coh(&f.lab[c]);
+  };
+  auto stLab = [&](int c, int v) {
+    if constexpr (LOCAL) sm.lab[c] = (uint8_t)v; else st_coh(&f.lab[c], (uint8_t)v);
+  };
+  auto ldLvl = [&](int c) -> int {
+    if constexpr (LOCAL) return sm.lvl[c]; else return ld_coh(&f.level[c]);
+  };
+  auto ldPos = [&](int c) -> int {
+    if constexpr (LOCAL) return sm.pos[c]; else return ld_coh(&f.posf[c]);
+  };
+  auto stPos = [&](int c, int p) {
+    if constexpr (LOCAL) sm.pos[c] = (int16_t)p; else st_coh(&f.posf[c], p);
+  };
+  auto sync = [&]() {
+    if constexpr (!LOCAL) __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  };
+  auto ldDc = [&](int c) -> double {
+    if constexpr (LOCAL) return sm.dc[c]; else return f.dc[c];
+  };
+  auto ldAcc = [&](int c) -> int {
+    if constexpr (LOCAL) return sm.acc[c]; else return f.cacc[c];
+  };
+  if constexpr (LOCAL) {
+    for (int c = lane; c < J; c += 64) {
+      sm.U[c] = f.Uc[c];
+      sm.dc[c] = f.dc[c];
+      sm.acc[c] = f.cacc[c];
+      sm.lab[c] = 0;
+    }
+    __syncthreads();
+  }
   int maxlv = -1, na = 0, nf = 0;
-  // level of cell c at position r: one more than the highest level among
-  // neighbours with a smaller position
-  auto place = [&](int c, int r) {
+  // cell c takes position na: rank, level (one more than the highest level
+  // among its accepted neighbours), accepted
+  auto place = [&](int c) {
     int lv = -1;
     if (lane < 6) {
       const int nb = nb_cell3(g, c, lane);
-      if (nb >= 0) {
-        const int rn = ld_coh(&f.rank[nb]);
-        if (rn >= 0 && rn < r) lv = ld_coh(&f.level[nb]);
-      }
+      if (nb >= 0 && ldLab(nb) == 2) lv = ldLvl(nb);
     }
     lv = wave_max_i(lv) + 1;
     if (lane == 0) {
-      st_coh(&f.rank[c], r);
-      st_coh(&f.level[c], lv);
-      st_coh(&f.lab[c], (uint8_t)2);
-    }
-    maxlv = lv > maxlv ? lv : maxlv;
-    __builtin_amdgcn_s_waitcnt(0);
-  };
-  // relaxes the six neighbours of cell x (pairwise non-adjacent: one lane each)
-  auto relax = [&](int x) -> bool {
-    int nb = -1;
-    bool fresh = false;
-    double u = INF;
-    if (lane < 6) {
-      nb = nb_cell3(g, x, lane);
-      if (nb >= 0 && (!f.cacc[nb] || ld_coh(&f.lab[nb]) == 2)) nb = -1;
-      if (nb >= 0) {
-        double v[6];
-        for (int e = 0; e < 6; ++e) {
-          const int m = nb_cell3(g, nb, e);
-          v[e] = m >= 0 ? ld_coh(&f.Uc[m]) : INF;
-        }
-        const double a = v[0] < v[1] ? v[0] : v[1], b = v[2] < v[3] ? v[2] : v[3],
-                     cc = v[4] < v[5] ? v[4] : v[5];
-        const double t = update3(a, b, cc, f.dc[nb]);
-        u = ld_coh(&f.Uc[nb]);
-        if (t < u) {
-          u = t;
-          st_coh(&f.Uc[nb], t);
-        }
-        if (ld_coh(&f.lab[nb]) == 0) {
-          st_coh(&f.lab[nb], (uint8_t)1);
-          fresh = true;
-        } else {
-          fv[ld_coh(&f.posf[nb])] = u;
-        }
+      if constexpr (LOCAL) {
+        sm.lvl[c] = (int16_t)lv;
+        f.rank[c] = na;
+        f.level[c] = lv;
+      } else {
+        st_coh(&f.rank[c], na);
+        st_coh(&f.level[c], lv);
       }
+      stLab(c, 2);
     }
-    const unsigned long long m = __ballot(fresh);
-    const int add = __popcll(m);
-    if (nf + add > kFront3) return false;
-    if (fresh) {
-      const int p = nf + __popcll(m & ((1ull << lane) - 1ull));
-      fv[p] = u;
-      fi[p] = nb;
-      st_coh(&f.posf[nb], p);
-    }
-    nf += add;
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    return true;
-  };
-  bool ok = true;
-  for (int s = 0; s < ns; ++s) place(f.sorted[s], s);
-  na = ns;
-  for (int s = 0; s < ns && ok; ++s) ok = relax(f.sorted[s]);
-  // Accepting cell x at position na: its level, then the relaxation of its
-  // six neighbours, with every load of the step issued together (indices
-  // outside the grid are clamped to a valid cell and their values ignored).
-  auto accept = [&](int x) -> bool {
-    int nb = -1;
-    if (lane < 6) nb = nb_cell3(g, x, lane);
-    const int nbs = nb >= 0 ? nb : x;
-    int mm[6];
-    for (int e = 0; e < 6; ++e) mm[e] = nb_cell3(g, nbs, e);
-    const int rn = ld_coh(&f.rank[nbs]);
-    const int lvn = ld_coh(&f.level[nbs]);
-    const uint8_t ln = ld_coh(&f.lab[nbs]);
-    const uint8_t an = f.cacc[nbs];
-    const double dn = f.dc[nbs], un = ld_coh(&f.Uc[nbs]);
-    const int pn = ld_coh(&f.posf[nbs]);
-    double v[6];
-    for (int e = 0; e < 6; ++e) v[e] = ld_coh(&f.Uc[mm[e] >= 0 ? mm[e] : nbs]);
-    for (int e = 0; e < 6; ++e) v[e] = mm[e] >= 0 ? v[e] : INF;
-    // level of x: one more than the highest among its earlier neighbours
-    const int lv = wave_max_i(lane < 6 && nb >= 0 && rn >= 0 ? lvn : -1) + 1;
     maxlv = lv > maxlv ? lv : maxlv;
-    if (lane == 0) {
-      st_coh(&f.rank[x], na);
-      st_coh(&f.level[x], lv);
-      st_coh(&f.lab[x], (uint8_t)2);
+    ++na;
+    sync();
+  };
+  // relaxes the six neighbours of the accepted cell x (pairwise
+  // non-adjacent: one lane each), every read of the step issued together;
+  // PLACE: x is placed first (its level from the same reads); false when the
+  // front would overflow
+  auto relax = [&](int x, bool PLACE) -> bool {
+    // coordinates once (no integer division per neighbour)
+    const int xx = x % g.kx, xy = (x / g.kx) % g.ky, xz = x / (g.kx * g.ky);
+    const int sy = g.kx, sz = g.kx * g.ky;
+    const int ax = lane == 0 ? -1 : lane == 1 ? 1 : 0, ay = lane == 2 ? -1 : lane == 3 ? 1 : 0,
+              az = lane == 4 ? -1 : lane == 5 ? 1 : 0;
+    const int nx = xx + ax, ny = xy + ay, nz = xz + az;
+    const bool nin = lane < 6 && nx >= 0 && ny >= 0 && nz >= 0 && nx < g.kx && ny < g.ky && nz < g.kz;
+    const int nb = nin ? x + ax + ay * sy + az * sz : -1;
+    const int nbs = nin ? nb : x;
+    const int bx = nin ? nx : xx, by = nin ? ny : xy, bz = nin ? nz : xz;
+    int mm[6];
+    mm[0] = bx > 0 ? nbs - 1 : -1;
+    mm[1] = bx + 1 < g.kx ? nbs + 1 : -1;
+    mm[2] = by > 0 ? nbs - sy : -1;
+    mm[3] = by + 1 < g.ky ? nbs + sy : -1;
+    mm[4] = bz > 0 ? nbs - sz : -1;
+    mm[5] = bz + 1 < g.kz ? nbs + sz : -1;
+    const int ln = ldLab(nbs);
+    const int lvn = ldLvl(nbs);
+    const int an = ldAcc(nbs);
+    const double dn = ldDc(nbs), un = ldU(nbs);
+    const int pn = ldPos(nbs);
+    double v[6];
+    for (int e = 0; e < 6; ++e) v[e] = ldU(mm[e] >= 0 ? mm[e] : nbs);
+    for (int e = 0; e < 6; ++e) v[e] = mm[e] >= 0 ? v[e] : INF;
+    if (PLACE) {
+      const int lv = wave_max_i(lane < 6 && nb >= 0 && ln == 2 ? lvn : -1) + 1;
+      if (lane == 0) {
+        if constexpr (LOCAL) {
+          sm.lvl[x] = (int16_t)lv;
+          f.rank[x] = na;
+          f.level[x] = lv;
+        } else {
+          st_coh(&f.rank[x], na);
+          st_coh(&f.level[x], lv);
+        }
+        stLab(x, 2);
+      }
+      maxlv = lv > maxlv ? lv : maxlv;
+      ++na;
     }
-    // relaxation (the neighbours are pairwise non-adjacent: one lane each)
     const bool live = lane < 6 && nb >= 0 && an && ln != 2;
     bool fresh = false;
     double u = un;
@@ -599,59 +636,62 @@ __global__ __launch_bounds__(64) void k3f_fmm(Grid3 g, Fmsm3 f) {
       const double t = update3(a, b, cc, dn);
       if (t < u) {
         u = t;
-        st_coh(&f.Uc[nb], t);
+        stU(nb, t);
       }
       if (ln == 0) {
-        st_coh(&f.lab[nb], (uint8_t)1);
+        stLab(nb, 1);
         fresh = true;
       } else {
-        fv[pn] = u;
+        sm.fv[pn] = u;
       }
     }
     const unsigned long long m = __ballot(fresh);
     const int add = __popcll(m);
-    if (nf + add > kFront3) return false;
+    if (nf + add > CAP) return false;
     if (fresh) {
       const int p = nf + __popcll(m & ((1ull << lane) - 1ull));
-      fv[p] = u;
-      fi[p] = nb;
-      st_coh(&f.posf[nb], p);
+      sm.fv[p] = u;
+      sm.fi[p] = nb;
+      stPos(nb, p);
     }
     nf += add;
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    sync();
     return true;
   };
+  bool ok = true;
+  for (int s = 0; s < ns; ++s) place(f.sorted[s]);  // sources: accepted in (q, index) order ...
+  for (int s = 0; s < ns && ok; ++s) ok = relax(f.sorted[s], false);  // ... then relaxed
   while (ok && nf > 0) {
+    // the (value, index) minimum of the front; each lane takes four of its
+    // slots per round so that their LDS reads are in flight together
     double bv = INF;
     int bi = 0x7fffffff, bp = -1;
-    for (int p = lane; p < nf; p += 64) {
-      const double v = fv[p];
-      const int c = fi[p];
-      if (v < bv || (v == bv && c < bi)) {
-        bv = v;
-        bi = c;
-        bp = p;
+    for (int t0 = lane; t0 < nf; t0 += 256) {
+      int cq[4];
+      double vq[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const bool in = t0 + 64 * k < nf;
+        cq[k] = in ? (int)sm.fi[t0 + 64 * k] : 0;
+        vq[k] = in ? sm.fv[t0 + 64 * k] : INF;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const bool take = t0 + 64 * k < nf && (vq[k] < bv || (vq[k] == bv && cq[k] < bi));
+        bv = take ? vq[k] : bv;
+        bi = take ? cq[k] : bi;
+        bp = take ? t0 + 64 * k : bp;
       }
     }
-    for (int off = 32; off >= 1; off >>= 1) {
-      const double ov = __shfl_xor(bv, off);
-      const int oi = __shfl_xor(bi, off), op = __shfl_xor(bp, off);
-      if (ov < bv || (ov == bv && oi < bi)) {
-        bv = ov;
-        bi = oi;
-        bp = op;
-      }
-    }
+    wave::argmin(bv, bi, bp, lane);
     if (lane == 0 && bp != nf - 1) {  // the last entry fills the hole
-      fv[bp] = fv[nf - 1];
-      fi[bp] = fi[nf - 1];
-      st_coh(&f.posf[fi[bp]], bp);
+      sm.fv[bp] = sm.fv[nf - 1];
+      sm.fi[bp] = sm.fi[nf - 1];
+      stPos(sm.fi[bp], bp);
     }
     --nf;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    ok = accept(bi);
-    ++na;
+    sync();
+    ok = relax(bi, true);
   }
   if (!ok) {
     if (lane == 0) __hip_atomic_fetch_or(g.err, kErr3Front, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -660,14 +700,16 @@ __global__ __launch_bounds__(64) void k3f_fmm(Grid3 g, Fmsm3 f) {
   // accessible cells the coarse front never reached, in index order
   for (int base = 0; base < J; base += 64) {
     const int c = base + lane;
-    const bool left = c < J && f.cacc[c] && ld_coh(&f.lab[c]) != 2;
+    const bool left = c < J && ldAcc(c) && ldLab(c) != 2;
     unsigned long long m = __ballot(left);
     while (m) {
       const int k = __builtin_ctzll(m);
       m &= m - 1ull;
-      place(base + k, na++);
+      place(base + k);
     }
   }
+  if constexpr (LOCAL)
+    for (int c = lane; c < J; c += 64) f.Uc[c] = sm.U[c];
   if (lane == 0) {
     st_coh(&f.ctl[1], maxlv + 1);
     st_coh(&f.ctl[2], na);
@@ -798,7 +840,10 @@ hipError_t launch3f_prepare(const Grid3& g, const Fmsm3& f, hipStream_t stream) 
   hipLaunchKernelGGL(k3f_sources, dim3(grid_for3(g.nsrc, 256, 1024)), dim3(256), 0, stream, g, f);
   hipLaunchKernelGGL(k3f_coarse, dim3(grid_for3(J, 64, 4096)), dim3(64), 0, stream, g, f);
   hipLaunchKernelGGL(k3f_src_rank, dim3(grid_for3(J, 256, 4096)), dim3(256), 0, stream, g, f);
-  hipLaunchKernelGGL(k3f_fmm, dim3(1), dim3(64), 0, stream, g, f);
+  if (J <= kLocal3)
+    hipLaunchKernelGGL(k3f_fmm<true>, dim3(1), dim3(64), 0, stream, g, f);
+  else
+    hipLaunchKernelGGL(k3f_fmm<false>, dim3(1), dim3(64), 0, stream, g, f);
   return hipGetLastError();
 }
 

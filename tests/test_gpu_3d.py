@@ -127,3 +127,16 @@ def test_fmsm3_host_inputs_match_device_inputs(eik):
     F, src, q, mask = dev(w)
     ud, _ = eik.eik_solve3(F, w["h"], src, q, mask, method="fmsm")
     assert np.array_equal(uh, ud.cpu().numpy())
+
+
+def test_fmsm3_coarse_grid_in_device_memory(eik):
+    """More coarse cells (20^3 = 8000) than the LDS-resident coarse Fast
+    Marching holds: the variant with its state in device memory, still
+    bitwise equal to the oracle."""
+    w = W.sine3(160, 160, 160, 0.5)
+    V, st_o = O.fmsm3(O.Problem3.from_workload(w), 8)
+    F, src, q, mask = dev(w)
+    print("[gpu] 3-D FMSM 160^3", flush=True)
+    u, st = eik.eik_solve3(F, w["h"], src, q, mask, method="fmsm")
+    assert np.array_equal(u.cpu().numpy(), V)
+    assert st["sweeps"] == st_o["sweeps"]
