@@ -46,9 +46,9 @@ def cases():
             W.sine3(64, 64, 16, 0.5), W.sine3(1, 1, 1), W.sine3(2, 2, 70), W.sine3(50, 30, 1)]
 
 
-@pytest.mark.parametrize("case", range(9))
+@pytest.mark.parametrize("case", range(10))
 def test_exact_3d_matches_fast_marching(eik, case):
-    w = cases()[case]
+    w = (cases() + [fmsm_special()])[case]
     U = O.fmm3(O.Problem3.from_workload(w))
     F, src, q, mask = dev(w)
     print(f"[gpu] 3-D {w['name']}", flush=True)
@@ -100,15 +100,32 @@ def test_device_pointers_must_be_aligned(eik):
 # coarse order, same orderings, same directional update), cells of 8^3 nodes
 # --------------------------------------------------------------------------
 
+def fmsm_special():
+    """Coarse obstacles (an 8-node wall on a cell layer sealing x >= 32),
+    unreached accessible cells behind it, and cells whose centre nodes are
+    all obstacles (their coarse speed falls back to the cell mean)."""
+    nx, ny, nz = 41, 27, 19
+    h = 1.0 / (max(nx, ny, nz) - 1)
+    z, y, x = np.meshgrid(np.arange(nz) * h, np.arange(ny) * h, np.arange(nx) * h, indexing="ij")
+    F = 1.0 + 0.6 * np.sin(5.0 * x) * np.cos(4.0 * y) * np.sin(3.0 * z + 0.5)
+    mask = np.ones((nz, ny, nx), dtype=np.uint8)
+    mask[:, :, 24:32] = 0                 # the wall: cells with cx = 3 are all obstacles
+    mask[3:5, 3:5, 3:5] = 0               # centre nodes of cell (0, 0, 0)
+    mask[11:13, 11:13, 11:13] = 0         # centre nodes of cell (1, 1, 1)
+    c = (9 * ny + 20) * nx + 13
+    return dict(name="fmsm_special", F=F, h=h, nx=nx, ny=ny, nz=nz, src=np.array([c], dtype=np.int64),
+                q=np.array([0.0]), mask=mask)
+
+
 def fmsm_cases():
     rng = np.random.default_rng(33)
     return [W.sine3(33, 33, 33, 0.5), W.sine3(41, 37, 29, 0.9, 1.5), W.sine3(33, 33, 33, 0.0),
             W.boxes3(40, 24, 17, rng), W.boxes3(27, 30, 33, np.random.default_rng(5), nbox=10, nsrc=1),
             boundary_exit(25), W.sine3(64, 64, 16, 0.5), W.sine3(1, 1, 1), W.sine3(2, 2, 70),
-            W.sine3(50, 30, 1, 0.7, 2.0)]
+            W.sine3(50, 30, 1, 0.7, 2.0), fmsm_special()]
 
 
-@pytest.mark.parametrize("case", range(10))
+@pytest.mark.parametrize("case", range(11))
 def test_fmsm3_matches_oracle_bitwise(eik, case):
     w = fmsm_cases()[case]
     V, st_o = O.fmsm3(O.Problem3.from_workload(w), 8)
