@@ -35,8 +35,9 @@ hipError_t launch3_prepare(const Grid3& g, hipStream_t stream);
 // round `round` (>= 1): its list length is read on the device, so rounds can
 // be enqueued without waiting; an empty round does nothing.  Each round also
 // zeroes the counter the round after it queues into.  `blocks` waves loop
-// over the list.
-hipError_t launch3_round(const Grid3& g, int round, int blocks, hipStream_t stream);
+// over the list.  cap > 0: at most cap sweeps per visit; a cell not yet
+// converged is listed again for the next round.
+hipError_t launch3_round(const Grid3& g, int round, int blocks, int cap, hipStream_t stream);
 // resident 64-thread blocks of the round kernel per compute unit
 int round3_blocks_per_cu();
 

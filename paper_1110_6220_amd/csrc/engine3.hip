@@ -21,7 +21,8 @@
 // values).  A wave performs its LDS accesses in order, so the previous
 // step's writes are visible without waiting; the order is a topological
 // order of the lexicographic sweep, which it therefore equals.  Sweeps cycle
-// through the orderings until one changes nothing.
+// through the orderings until one changes nothing, at most a capped number
+// per visit: a cell still changing is listed again for the next round.
 #include <math.h>
 #include <stdint.h>
 
@@ -142,7 +143,7 @@ __global__ void k3_sources(Grid3 g) {
 // cell (u) and h/F of the cell into LDS, sweeps until a sweep changes
 // nothing, stores the nodes that decreased and applies the add criterion on
 // the six faces.
-__global__ __launch_bounds__(64) void k3_round(Grid3 g, int round) {
+__global__ __launch_bounds__(64) void k3_round(Grid3 g, int round, int cap) {
   __shared__ double tu[P3 * P3 * P3];      // u on the cell and its one-node halo
   __shared__ double td[C3 * C3 * C3];      // h/F on the cell
   __shared__ uint8_t dec[C3 * C3 * C3];    // the node decreased in this visit
@@ -210,8 +211,9 @@ __global__ __launch_bounds__(64) void k3_round(Grid3 g, int round) {
       const int lo = (entry >> (2 * ax)) & 1, hi = (entry >> (2 * ax + 1)) & 1;
       if (lo != hi) ord[m++] = ax;
     }
-    // sweeps until one changes nothing
+    // sweeps until one changes nothing (at most `cap` per visit when cap > 0)
     const int ii = lane % C3, jj = lane / C3;
+    bool again = false;
     for (int sw = 0;; ++sw) {
       const int dir = base ^ ((sw & 1) << ord[0]) ^ (((sw >> 1) & 1) << ord[1]) ^ (((sw >> 2) & 1) << ord[2]);
       const int sx = (dir & 1) ? -1 : 1, sy = (dir & 2) ? -1 : 1, sz = (dir & 4) ? -1 : 1;
@@ -240,6 +242,10 @@ __global__ __launch_bounds__(64) void k3_round(Grid3 g, int round) {
       }
       ++nsw;
       if (__ballot(changed) == 0ull) break;
+      if (sw + 1 == cap) {  // not yet converged: the cell continues in the next round
+        again = true;
+        break;
+      }
       if (sw > 4096) {  // a cell solve terminates; guard anyway
         if (lane == 0) __hip_atomic_fetch_or(g.err, kErr3Guard, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
@@ -285,6 +291,10 @@ __global__ __launch_bounds__(64) void k3_round(Grid3 g, int round) {
           q = true;
       }
       if (__ballot(q) != 0ull && lane == 0) queue3(g, nb, round + 1, 2 * ax + (1 - side));
+    }
+    if (again && lane == 0) {  // the same entry faces, so that its next visit starts alike
+      __hip_atomic_fetch_or(&g.entry[c], entry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      enlist3(g, c, round + 1);
     }
     __syncthreads();  // the next cell reuses the LDS arrays
   }
@@ -827,8 +837,8 @@ hipError_t launch3_prepare(const Grid3& g, hipStream_t stream) {
   return hipGetLastError();
 }
 
-hipError_t launch3_round(const Grid3& g, int round, int blocks, hipStream_t stream) {
-  hipLaunchKernelGGL(k3_round, dim3(blocks), dim3(64), 0, stream, g, round);
+hipError_t launch3_round(const Grid3& g, int round, int blocks, int cap, hipStream_t stream) {
+  hipLaunchKernelGGL(k3_round, dim3(blocks), dim3(64), 0, stream, g, round, cap);
   return hipGetLastError();
 }
 
