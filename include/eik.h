@@ -261,7 +261,8 @@ int eik_sweep_solve(int32_t nx, int32_t ny, double h, const void* F, const uint8
    root of (U-m1)^2 + (U-m2)^2 + (U-m3)^2 = (h/F)^2.  Cells of 8 x 8 x 8 nodes
    (the last ones ragged) are processed in rounds: all queued cells at once,
    one wave each, and a cell is queued for the next round when a node on a
-   shared face decreased below the node across.  FP64 only.  F, mask, src, q,
+   shared face decreased below the node across (a visit makes at most three
+   sweeps; a cell still changing is queued again).  FP64 only.  F, mask, src, q,
    u_out are host arrays (device_ptrs = 0: copied in and out, validated
    before any device work) or device arrays on the current device
    (device_ptrs = 1: 8-byte aligned, else EINVAL; values validated on the
