@@ -35,6 +35,7 @@
 #include <stdint.h>
 
 #include "engine.h"
+#include "wave.h"
 
 namespace eik {
 namespace {
@@ -121,19 +122,7 @@ __device__ __forceinline__ float local_update(float a, float b, float dl) {
   return (fabs(dd) >= ddl) ? one : two;
 }
 
-// IEEE minNum without the compiler's NaN canonicalisation of the operands
-// (operands here are never signalling NaNs); a quiet NaN operand yields the
-// other operand.  ALU-only inline assembly.
-__device__ __forceinline__ double vmin(double a, double b) {
-  double r;
-  asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-  return r;
-}
-__device__ __forceinline__ float vmin(float a, float b) {
-  float r;
-  asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-  return r;
-}
+using wave::vmin;  // IEEE minNum without NaN canonicalisation (wave.h)
 
 // Lane l receives lane l-1's value; lane 0 receives `edge` (DPP wave_shr:1
 // with the out-of-range source replaced by the old value).
@@ -1457,58 +1446,6 @@ __global__ void k_coarse_sources(Engine e, const CoarseOut* co) {
 // a copy of the front values next to the front).
 constexpr int kFmmFar = -1, kFmmObst = -2, kFmmAcc = -3;
 
-// Cross-lane moves within 16-lane rows (DPP) and reductions to a
-// wave-uniform minimum: min over quads, half rows, rows, then the four row
-// results read from lanes 0, 16, 32 and 48.
-template <int CTRL>
-__device__ __forceinline__ int dpp_i(int v) {
-  return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, false);
-}
-template <int CTRL>
-__device__ __forceinline__ double dpp_d(double v) {
-  const long long b = __builtin_bit_cast(long long, v);
-  const int lo = dpp_i<CTRL>((int)b), hi = dpp_i<CTRL>((int)(b >> 32));
-  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ double readlane_d(double v, int l) {
-  const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
-}
-constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
-__device__ __forceinline__ double wave_min_d(double v) {
-  v = vmin(v, dpp_d<kDppXor1>(v));
-  v = vmin(v, dpp_d<kDppXor2>(v));
-  v = vmin(v, dpp_d<kDppHalfMirror>(v));
-  v = vmin(v, dpp_d<kDppMirror>(v));
-  return vmin(vmin(readlane_d(v, 0), readlane_d(v, 16)), vmin(readlane_d(v, 32), readlane_d(v, 48)));
-}
-__device__ __forceinline__ int wave_min_i(int v) {
-  v = min(v, dpp_i<kDppXor1>(v));
-  v = min(v, dpp_i<kDppXor2>(v));
-  v = min(v, dpp_i<kDppHalfMirror>(v));
-  v = min(v, dpp_i<kDppMirror>(v));
-  return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
-             min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
-}
-
-// Wave-wide minimum of the lanes' (v, c) in lexicographic order (values are
-// never NaN; lanes without an entry hold (+inf, INT_MAX)); returns the
-// winning lane's (v, c, slot), wave-uniform.
-__device__ __forceinline__ void wave_argmin(double& v, int& c, int& slot, int lane) {
-  const double vm = wave_min_d(v);
-  const unsigned long long tie = ballot(v == vm);
-  int win = __builtin_ctzll(tie);
-  if (tie & (tie - 1)) {  // equal values: the smallest cell index
-    const bool in = (tie >> lane) & 1ull;
-    const int cm = wave_min_i(in ? c : 0x7fffffff);
-    win = __builtin_ctzll(ballot(in && c == cm));
-  }
-  v = vm;
-  c = __builtin_amdgcn_readlane(c, win);
-  slot = __builtin_amdgcn_readlane(slot, win);
-}
-
 // FV: the spill layout (global memory, front values kept beside the front).
 // In the LDS layout every access inside the acceptance loop is an LDS access
 // of this one wave, which the LDS performs in order, so lanes see each
@@ -1577,7 +1514,7 @@ __device__ void coarse_fmm(const CoarseOut& C, int kx, int ky, double hc, int la
         bs = take ? t0 + 64 * u : bs;
       }
     }
-    wave_argmin(bv, bc, bs, lane);
+    wave::argmin(bv, bc, bs, lane);
     if (lane == 0) {
       if (exits) {  // the exit list shrinks from below
         if constexpr (FV) fv[bs] = fv[lo];

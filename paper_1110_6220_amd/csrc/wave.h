@@ -6,9 +6,17 @@
 namespace eik {
 namespace wave {
 
+// IEEE minNum without the compiler's NaN canonicalisation of the operands
+// (operands here are never signalling NaNs); a quiet NaN operand yields the
+// other operand.  ALU-only inline assembly.
 __device__ __forceinline__ double vmin(double a, double b) {
   double r;
   asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ float vmin(float a, float b) {
+  float r;
+  asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
   return r;
 }
 
