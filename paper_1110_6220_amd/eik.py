@@ -140,6 +140,27 @@ def _opts(dtype, method, cell, band, device, stream, residual_check, workers, ma
                 int(bool(graph)))
 
 
+def _check_arrays(shape, mask, q, nsrc, u_out, out_dtype, device):
+    """The library takes plain pointers and cannot see buffer sizes: the
+    arrays must match the grid before any call.  Raises ValueError."""
+    shape = tuple(shape)
+    if mask is not None and tuple(mask.shape) != shape:
+        raise ValueError(f"mask has shape {tuple(mask.shape)}, the grid {shape}")
+    if q is not None and (q.numel() if _is_torch(q) else q.size) != nsrc:
+        raise ValueError(f"q has {q.numel() if _is_torch(q) else q.size} values for {nsrc} sources")
+    if u_out is None:
+        return
+    if tuple(u_out.shape) != shape:
+        raise ValueError(f"u_out has shape {tuple(u_out.shape)}, the grid {shape}")
+    if u_out.dtype != out_dtype:
+        raise ValueError(f"u_out has dtype {u_out.dtype}, expected {out_dtype}")
+    if device is not None:
+        if not _is_torch(u_out) or u_out.device != device or not u_out.is_contiguous():
+            raise ValueError("u_out must be a contiguous tensor on the inputs' device")
+    elif _is_torch(u_out) or not u_out.flags.c_contiguous or not u_out.flags.writeable:
+        raise ValueError("u_out must be a writeable C-contiguous numpy array for host inputs")
+
+
 def _marshal(F, h, src, q, mask, u_out, dtype):
     """Returns (Problem, keepalive, u_out, device, dtype code)."""
     if _is_torch(F):
@@ -160,6 +181,7 @@ def _marshal(F, h, src, q, mask, u_out, dtype):
         srct = as_dev(src if _is_torch(src) else np.asarray(src, dtype=np.int64).ravel(), torch.int64)
         qt = None if q is None else as_dev(q, torch.float64)
         mt = None if mask is None else as_dev(mask, torch.uint8)
+        _check_arrays(F.shape, mt, qt, srct.numel(), u_out, tdt, dev)
         if u_out is None:
             u_out = torch.empty_like(F)
         ny, nx = F.shape
@@ -172,6 +194,7 @@ def _marshal(F, h, src, q, mask, u_out, dtype):
     srca = np.ascontiguousarray(np.atleast_1d(src), dtype=np.int64)
     qa = None if q is None else np.ascontiguousarray(np.atleast_1d(q), dtype=np.float64)
     ma = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    _check_arrays(F.shape, ma, qa, len(srca), u_out, np.dtype(ndt), None)
     if u_out is None:
         u_out = np.empty_like(F)
     ny, nx = F.shape
@@ -267,6 +290,7 @@ def eik_solve3(F, h, src, q=None, mask=None, u_out=None, *, method="exact"):
                                                     device=dev).to(torch.float64).contiguous()
         m_ = None if mask is None else torch.as_tensor(mask if _is_torch(mask) else np.asarray(mask),
                                                        device=dev).to(torch.uint8).contiguous()
+        _check_arrays(F_.shape, m_, q_, src_.numel(), u_out, torch.float64, dev)
         u = torch.empty_like(F_) if u_out is None else u_out
         ptr = lambda t: None if t is None else t.data_ptr()
         nsrc = src_.numel()
@@ -276,6 +300,7 @@ def eik_solve3(F, h, src, q=None, mask=None, u_out=None, *, method="exact"):
         src_ = np.ascontiguousarray(np.atleast_1d(src), dtype=np.int64)
         q_ = None if q is None else np.ascontiguousarray(np.atleast_1d(q), dtype=np.float64)
         m_ = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+        _check_arrays(F_.shape, m_, q_, len(src_), u_out, np.dtype(np.float64), None)
         u = np.empty_like(F_) if u_out is None else u_out
         ptr = lambda a: None if a is None else a.ctypes.data
         nsrc = len(src_)

@@ -182,3 +182,29 @@ def test_solve3_arguments_are_rejected_before_device_work():
             else:
                 raise AssertionError((method, args[1:]))
     assert (u == 7.0).all()
+
+
+def test_binding_rejects_mismatched_arrays():
+    """The library takes plain pointers, so the binding checks array shapes,
+    dtypes and layout against the grid before calling it (no device needed:
+    host inputs are rejected before staging)."""
+    import numpy as np
+    import pytest
+    from paper_1110_6220_amd import eik
+    F2 = np.ones((6, 7))
+    bad2 = [dict(u_out=np.empty((6, 6))), dict(u_out=np.empty((6, 7), dtype=np.float32)),
+            dict(u_out=np.empty((7, 6)).T), dict(mask=np.ones((5, 7), dtype=np.uint8)),
+            dict(q=[0.0, 0.1])]
+    for kw in bad2:
+        with pytest.raises(ValueError):
+            eik.eik_solve(F2, 0.1, [3], **kw)
+    F3 = np.ones((3, 4, 5))
+    bad3 = [dict(u_out=np.empty((3, 4, 4))), dict(u_out=np.empty((3, 4, 5), dtype=np.float32)),
+            dict(mask=np.ones((3, 4, 4), dtype=np.uint8)), dict(q=[0.0, 0.0, 0.0])]
+    for kw in bad3:
+        with pytest.raises(ValueError):
+            eik.eik_solve3(F3, 0.1, [0, 7], **kw)
+    ro = np.empty((6, 7))
+    ro.setflags(write=False)
+    with pytest.raises(ValueError):
+        eik.eik_solve(F2, 0.1, [3], u_out=ro)
