@@ -266,14 +266,13 @@ __global__ __launch_bounds__(64) void k3_round(Grid3 g, int round, int cap) {
     __syncthreads();
     // add criterion per face: a face node that decreased and is below the
     // node across (accessible, not an exit node: finite h/F) queues the
-    // neighbour
+    // neighbour; the six neighbours are queued by six lanes at once
+    unsigned qmask = 0;
     for (int f = 0; f < 6; ++f) {
       const int ax = f >> 1, side = f & 1;
-      int nb = -1;
-      if (ax == 0) nb = side ? (cx + 1 < g.kx ? c + 1 : -1) : (cx > 0 ? c - 1 : -1);
-      if (ax == 1) nb = side ? (cy + 1 < g.ky ? c + g.kx : -1) : (cy > 0 ? c - g.kx : -1);
-      if (ax == 2) nb = side ? (cz + 1 < g.kz ? c + g.kx * g.ky : -1) : (cz > 0 ? c - g.kx * g.ky : -1);
-      if (nb < 0) continue;  // no cell across: the across plane is outside the grid
+      const bool has = ax == 0 ? (side ? cx + 1 < g.kx : cx > 0)
+                               : ax == 1 ? (side ? cy + 1 < g.ky : cy > 0) : (side ? cz + 1 < g.kz : cz > 0);
+      if (!has) continue;  // no cell across: the across plane is outside the grid
       const int n0 = ax == 0 ? hg : w, n1 = ax == 2 ? hg : dp;  // face extents
       const int lim = ax == 0 ? w : ax == 1 ? hg : dp;
       const int pos = side ? lim - 1 : 0, across = side ? lim : -1;
@@ -290,7 +289,12 @@ __global__ __launch_bounds__(64) void k3_round(Grid3 g, int round, int cap) {
             g.delta[(z0 + ee) * sxy + (int64_t)(y0 + bb) * g.nx + x0 + aa] != INF)
           q = true;
       }
-      if (__ballot(q) != 0ull && lane == 0) queue3(g, nb, round + 1, 2 * ax + (1 - side));
+      if (__ballot(q) != 0ull) qmask |= 1u << f;
+    }
+    if (lane < 6 && ((qmask >> lane) & 1u)) {
+      const int ax = lane >> 1, side = lane & 1;
+      const int nb = c + (side ? 1 : -1) * (ax == 0 ? 1 : ax == 1 ? g.kx : g.kx * g.ky);
+      queue3(g, nb, round + 1, 2 * ax + (1 - side));
     }
     if (again && lane == 0) {  // the same entry faces, so that its next visit starts alike
       __hip_atomic_fetch_or(&g.entry[c], entry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
