@@ -885,18 +885,20 @@ __device__ void publish(const Engine& e, const Inst& I, const CellBox& B, int g,
 
 // First processing of cell g done: a later neighbour starts once all its
 // earlier neighbours are done.  One lane.
+// Side `side` (0..3) of cell g: its later neighbour there loses one
+// dependency and starts when none is left.  Lanes 0..3 call it for one side
+// each, so the four dependency counts and queue pushes (chains of
+// device-scope atomics) proceed at once.
 __device__ void release_later(const Engine& e, int g, const Inst& I, const CellBox& B,
-                              uint32_t ordb) {
-  for (int side = 0; side < 4; ++side) {
-    int nb = -1;
-    if (side == 0 && B.cx > 0) nb = g - 1;
-    if (side == 1 && B.cx + 1 < I.kx) nb = g + 1;
-    if (side == 2 && B.cy > 0) nb = g - I.kx;
-    if (side == 3 && B.cy + 1 < I.ky) nb = g + I.kx;
-    if (nb < 0 || (ordb & (1u << side))) continue;  // none, or earlier
-    if (e.ord[nb] & kOrdEmpty) continue;
-    if (atomic_add_relaxed(&e.deps[nb], -1) == 1) release_first(e, nb);
-  }
+                              uint32_t ordb, int side) {
+  int nb = -1;
+  if (side == 0 && B.cx > 0) nb = g - 1;
+  if (side == 1 && B.cx + 1 < I.kx) nb = g + 1;
+  if (side == 2 && B.cy > 0) nb = g - I.kx;
+  if (side == 3 && B.cy + 1 < I.ky) nb = g + I.kx;
+  if (nb < 0 || (ordb & (1u << side))) return;  // none, or earlier
+  if (e.ord[nb] & kOrdEmpty) return;
+  if (atomic_add_relaxed(&e.deps[nb], -1) == 1) release_first(e, nb);
 }
 
 // NW waves per workgroup: wave 0 runs the worker; with NW > 1 (single
@@ -1102,14 +1104,16 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
       if constexpr (M != kFmsm) {
         // publish has made the boundary visible: later neighbours start
         // while the interior is written back
-        if (lane == 0 && e.dag && !done1) release_later(e, g, I, B, ordb);
+        if (lane < 4 && e.dag && !__builtin_amdgcn_readfirstlane(done1))  // lane 0's flag
+          release_later(e, g, I, B, ordb, lane);
       }
       tile_store(I, B, g);
       order_release();
       int again = 0;
       if (lane == 0) {
         if (e.dag && !done1) {
-          if (M == kFmsm) release_later(e, g, I, B, ordb);
+          if (M == kFmsm)
+            for (int sd = 0; sd < 4; ++sd) release_later(e, g, I, B, ordb, sd);
           done1 = 1;
         }
         uint32_t exp = run_state;
