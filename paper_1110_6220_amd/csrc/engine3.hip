@@ -51,9 +51,10 @@ __device__ __forceinline__ void st_coh(T* p, T v) {
 // (U-m1)^2 + (U-m2)^2 + (U-m3)^2 = delta^2.
 __device__ double update3(double a, double b, double c, double delta) {
   const double INF = __builtin_huge_val();
-  const double lo = a < b ? a : b, hi = a < b ? b : a;
-  const double m1 = lo < c ? lo : c, mid = lo < c ? c : lo;
-  const double m2 = hi < mid ? hi : mid, m3 = hi < mid ? mid : hi;
+  // sorting network on single min/max instructions (operands are never NaN)
+  const double lo = wave::vmin(a, b), hi = wave::vmax(a, b);
+  const double m1 = wave::vmin(lo, c), mid = wave::vmax(lo, c);
+  const double m2 = wave::vmin(hi, mid), m3 = wave::vmax(hi, mid);
   if (m1 == INF) return INF;
   const double d = m1 - m2;
   if (fabs(d) >= delta) return m1 + delta;
@@ -229,7 +230,7 @@ __global__ __launch_bounds__(64) void k3_round(Grid3 g, int round, int cap) {
           double dl = td[ci];
           const double uD = tu[t - P3 * P3], uU = tu[t + P3 * P3], uo = tu[t];
           asm volatile("" : "+v"(dl));  // h/F joins the neighbours' LDS round trip
-          const double a = uW < uE ? uW : uE, b = uS < uN ? uS : uN, cc = uD < uU ? uD : uU;
+          const double a = wave::vmin(uW, uE), b = wave::vmin(uS, uN), cc = wave::vmin(uD, uU);
           const double U = update3(a, b, cc, dl);
           if (U < uo) {
             tu[t] = U;
@@ -360,9 +361,9 @@ __device__ __forceinline__ bool sweep_cell3(double* tu, const double* td, uint8_
       } else {
         const double uW = tu[t - 1], uE = tu[t + 1], uS = tu[t - P3], uN = tu[t + P3];
         const double uD = tu[t - P3 * P3], uU = tu[t + P3 * P3];
-        a = uW < uE ? uW : uE;
-        b = uS < uN ? uS : uN;
-        cc = uD < uU ? uD : uU;
+        a = wave::vmin(uW, uE);
+        b = wave::vmin(uS, uN);
+        cc = wave::vmin(uD, uU);
       }
       asm volatile("" : "+v"(dl));  // h/F joins the neighbours' LDS round trip
       const double U = update3(a, b, cc, dl);
