@@ -10,7 +10,8 @@ Fast Marching solution) count.  Prints one JSON line.
 
 Beside the headline line's own fields it reports, from the same run:
   batched  the 256-instance Gaussian-bump batch (sides 65..1025) solved in one
-           persistent launch, against the same instances solved one launch each;
+           persistent launch, against the same instances solved one launch each
+           (batched_f32: the same in FP32);
   serving  Kruskal-maze requests (sides 129..2049, FP32 with the FP64 residual
            recheck) through the continuous-batching server under a 64 GiB
            budget: saturated throughput, then p50/p99 latency of Poisson
@@ -80,12 +81,13 @@ def main():
     ap.add_argument("--no-graph", action="store_true",
                     help="launch every step's kernels one by one instead of replaying the "
                          "captured HIP graph of the solve")
-    ap.add_argument("--only", choices=["batched", "serving", "early_termination", "three_d", "cells",
-                                       "large"],
+    ap.add_argument("--only", choices=["batched", "batched_f32", "serving", "early_termination", "three_d",
+                                       "cells", "large"],
                     help="run one of the extra studies alone and print its JSON (no headline)")
     args = ap.parse_args()
     if args.only:
         runs = {"batched": lambda: bench_batched("f64", graph=not args.no_graph),
+                "batched_f32": lambda: bench_batched("f32", graph=not args.no_graph),
                 "serving": lambda: bench_serving(args.serve_requests),
                 "early_termination": bench_early_termination, "three_d": bench_3d,
                 "cells": bench_cells, "large": bench_large}
@@ -213,6 +215,7 @@ def main():
     if not args.no_extras:
         print("[bench] headline done; batched", file=sys.stderr, flush=True)
         line["batched"] = bench_batched("f64", graph=not args.no_graph)
+        line["batched_f32"] = bench_batched("f32", graph=not args.no_graph)
         print("[bench] batched done; serving", file=sys.stderr, flush=True)
         line["serving"] = bench_serving(args.serve_requests)
         print("[bench] serving done; early termination", file=sys.stderr, flush=True)
@@ -247,8 +250,9 @@ def _max_rel(got, ref):
 
 def bench_batched(dtype, reps=5, graph=True):
     """256 instances in one launch vs one launch per instance (same kernels,
-    same accuracy: FP64, <= 1e-12 relative to the oracle on sampled
-    instances), inputs resident on the device."""
+    same accuracy on sampled instances: FP64 <= 1e-12 relative to the
+    oracle; FP32 within (nx + ny) 2^-24 max u, reported as the worst share of
+    that bound), inputs resident on the device."""
     import numpy as np
     import torch
 
@@ -283,11 +287,19 @@ def bench_batched(dtype, reps=5, graph=True):
     # accuracy gate on sampled instances (largest, smallest, every 51st)
     sizes = np.array([w["nx"] for w in ws])
     pick = sorted({int(sizes.argmax()), int(sizes.argmin())} | set(range(0, 256, 51)))
-    worst = 0.0
+    worst, passed = 0.0, True
     for k in pick:
         U = oracle.fmm(oracle.Problem.from_workload(ws[k]))
-        worst = max(worst, _max_rel(out["u"][k].double().cpu().numpy(), U))
-    passed = worst <= 1e-12
+        got = out["u"][k].double().cpu().numpy()
+        if dtype == "f64":
+            worst = max(worst, _max_rel(got, U))
+            passed = passed and worst <= 1e-12
+        else:  # FP32: within (nx + ny) 2^-24 max u, identical infinite sets
+            fin = np.isfinite(U)
+            err = float(np.abs(got[fin] - U[fin]).max())
+            bound = (ws[k]["nx"] + ws[k]["ny"]) * 2.0 ** -24 * float(U[fin].max())
+            worst = max(worst, err / bound)
+            passed = passed and err <= bound and bool(np.array_equal(np.isfinite(got), fin))
     st = out["st"][0]
     return {
         "workload": "256 instances, sides ~U{65..1025}, F = clip(1 + 4 Gaussian bumps, 0.25, 2), "
@@ -299,7 +311,8 @@ def bench_batched(dtype, reps=5, graph=True):
         "one_launch_per_instance_ms": t_seq * 1e3,
         "speedup_vs_one_launch_per_instance": t_seq / t_batch,
         "kernel_ms": st["kernel_seconds"] * 1e3, "AvHR": st["AvHR"], "AvS": st["AvS"],
-        "accuracy": {"max_rel_err_vs_fmm_sampled": worst, "sampled": len(pick), "passed": passed},
+        "accuracy": {("max_rel_err_vs_fmm_sampled" if dtype == "f64" else "worst_share_of_f32_bound"): worst,
+                     "sampled": len(pick), "passed": passed},
     }
 
 
