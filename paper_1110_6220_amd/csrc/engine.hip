@@ -1378,6 +1378,35 @@ __global__ __launch_bounds__(64) void k_coarse_cells(Engine e, const CoarseOut* 
     const Inst I = inst_at(e, k);
     const CellBox B = cell_box(I, g - I.cell0);
     const T* F = static_cast<const T*>(I.F);
+    // the speed at the cell centre: the centre node, or the mean of the
+    // accessible nodes around it (x ascending, then y); an accessible one
+    // also makes the cell accessible, so the cell mean is needed only when
+    // none of them is
+    double sc = 0.0;
+    int nc = 0;
+    if (lane == 0) {
+      const int ia = (B.x0 + B.x1 - 1) / 2, ib = (B.x0 + B.x1) / 2;
+      const int ja = (B.y0 + B.y1 - 1) / 2, jb = (B.y0 + B.y1) / 2;
+      for (int a = 0; a < (ia == ib ? 1 : 2); ++a)
+        for (int b = 0; b < (ja == jb ? 1 : 2); ++b) {
+          const size_t n = (size_t)(b ? jb : ja) * I.nx + (a ? ib : ia);
+          if (I.mask && !I.mask[n]) continue;
+          sc += (double)F[n];
+          nc++;
+        }
+    }
+    nc = __builtin_amdgcn_readfirstlane(nc);
+    const int cl = g - I.cell0;
+    if (nc > 0) {
+      if (lane == 0) {
+        co[k].F[cl] = sc / nc;
+        co[k].mask[cl] = 1;
+        co[k].q[cl] = __builtin_huge_val();
+      }
+      continue;
+    }
+    // no accessible centre node: the mean of F over the cell, summed column
+    // by column (each column bottom to top, then the columns left to right)
     double col = 0.0;
     int cnt = 0;
     if (lane < B.w) {
@@ -1402,22 +1431,7 @@ __global__ __launch_bounds__(64) void k_coarse_cells(Engine e, const CoarseOut* 
         sum += csum[l];
         c += ccnt[l];
       }
-      // the speed at the cell centre: the centre node, or the mean of the
-      // accessible nodes around it (x ascending, then y); the cell mean when
-      // none of them is accessible
-      const int ia = (B.x0 + B.x1 - 1) / 2, ib = (B.x0 + B.x1) / 2;
-      const int ja = (B.y0 + B.y1 - 1) / 2, jb = (B.y0 + B.y1) / 2;
-      double sc = 0.0;
-      int nc = 0;
-      for (int a = 0; a < (ia == ib ? 1 : 2); ++a)
-        for (int b = 0; b < (ja == jb ? 1 : 2); ++b) {
-          const size_t n = (size_t)(b ? jb : ja) * I.nx + (a ? ib : ia);
-          if (I.mask && !I.mask[n]) continue;
-          sc += (double)F[n];
-          nc++;
-        }
-      const int cl = g - I.cell0;
-      co[k].F[cl] = nc ? sc / nc : c ? sum / c : 1.0;
+      co[k].F[cl] = c ? sum / c : 1.0;
       co[k].mask[cl] = c > 0;
       co[k].q[cl] = __builtin_huge_val();
     }
