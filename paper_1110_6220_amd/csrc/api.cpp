@@ -630,10 +630,14 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
   Engine ce;
   // coarse grid of cell centres with spacing h^c = s h (FMSM Part I): FMSM
   // orders its cells by Fast Marching on it, as the method prescribes; the
-  // other methods use the order only as a schedule and take the faster
-  // parallel exact solve (coarse_engine)
+  // other methods use the order only as a schedule and take a parallel exact
+  // solve: Jacobi iteration in one workgroup per problem for coarse grids of
+  // up to kCoarseJacobiMax cells, else the cell engine (coarse_engine)
   bool have_coarse = false, coarse_engine = false;
   const bool fmm = method == EIK_FMSM;
+  int64_t max_coarse = 0;
+  for (int k = 0; k < n; ++k) max_coarse = std::max<int64_t>(max_coarse, (int64_t)inst[k].kx * inst[k].ky);
+  const bool jacobi = !fmm && max_coarse <= kCoarseJacobiMax;
   int cext = 0, fmm_lds = 0;
   FmmSpill spill{};
   if (dag) {
@@ -657,7 +661,7 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
         spill.st = reinterpret_cast<int32_t*>(spill.fval + J);
         spill.fidx = spill.st + J;
       }
-    } else {
+    } else if (!jacobi) {
       HIP_TRY(ws->coarse.delta.ensure(J * sizeof(double)));
     }
     DevBuf& coutbuf = np ? np->cout : ws->cout;
@@ -671,7 +675,7 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
       co[k].q = ws->cq.as<double>() + c0;
       co[k].u = ws->cu.as<double>() + c0;
       co[k].rank = fmm ? ws->crank.as<int32_t>() + c0 : nullptr;
-      if (fmm) continue;
+      if (fmm || jacobi) continue;
       Inst& C = cinst[k];
       std::memset(&C, 0, sizeof C);
       C.u = co[k].u;
@@ -691,11 +695,11 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
       cext = std::max(cext, ct.extent);
     }
     HIP_TRY(hipMemcpyAsync(coutbuf.p, co.data(), n * sizeof(CoarseOut), hipMemcpyHostToDevice, stream));
-    if (!fmm && (rc = setup_engine(ws->coarse, cinst, EIK_F64, EIK_EXACT, 0, -1.0, 0, 0, 0, timeout, stream,
+    if (!fmm && !jacobi && (rc = setup_engine(ws->coarse, cinst, EIK_F64, EIK_EXACT, 0, -1.0, 0, 0, 0, timeout, stream,
                                    &ce, np ? &np->cinst : nullptr)))
       return rc;
     have_coarse = true;
-    coarse_engine = !fmm;
+    coarse_engine = !fmm && !jacobi;
   }
   const CoarseOut* co_dev = have_coarse ? (np ? np->cout : ws->cout).as<CoarseOut>() : nullptr;
 
@@ -719,7 +723,9 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
     step("prepare", launch_prepare(e, max_nodes, ls));
     if (have_coarse) {
       step("coarse inputs", launch_coarse_inputs(e, co_dev, (int)max_src, ls));
-      if (coarse_engine) {
+      if (jacobi) {
+        step("coarse solve", launch_coarse_jacobi(e, co_dev, (int)max_coarse, ls));
+      } else if (coarse_engine) {
         step("coarse prepare", launch_prepare(ce, J, ls));
         step("coarse solve", launch_solve(ce, cw, tile_for(cext), ls));
       } else {

@@ -155,6 +155,12 @@ hipError_t launch_residual(const Engine& e, int64_t max_nodes, hipStream_t strea
 // at co[k].*[cell - cell0])
 hipError_t launch_coarse_inputs(const Engine& fine, const CoarseOut* co_dev, int max_cells,
                                 hipStream_t stream);
+// Exact solve of every problem's coarse grid (values into co[k].u) when no
+// problem has more than kCoarseJacobiMax coarse cells; max_cells = the
+// largest count.
+constexpr int kCoarseJacobiMax = 1024;
+hipError_t launch_coarse_jacobi(const Engine& fine, const CoarseOut* co_dev, int max_cells,
+                                hipStream_t stream);
 // Fast Marching on the coarse grid of every problem (FMSM Part I): values
 // into co[k].u, acceptance ranks into co[k].rank.  Problems with at most
 // lds_cells coarse cells work in LDS (kFmmLdsBytesPerCell bytes per cell),

@@ -1593,6 +1593,58 @@ __device__ void coarse_fmm(const CoarseOut& C, int kx, int ky, double hc, int la
   }
 }
 
+// Exact solve of a small coarse grid (at most kCoarseJacobiMax cells) by
+// Jacobi iteration, one workgroup per problem, one cell per thread: every
+// iteration applies the local update of Section 2 to all cells at once from
+// the previous iterate (two LDS buffers, one barrier per iteration) until no
+// value decreases.  The update is causal (a new value exceeds the values it
+// is computed from), so a value is final once the chain of cells it depends
+// on is, and at most J + 1 iterations are needed.  The exact, HCM and FHCM
+// methods use these values only to order the fine cells.
+__global__ __launch_bounds__(kCoarseJacobiMax) void k_coarse_jacobi(Engine e, const CoarseOut* co) {
+  __shared__ double ub[2][kCoarseJacobiMax];
+  const int k = blockIdx.x;
+  const Inst I = inst_at(e, k);
+  const CoarseOut C = co[k];
+  const int kx = I.kx, ky = I.ky, J = kx * ky;
+  const double hc = (double)I.s * I.h;
+  const int c = threadIdx.x;
+  const double inf = __builtin_huge_val();
+  // dl = h^c / F^c on coarse cells that are updated: accessible and not exit cells
+  double dl = inf, u0 = inf;
+  int cx = 0, cy = 0;
+  if (c < J) {
+    cx = c % kx;
+    cy = c / kx;
+    if (C.mask[c]) {
+      u0 = C.q[c];
+      if (!(u0 < inf)) dl = hc / C.F[c];
+    }
+    ub[0][c] = u0;
+  }
+  __syncthreads();
+  double u = u0;
+  const bool live = c < J && dl < inf;
+  for (int it = 0; it <= J; ++it) {
+    const double* cur = ub[it & 1];
+    double* nxt = ub[(it + 1) & 1];
+    bool dec = false;
+    if (live) {
+      const double l = cx > 0 ? cur[c - 1] : inf, r = cx + 1 < kx ? cur[c + 1] : inf;
+      const double d = cy > 0 ? cur[c - kx] : inf, t = cy + 1 < ky ? cur[c + kx] : inf;
+      const double a = l < r ? l : r, b = d < t ? d : t;
+      const double v = local_update(a, b, dl);
+      if (v < u) {
+        u = v;
+        dec = true;
+      }
+    }
+    if (c < J) nxt[c] = u;
+    if (!__syncthreads_or(dec)) break;
+  }
+  if (c < J) C.u[c] = u;
+}
+
 __global__ __launch_bounds__(64) void k_coarse_fmm(Engine e, const CoarseOut* co, int lds_cells,
                                                    FmmSpill spill) {
   extern __shared__ __align__(16) unsigned char fmm_lds[];
@@ -1906,6 +1958,15 @@ hipError_t launch_sweep_diag(const Engine& e, const SweepArgs& a, int tiles, hip
 
 hipError_t launch_sweep_seed(const Engine& e, int nsrc, uint8_t* dirty, hipStream_t stream) {
   hipLaunchKernelGGL(k_sweep_seed, dim3(grid_for(nsrc, 256, 1024)), dim3(256), 0, stream, e, dirty);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse_jacobi(const Engine& fine, const CoarseOut* co_dev, int max_cells,
+                                hipStream_t stream) {
+  if (max_cells < 1) return hipSuccess;
+  const int threads = (max_cells + 63) / 64 * 64;
+  if (threads > kCoarseJacobiMax) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_coarse_jacobi, dim3(fine.ninst), dim3(threads), 0, stream, fine, co_dev);
   return hipGetLastError();
 }
 
