@@ -1242,10 +1242,20 @@ __global__ void k_prep_cells(Engine e) {
   }
 }
 
-// delta = h/F on accessible nodes (validating F), +inf on obstacles.
+// delta = h/F on accessible nodes (validating F), +inf on obstacles; the
+// first block of every problem also validates its exit nodes (index range,
+// accessibility, finite q).
 template <typename T>
 __global__ void k_prep_nodes(Engine e) {
   const Inst I = inst_at(e, blockIdx.y);
+  if (blockIdx.x == 0) {
+    const long long nn = (long long)I.nx * I.ny;
+    for (int s = threadIdx.x; s < I.nsrc; s += blockDim.x) {
+      const long long k = I.src[s];
+      const double q = I.q ? I.q[s] : 0.0;
+      if (k < 0 || k >= nn || (I.mask && !I.mask[k]) || !isfinite(q)) set_err(e.ctl, kErrSource);
+    }
+  }
   const size_t n = (size_t)I.nx * I.ny;
   const T* F = static_cast<const T*>(I.F);
   const double* Fd = static_cast<const double*>(I.F);
@@ -1264,17 +1274,6 @@ __global__ void k_prep_nodes(Engine e) {
     dl[k] = d;
   }
   if (bad) set_err(e.ctl, kErrSpeed);
-}
-
-// Source validation (index range, accessibility, finite q).
-__global__ void k_check_sources(Engine e) {
-  const Inst I = inst_at(e, blockIdx.y);
-  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < I.nsrc; s += gridDim.x * blockDim.x) {
-    const long long k = I.src[s];
-    const double q = I.q ? I.q[s] : 0.0;
-    const long long n = (long long)I.nx * I.ny;
-    if (k < 0 || k >= n || (I.mask && !I.mask[k]) || !isfinite(q)) set_err(e.ctl, kErrSource);
-  }
 }
 
 __device__ __forceinline__ int cell_of_node(const Inst& I, int i, int j) {
@@ -1669,7 +1668,7 @@ __global__ __launch_bounds__(64) void k_coarse_fmm(Engine e, const CoarseOut* co
 // Order of the cells: exit cells first by (q, index), then by (coarse value,
 // index) -- the acceptance order of Fast Marching on the coarse grid -- and
 // cells the coarse front does not reach last, by index.  Each cell counts
-// the accessible neighbours that precede it.
+// the accessible neighbours that precede it; a cell with none is queued.
 __global__ void k_dag(Engine e, const CoarseOut* co) {
   for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < e.ncells; g += gridDim.x * blockDim.x) {
     const int k = inst_index(e, g);
@@ -1710,15 +1709,7 @@ __global__ void k_dag(Engine e, const CoarseOut* co) {
     e.ord[g] = o;
     e.deps[g] = n;
     atomic_add_relaxed(&e.ctl->active, 1ull);
-  }
-}
-
-// Queues the cells without earlier neighbours (after every count is set).
-__global__ void k_dag_roots(Engine e) {
-  if (get_err(e.ctl)) return;
-  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < e.ncells; g += gridDim.x * blockDim.x) {
-    if (e.ord[g] & kOrdEmpty) continue;
-    if (e.deps[g] == 0) release_first(e, g);
+    if (n == 0 && !get_err(e.ctl)) release_first(e, g);
   }
 }
 
@@ -1782,7 +1773,7 @@ __global__ void k_sweep_seed(Engine e, uint8_t* dirty) {
   const Inst I = inst_at(e, 0);
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < I.nsrc; s += gridDim.x * blockDim.x) {
     const long long k = I.src[s];
-    if (k < 0 || k >= (long long)I.nx * I.ny) continue;  // reported by k_check_sources
+    if (k < 0 || k >= (long long)I.nx * I.ny) continue;  // reported by k_prep_nodes
     const int g = cell_of_node(I, (int)(k % I.nx), (int)(k / I.nx));
     const int cx = g % I.kx, cy = g / I.kx;
     dirty[g] = 1;
@@ -1858,7 +1849,6 @@ hipError_t launch_prepare(const Engine& e, int64_t max_nodes, hipStream_t stream
   const dim3 gn(grid_for(max_nodes, 256, gy > 1 ? 512 : 8192), gy);
   if (e.dtype == 0) hipLaunchKernelGGL(k_prep_nodes<double>, gn, dim3(256), 0, stream, e);
   else hipLaunchKernelGGL(k_prep_nodes<float>, gn, dim3(256), 0, stream, e);
-  hipLaunchKernelGGL(k_check_sources, dim3(1, gy), dim3(64), 0, stream, e);
   if (e.dtype == 0) hipLaunchKernelGGL(k_init_u<double>, gn, dim3(256), 0, stream, e);
   else hipLaunchKernelGGL(k_init_u<float>, gn, dim3(256), 0, stream, e);
   if (e.dtype == 0) hipLaunchKernelGGL(k_apply_sources<double>, dim3(1, gy), dim3(64), 0, stream, e);
@@ -1980,7 +1970,6 @@ hipError_t launch_coarse_fmm(const Engine& fine, const CoarseOut* co_dev, int ld
 hipError_t launch_dag(const Engine& fine, const CoarseOut* co_dev, int, hipStream_t stream) {
   const dim3 gc(grid_for(fine.ncells, 256, 4096));
   hipLaunchKernelGGL(k_dag, gc, dim3(256), 0, stream, fine, co_dev);
-  hipLaunchKernelGGL(k_dag_roots, gc, dim3(256), 0, stream, fine);
   return hipGetLastError();
 }
 
