@@ -1602,6 +1602,7 @@ __device__ void coarse_fmm(const CoarseOut& C, int kx, int ky, double hc, int la
 // methods use these values only to order the fine cells.
 __global__ __launch_bounds__(kCoarseJacobiMax) void k_coarse_jacobi(Engine e, const CoarseOut* co) {
   __shared__ double ub[2][kCoarseJacobiMax];
+  __shared__ int dec_any[3];  // iteration it reports decreases in dec_any[it % 3]
   const int k = blockIdx.x;
   const Inst I = inst_at(e, k);
   const CoarseOut C = co[k];
@@ -1621,6 +1622,7 @@ __global__ __launch_bounds__(kCoarseJacobiMax) void k_coarse_jacobi(Engine e, co
     }
     ub[0][c] = u0;
   }
+  if (c < 3) dec_any[c] = 0;
   __syncthreads();
   double u = u0;
   const bool live = c < J && dl < inf;
@@ -1639,7 +1641,13 @@ __global__ __launch_bounds__(kCoarseJacobiMax) void k_coarse_jacobi(Engine e, co
       }
     }
     if (c < J) nxt[c] = u;
-    if (!__syncthreads_or(dec)) break;
+    // the flag of iteration it + 1 was last read after the barrier of
+    // iteration it - 2, which every thread has passed
+    const int f = it % 3;
+    if (c == 0) dec_any[f == 2 ? 0 : f + 1] = 0;
+    if (dec) dec_any[f] = 1;
+    __syncthreads();
+    if (!dec_any[f]) break;
   }
   if (c < J) C.u[c] = u;
 }
