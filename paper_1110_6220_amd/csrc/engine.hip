@@ -1439,10 +1439,12 @@ __global__ __launch_bounds__(64) void k_coarse_cells(Engine e, const CoarseOut* 
 }
 
 __global__ void k_coarse_sources(Engine e, const CoarseOut* co) {
+  if (get_err(e.ctl)) return;  // an invalid exit node has no cell
   const int k = blockIdx.y;
   const Inst I = inst_at(e, k);
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < I.nsrc; s += gridDim.x * blockDim.x) {
     const long long n = I.src[s];
+    if (n < 0 || n >= (long long)I.nx * I.ny) continue;  // reported by k_prep_nodes
     const double q = I.q ? I.q[s] : 0.0;
     const int g = cell_of_node(I, (int)(n % I.nx), (int)(n / I.nx));
     atomic_min_val(co[k].q + (g - I.cell0), q);

@@ -142,6 +142,24 @@ def test_device_validation_leaves_output_untouched(eik):
     assert bool((u == 42.0).all())
 
 
+def test_device_exit_nodes_out_of_range(eik):
+    """Device exit-node indices far outside the grid (negative, or beyond
+    2^31 nodes) are EINVAL for every method that orders cells on the coarse
+    grid, and no kernel maps them to a cell."""
+    import torch
+    w = W.random_small(np.random.default_rng(7), 40, 40, obst=0.0, nsrc=1)
+    d = to_dev(w)
+    u = torch.full_like(d["F"], 42.0)
+    for method in ("exact", "hcm", "fmsm"):
+        for bad in (-1, -100000, 2 ** 40, -(2 ** 40)):
+            print(f"[gpu] {method} exit node {bad}", flush=True)
+            src = torch.tensor([0, bad], dtype=torch.int64, device="cuda:0")
+            with pytest.raises(eik.EikError) as ex:
+                eik.eik_solve(d["F"], d["h"], src, u_out=u, method=method, cell=8)
+            assert ex.value.code == eik.EIK_EINVAL
+            assert bool((u == 42.0).all())
+
+
 def test_device_pointers_must_be_aligned(eik):
     """Device u_out off its element alignment is EINVAL for the cell solver
     and the whole-grid sweep, rejected on the host before any launch."""
