@@ -85,10 +85,14 @@ def test_point_source_first_nodes_solve_equation():
     U = O.fmm(O.Problem.from_workload(w))
     assert U[3, 4] == 1.0 and U[3, 5] == 2.0 and U[4, 3] == 1.0
     assert_solves_discrete_system(U, w)
-    # survey-computed regression values (T1), checked here for stability only
-    assert U[4, 4] == pytest.approx(1.7071067811865475, abs=1e-15)
-    assert U[4, 5] == pytest.approx(2.545328925426122, abs=1e-15)
-    assert U[5, 5] == pytest.approx(3.25243570661267, abs=1e-14)
+    # closed forms of the discrete equation: the diagonal neighbour sees a = b
+    # = 1, so (U - 1)^2 * 2 = 1; the next ones solve the two-sided quadratic
+    # with the values already known (U[4, 5] and U[5, 4] are equal by symmetry)
+    d1 = 1.0 + np.sqrt(0.5)
+    assert U[4, 4] == pytest.approx(d1, abs=1e-15)
+    d2 = 0.5 * (2.0 + d1 + np.sqrt(2.0 - (2.0 - d1) ** 2))
+    assert U[4, 5] == pytest.approx(d2, abs=1e-15)
+    assert U[5, 5] == pytest.approx(d2 + np.sqrt(0.5), abs=1e-14)
 
 
 def test_plane_front_and_strip_are_exact():
