@@ -43,6 +43,16 @@ template <typename T>
 __device__ __forceinline__ void st_coh(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// accesses to data that only one workgroup touches while the kernel runs:
+// the compute unit's caches serve them
+template <typename T>
+__device__ __forceinline__ T ld_wg(const T* p) {
+  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <typename T>
+__device__ __forceinline__ void st_wg(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
 
 // The upwind update from the three axis minima, in the expression order of
 // the CPU oracle (contraction disabled; sqrt correctly rounded): sorted
@@ -530,31 +540,37 @@ __global__ __launch_bounds__(64) void k3f_fmm(Grid3 g, Fmsm3 f) {
   const int J = g.kx * g.ky * g.kz;
   const int ns = ld_coh(&f.ctl[0]);
   const double INF = __builtin_huge_val();
-  // state accessors (LDS, or device memory with coherent accesses)
+  // state accessors: LDS, or device memory; the kernel is one wave, the only
+  // one that reads or writes this state while it runs, so workgroup-scope
+  // accesses (cached by the compute unit) ordered by sync() suffice
   auto ldU = [&](int c) -> double {
-    if constexpr (LOCAL) return sm.U[c]; else return ld_coh(&f.Uc[c]);
+    if constexpr (LOCAL) return sm.U[c]; else return ld_wg(&f.Uc[c]);
   };
   auto stU = [&](int c, double v) {
-    if constexpr (LOCAL) sm.U[c] = v; else st_coh(&f.Uc[c], v);
+    if constexpr (LOCAL) sm.U[c] = v; else st_wg(&f.Uc[c], v);
   };
   auto ldLab = [&](int c) -> int {
-    if constexpr (LOCAL) return sm.lab[c]; else return ld_coh(&f.lab[c]);
+    if constexpr (LOCAL) return sm.lab[c]; else return ld_wg(&f.lab[c]);
   };
   auto stLab = [&](int c, int v) {
-    if constexpr (LOCAL) sm.lab[c] = (uint8_t)v; else st_coh(&f.lab[c], (uint8_t)v);
+    if constexpr (LOCAL) sm.lab[c] = (uint8_t)v; else st_wg(&f.lab[c], (uint8_t)v);
   };
   auto ldLvl = [&](int c) -> int {
-    if constexpr (LOCAL) return sm.lvl[c]; else return ld_coh(&f.level[c]);
+    if constexpr (LOCAL) return sm.lvl[c]; else return ld_wg(&f.level[c]);
   };
   auto ldPos = [&](int c) -> int {
-    if constexpr (LOCAL) return sm.pos[c]; else return ld_coh(&f.posf[c]);
+    if constexpr (LOCAL) return sm.pos[c]; else return ld_wg(&f.posf[c]);
   };
   auto stPos = [&](int c, int p) {
-    if constexpr (LOCAL) sm.pos[c] = (int16_t)p; else st_coh(&f.posf[c], p);
+    if constexpr (LOCAL) sm.pos[c] = (int16_t)p; else st_wg(&f.posf[c], p);
   };
   auto sync = [&]() {
-    if constexpr (!LOCAL) __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    if constexpr (LOCAL) {
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    } else {
+      // the waits this needs for workgroup scope on this target come with the fence
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    }
   };
   auto ldDc = [&](int c) -> double {
     if constexpr (LOCAL) return sm.dc[c]; else return f.dc[c];
@@ -587,8 +603,8 @@ __global__ __launch_bounds__(64) void k3f_fmm(Grid3 g, Fmsm3 f) {
         f.rank[c] = na;
         f.level[c] = lv;
       } else {
-        st_coh(&f.rank[c], na);
-        st_coh(&f.level[c], lv);
+        st_wg(&f.rank[c], na);
+        st_wg(&f.level[c], lv);
       }
       stLab(c, 2);
     }
@@ -634,8 +650,8 @@ __global__ __launch_bounds__(64) void k3f_fmm(Grid3 g, Fmsm3 f) {
           f.rank[x] = na;
           f.level[x] = lv;
         } else {
-          st_coh(&f.rank[x], na);
-          st_coh(&f.level[x], lv);
+          st_wg(&f.rank[x], na);
+          st_wg(&f.level[x], lv);
         }
         stLab(x, 2);
       }
