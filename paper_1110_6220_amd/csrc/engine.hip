@@ -105,7 +105,7 @@ __device__ __forceinline__ double sqrt_pos(double x) {
 // so both round identically.  a = b = +inf gives NaN, which the caller's
 // minimum with the old value turns into "no update".
 __device__ __forceinline__ double local_update(double a, double b, double dl) {
-  const double lo = a < b ? a : b;
+  const double lo = wave::vmin(a, b);  // a and b are never NaN
   const double d = a - b;
   const double one = lo + dl;
   const double two = 0.5 * (a + b + sqrt_pos(2.0 * dl * dl - d * d));
@@ -115,7 +115,7 @@ __device__ __forceinline__ double local_update(double a, double b, double dl) {
 // FP32 storage: the branch test and the two-sided root are evaluated in FP64
 // and rounded once to FP32.
 __device__ __forceinline__ float local_update(float a, float b, float dl) {
-  const float lo = a < b ? a : b;
+  const float lo = wave::vmin(a, b);
   const double da = a, db = b, dd = da - db, ddl = dl;
   const float one = lo + dl;
   const float two = (float)(0.5 * (da + db + sqrt_pos(2.0 * ddl * ddl - dd * dd)));
@@ -473,9 +473,9 @@ __device__ uint32_t claim(const Engine& e, int g) {
 // oracle's explicit test does.
 // STATS: also the lane's largest decrease (+inf for a node that left +inf)
 // and number of decreased nodes, into *mx and *cnt.
-template <typename T, int P, bool DIRECTIONAL, bool STATS = false>
-__device__ uint32_t sweep_tile(T* tu, const T* td, int w, int hgt, int dir, int lane,
-                               double* mx = nullptr, int* cnt = nullptr) {
+template <typename T, int P, bool DIRECTIONAL, bool STATS, int dir>
+__device__ __forceinline__ uint32_t sweep_tile_dir(T* tu, const T* td, int w, int hgt, int lane,
+                                                   double* mx, int* cnt) {
   lane = opaque_lane(lane);
   double smx = 0.0;
   int scnt = 0;
@@ -530,6 +530,19 @@ __device__ uint32_t sweep_tile(T* tu, const T* td, int w, int hgt, int dir, int 
     *cnt = scnt;
   }
   return (ballot(changed) ? 1u : 0u) | (ballot(back_x) ? 2u : 0u) | (ballot(back_y) ? 4u : 0u);
+}
+
+// The sweep with its direction fixed at compile time (the neighbour offsets
+// become immediates of the LDS accesses).
+template <typename T, int P, bool DIRECTIONAL, bool STATS = false>
+__device__ uint32_t sweep_tile(T* tu, const T* td, int w, int hgt, int dir, int lane,
+                               double* mx = nullptr, int* cnt = nullptr) {
+  switch (dir) {
+    case 0: return sweep_tile_dir<T, P, DIRECTIONAL, STATS, 0>(tu, td, w, hgt, lane, mx, cnt);
+    case 1: return sweep_tile_dir<T, P, DIRECTIONAL, STATS, 1>(tu, td, w, hgt, lane, mx, cnt);
+    case 2: return sweep_tile_dir<T, P, DIRECTIONAL, STATS, 2>(tu, td, w, hgt, lane, mx, cnt);
+    default: return sweep_tile_dir<T, P, DIRECTIONAL, STATS, 3>(tu, td, w, hgt, lane, mx, cnt);
+  }
 }
 
 // Convergence test of the tile against its halo: true when no node would
