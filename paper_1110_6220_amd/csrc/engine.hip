@@ -486,7 +486,7 @@ __device__ __forceinline__ uint32_t sweep_tile_dir(T* tu, const T* td, int w, in
   const int i = col_ok ? (sx > 0 ? lane : w - 1 - lane) : 0;
   const int j0 = sy > 0 ? 0 : hgt - 1;
   const int dummy = P * P + lane;
-  const int nsteps = w + hgt - 1;
+  const int nsteps = __builtin_amdgcn_readfirstlane(w + hgt - 1);  // the same on every lane
   // LDS index of the lane's node at sweep-order row t, clamped to the halo rows
   auto idx_t = [&](int t) {
     const int tc = t < -1 ? -1 : (t > hgt ? hgt : t);
@@ -494,14 +494,19 @@ __device__ __forceinline__ uint32_t sweep_tile_dir(T* tu, const T* td, int w, in
   };
   int c = idx_t(-lane);
   T prev = tu[idx_t(-1)];
-  T ev = tu[c + sx], nv = tu[c + rowstep], uo = tu[c], dl = td[c], hw = tu[c - sx];
   bool changed = false, back_x = false, back_y = false;
-
-  for (int d = 0; d < nsteps; ++d) {
+  // One step at d: the node's old value uo and its north value nv were read
+  // before; the values of the next step are read into the *n references.
+  // The lane's row index moves by one row while t + 1 lies in [0, hgt].
+  auto step = [&](int d, const T& ev, const T& uo, const T& nv, const T& dl, const T& hw,
+                  T& evn, T& nvn, T& dln, T& hwn) {
     const int t = d - lane;
     const bool valid = col_ok && (unsigned)t < (unsigned)hgt;
-    const int c1 = idx_t(t + 1);
-    const T ev1 = tu[c1 + sx], nv1 = tu[c1 + rowstep], dl1 = td[c1], hw1 = tu[c1 - sx];
+    const int c1 = c + ((unsigned)(t + 1) <= (unsigned)hgt ? rowstep : 0);
+    evn = tu[c1 + sx];
+    nvn = tu[c1 + rowstep];
+    dln = td[c1];
+    hwn = tu[c1 - sx];
     const T wv = shr1_or(prev, hw);
     const T a = DIRECTIONAL ? wv : vmin(wv, ev);
     const T b = DIRECTIONAL ? prev : vmin(prev, nv);
@@ -519,12 +524,21 @@ __device__ __forceinline__ uint32_t sweep_tile_dir(T* tu, const T* td, int w, in
     tu[valid ? c : dummy] = r;
     prev = valid ? r : prev;
     c = c1;
-    ev = ev1;
-    uo = nv;
-    nv = nv1;
-    dl = dl1;
-    hw = hw1;
+  };
+  // two steps per iteration (the step count is wave-uniform): the values
+  // read one step ahead alternate between two register sets
+  T evA = tu[c + sx], nvA = tu[c + rowstep], uoA = tu[c], dlA = td[c], hwA = tu[c - sx];
+  T evB, nvB, dlB, hwB;
+  int d = 0;
+  for (; d + 1 < nsteps; d += 2) {
+    step(d, evA, uoA, nvA, dlA, hwA, evB, nvB, dlB, hwB);
+    step(d + 1, evB, nvA, nvB, dlB, hwB, evA, uoA, dlA, hwA);
+    // the next north value was read into uoA; the old value is nvB
+    const T nn = uoA;
+    uoA = nvB;
+    nvA = nn;
   }
+  if (d < nsteps) step(d, evA, uoA, nvA, dlA, hwA, evB, nvB, dlB, hwB);
   if constexpr (STATS) {
     *mx = smx;
     *cnt = scnt;
