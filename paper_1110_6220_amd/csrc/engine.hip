@@ -652,32 +652,42 @@ __device__ void load_tile(T* tu, T* td, const Inst& I, const CellBox& B, int lan
   lane = opaque_lane(lane);
   using lds_ptr = __attribute__((address_space(3))) void*;
   constexpr int kCohPolicy = 16;             // sc1
-  const char* ub = static_cast<const char*>(I.u);
-  const char* db = static_cast<const char*>(I.delta);
+  // the cell box and grid are the same on every lane: scalar loop control
+  // and row addresses
+  auto uni_ptr = [](const void* p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return reinterpret_cast<const char*>((uint64_t)hi << 32 | lo);
+  };
+  const char* ub = uni_ptr(I.u);
+  const char* db = uni_ptr(I.delta);
   const T INF = inf_v<T>();
-  const int nx = I.nx, ny = I.ny;
-  const int rowbytes = B.w * (int)sizeof(T);
+  const int nx = __builtin_amdgcn_readfirstlane(I.nx), ny = __builtin_amdgcn_readfirstlane(I.ny);
+  const int bw = __builtin_amdgcn_readfirstlane(B.w), bh = __builtin_amdgcn_readfirstlane(B.hgt);
+  const int bx0 = __builtin_amdgcn_readfirstlane(B.x0), by0 = __builtin_amdgcn_readfirstlane(B.y0);
+  const int rowbytes = bw * (int)sizeof(T);
   const int n16 = rowbytes >> 4;           // full 16-byte pieces of a row
   const int tail_dw = (rowbytes & 15) >> 2;  // remaining dwords
-  for (int r = -1; r <= B.hgt; ++r) {
-    const bool halo_row = r < 0 || r == B.hgt;
+  for (int r = -1; r <= bh; ++r) {
+    const bool halo_row = r < 0 || r == bh;
     if (!with_interior && !halo_row) {
-      r = B.hgt - 1;  // skip to the north halo row
+      r = bh - 1;  // skip to the north halo row
       continue;
     }
     if (nparts > 1 && (r + 1) % nparts != part) continue;
-    const int j = B.y0 + r;
+    const int j = by0 + r;
     T* lu = tu + (r + 1) * P + 1;
     T* ld = td + (r + 1) * P + 1;
     if (j < 0 || j >= ny) {
-      if (lane < B.w) {
+      if (lane < bw) {
         lu[lane] = INF;
         ld[lane] = INF;
       }
       continue;
     }
     const bool skip_u = fresh && !halo_row;
-    const size_t row = ((size_t)j * nx + B.x0) * sizeof(T);
+    const size_t row = ((size_t)j * nx + bx0) * sizeof(T);
     // 16 bytes per lane for the bulk of the row, then single dwords for the
     // ragged end (rows are at most 512 bytes: one instruction each)
     if (lane < n16) {
@@ -693,7 +703,7 @@ __device__ void load_tile(T* tu, T* td, const Inst& I, const CellBox& B, int lan
         __builtin_amdgcn_global_load_lds(db + at, (lds_ptr)((char*)ld + 16 * n16), 4, 0, 0);
       }
     }
-    if (skip_u && lane < B.w) lu[lane] = INF;
+    if (skip_u && lane < bw) lu[lane] = INF;
   }
   if (part == 0) {
     const gptr<const T> u = to_global(static_cast<const T*>(I.u));
