@@ -63,12 +63,20 @@ typedef enum { EIK_EXACT = 0, EIK_FMSM = 1, EIK_FHCM = 2 } eik_method;
  *           (eq. cell_value; the Heap-Cell Methods' heap with ties widened to
  *           a band of width `band`).  The default for FHCM.
  *   FIFO    cells are taken in the order they were queued.
+ *   HEAP    one cell at a time, always the queued cell with the smallest
+ *           (cell value, cell index): the heap of the Heap-Cell Methods
+ *           (Section 3.2.2) exactly, with cell values compared in FP64.
+ *           One wave does all the work (a reference order, slow: each
+ *           removal scans per-block minima of the queued cells' values);
+ *           FHCM under HEAP reproduces the serial method of Algorithm FHCM
+ *           bit for bit.  Not for FMSM.
  * EXACT gives the same result under every order. */
 typedef enum {
   EIK_SCHED_AUTO = 0,
   EIK_SCHED_COARSE = 1,
   EIK_SCHED_BANDS = 2,
-  EIK_SCHED_FIFO = 3
+  EIK_SCHED_FIFO = 3,
+  EIK_SCHED_HEAP = 4
 } eik_schedule;
 
 typedef struct {
@@ -81,7 +89,8 @@ typedef struct {
   void* stream;             /* hipStream_t, or NULL for the null stream         */
   uint64_t max_cell_visits; /* guard on total cell visits; 0 = 64 * cells + 1024 */
   int32_t residual_check;   /* F32: recheck the fixed-point residual in FP64 and
-                               re-solve in FP64 when it exceeds 4 * 2^-24       */
+                               re-solve in FP64 each problem whose residual
+                               exceeds residual_tol (F64: only report it)     */
   int32_t workers;          /* persistent waves; 0 = chosen from the problem    */
   int32_t band_window;      /* bands above the lowest unfinished band whose
                                cells may start, 0..63 (band <= 0: unused)       */
@@ -98,8 +107,14 @@ typedef struct {
                                contents may change between calls.  Up to 8
                                graphs are kept per device and dropped when the
                                library's workspace has to grow.              */
+  double residual_tol;      /* residual_check bound on max |T(u)-u|/u; 0 = 4 * 2^-24
+                               (must be >= 0 and finite)                       */
 } eik_opts;
 
+/* Statistics of one problem.  In a batch, cells, cell_visits, sweeps,
+   checks, max_residual and fell_back_to_f64 are the problem's own; seconds,
+   kernel_seconds, band_steps, mon_checks and mon_ok are those of the whole
+   launch. */
 typedef struct {
   double seconds;           /* wall time of the call                            */
   double kernel_seconds;    /* device time of the cell-processing kernel(s)     */
@@ -111,14 +126,18 @@ typedef struct {
   uint64_t band_steps;      /* advances of the queue's lowest band              */
   uint64_t mon_checks;      /* FHCM monotonicity checks                         */
   uint64_t mon_ok;          /* ... that found a monotone side                   */
-  double max_residual;      /* max fixed-point residual |T(u)-u|/u (FP64), or -1
-                               when not computed                                */
+  double max_residual;      /* max fixed-point residual |T(u)-u|/u (FP64) of the
+                               solution, or -1 when not computed; after an FP64
+                               re-solve, that of the FP64 solution before it is
+                               rounded into the FP32 output                    */
   int32_t cell_used;        /* cell side used                                   */
   double band_used;         /* band width used                                  */
-  int32_t fell_back_to_f64; /* F32 residual check failed and FP64 re-solved     */
-  uint64_t cells_total;     /* cells of the whole launch (batches: all problems;
-                               visit and sweep counters are launch totals)      */
+  int32_t fell_back_to_f64; /* F32 residual check failed and this problem was
+                               re-solved in FP64 (result rounded to FP32)      */
+  uint64_t cells_total;     /* cells of the whole launch (all problems)         */
   int32_t graph_replayed;   /* 1: this call replayed a captured graph          */
+  double residual_f32;      /* F32 with residual_check: the FP32 solution's own
+                               residual (also when it was re-solved), else -1  */
 } eik_stats;
 
 /* Solve one problem.

@@ -72,18 +72,19 @@ void DevBuf::release() {
   bytes = 0;
 }
 
+std::vector<DevBuf*> Solver::bufs() {
+  return {&delta, &st,   &visits, &cell_inst, &key, &deps, &ord,  &slot,
+          &head,  &tail, &inflight, &cursor,  &ctl, &inst, &hblk, &istat};
+}
+
 void Solver::release() {
-  for (DevBuf* b : {&delta, &st, &visits, &cell_inst, &key, &deps, &ord, &slot, &head, &tail,
-                    &inflight, &cursor, &ctl, &inst})
-    b->release();
+  for (DevBuf* b : bufs()) b->release();
 }
 
 static std::vector<DevBuf*> all_bufs(Workspace* w) {
   std::vector<DevBuf*> v;
   for (Solver* sv : {&w->fine, &w->coarse})
-    for (DevBuf* b : {&sv->delta, &sv->st, &sv->visits, &sv->cell_inst, &sv->key, &sv->deps, &sv->ord,
-                      &sv->slot, &sv->head, &sv->tail, &sv->inflight, &sv->cursor, &sv->ctl, &sv->inst})
-      v.push_back(b);
+    for (DevBuf* b : sv->bufs()) v.push_back(b);
   for (DevBuf* b : {&w->F, &w->u, &w->mask, &w->src, &w->q, &w->cF, &w->cmask, &w->cq, &w->cu,
                     &w->cout, &w->crank, &w->fmm_spill, &w->sweep_stat, &w->sweep_dirty, &w->grid3, &w->fmsm3, &w->F64,
                     &w->u64, &w->ready_at, &w->trace,
@@ -179,8 +180,10 @@ int check_opts(const eik_opts& o) {
   if (o.workers < 0) return fail(EIK_EINVAL, "workers must be >= 0");
   if (o.band_window < 0 || o.band_window > 63) return fail(EIK_EINVAL, "band_window outside [0, 63]");
   if (o.timeout_ms < 0) return fail(EIK_EINVAL, "timeout_ms must be >= 0");
-  if (o.schedule < EIK_SCHED_AUTO || o.schedule > EIK_SCHED_FIFO)
+  if (o.schedule < EIK_SCHED_AUTO || o.schedule > EIK_SCHED_HEAP)
     return fail(EIK_EINVAL, "unknown schedule %d", (int)o.schedule);
+  if (!(o.residual_tol >= 0.0) || std::isinf(o.residual_tol))
+    return fail(EIK_EINVAL, "residual_tol must be >= 0 and finite");
   if (o.method == EIK_FMSM && o.schedule != EIK_SCHED_AUTO && o.schedule != EIK_SCHED_COARSE)
     return fail(EIK_EINVAL, "FMSM processes cells in the coarse order only");
   if (o.method == EIK_FHCM && o.schedule == EIK_SCHED_COARSE)
@@ -312,9 +315,9 @@ int validate_shape(const eik_problem& p) {
 
 // Sizes the solver's buffers for the instances in `inst` (cell0 filled in
 // here) and fills the engine arguments.
-int setup_engine(Solver& sv, std::vector<Inst>& inst, int dtype, int method, int dag, double band,
-                 int window, int eager, uint64_t guard, uint64_t timeout, hipStream_t stream,
-                 Engine* out, DevBuf* instbuf) {
+int setup_engine(Solver& sv, std::vector<Inst>& inst, int dtype, int method, int dag, int heap,
+                 double band, int window, int eager, uint64_t guard, uint64_t timeout,
+                 hipStream_t stream, Engine* out, DevBuf* instbuf) {
   DevBuf& ib = instbuf ? *instbuf : sv.inst;
   int64_t J = 0;
   for (auto& I : inst) {
@@ -327,7 +330,9 @@ int setup_engine(Solver& sv, std::vector<Inst>& inst, int dtype, int method, int
   const int n = (int)inst.size();
   HIP_TRY(sv.st.ensure(J * sizeof(uint32_t)));
   HIP_TRY(sv.visits.ensure(J * sizeof(uint32_t)));
-  HIP_TRY(sv.key.ensure(J * sizeof(uint32_t)));
+  HIP_TRY(sv.key.ensure(J * sizeof(unsigned long long)));
+  HIP_TRY(sv.istat.ensure(4 * (size_t)n * sizeof(unsigned long long)));
+  HIP_TRY(sv.hblk.ensure(heap ? ((J + 63) / 64) * sizeof(unsigned long long) : 8));
   HIP_TRY(sv.cell_inst.ensure(n > 1 ? J * sizeof(int32_t) : 4));
   HIP_TRY(sv.deps.ensure(dag ? J * sizeof(int32_t) : 4));
   HIP_TRY(sv.ord.ensure(dag ? J : 4));
@@ -352,7 +357,10 @@ int setup_engine(Solver& sv, std::vector<Inst>& inst, int dtype, int method, int
   e.st = sv.st.as<uint32_t>();
   e.visits = sv.visits.as<uint32_t>();
   e.cell_inst = sv.cell_inst.as<int32_t>();
-  e.key = sv.key.as<unsigned int>();
+  e.key = sv.key.as<unsigned long long>();
+  e.heap = heap;
+  e.hblk = sv.hblk.as<unsigned long long>();
+  e.istat = sv.istat.as<unsigned long long>();
   e.deps = sv.deps.as<int32_t>();
   e.ord = sv.ord.as<uint8_t>();
   e.q.slot = sv.slot.as<unsigned long long>();
@@ -400,9 +408,9 @@ constexpr size_t kMaxPlans = 8;           // captured graphs kept per workspace
 
 static int complete(Workspace* ws, int n, const eik_problem* probs, const eik_opts& o,
                     const RunCtx& ctx, const std::vector<Inst>& inst, int64_t J, double band,
-                    bool coarse_engine, bool want_resid, hipStream_t stream, double t0,
-                    eik_stats* stats, RunInfo* info, std::unique_lock<std::mutex>& lk,
-                    bool replayed);
+                    bool coarse_engine, bool want_resid, const unsigned long long* istat,
+                    hipStream_t stream, double t0, eik_stats* stats, RunInfo* info,
+                    std::unique_lock<std::mutex>& lk, bool replayed);
 
 // Identity of a problem set for graph replay: every input that shapes the
 // launch sequence (sizes, spacing, buffer addresses, options).  The contents
@@ -451,6 +459,7 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
   int sched = o.schedule;
   if (sched == EIK_SCHED_AUTO) sched = method == EIK_FHCM ? EIK_SCHED_BANDS : EIK_SCHED_COARSE;
   const bool dag = sched == EIK_SCHED_COARSE;
+  const bool heap = sched == EIK_SCHED_HEAP;
   const bool dev = o.device_ptrs != 0;
   const bool want_resid = o.residual_check != 0;
 
@@ -475,7 +484,7 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
       HIP_TRY(hipGraphLaunch(pl->post, stream));
       HIP_TRY(hipStreamSynchronize(stream));
       return complete(ws, n, probs, o, ctx, pl->host_inst, pl->J, pl->band, pl->coarse_engine,
-                      pl->want_resid, stream, t0, stats, info, lk, true);
+                      pl->want_resid, pl->e.istat, stream, t0, stats, info, lk, true);
     }
   }
   std::unique_ptr<Plan> np(use_graph ? new Plan() : nullptr);
@@ -607,14 +616,18 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
   if (sched == EIK_SCHED_BANDS) band = o.band > 0.0 ? o.band : hs_max;  // one cell crossing at unit speed
   const uint64_t timeout = (uint64_t)ws->wall_khz * (uint64_t)(o.timeout_ms ? o.timeout_ms : 10000);
   Engine e;
-  if ((rc = setup_engine(ws->fine, inst, dt, method, dag, band, o.band_window, o.eager_publish,
-                         o.max_cell_visits, timeout, stream, &e, np ? &np->inst : nullptr)))
+  if ((rc = setup_engine(ws->fine, inst, dt, method, dag, heap, band, o.band_window,
+                         o.eager_publish, o.max_cell_visits, timeout, stream, &e,
+                         np ? &np->inst : nullptr)))
     return rc;
   const int64_t J = e.ncells;
   const int tile = tile_for(extent);
   if (extent > tile) return fail(EIK_EINVAL, "internal: a cell of %d nodes exceeds the %d-node tile", extent, tile);
+  // the heap schedule has exactly one worker (it alone keeps the heap)
   const int workers =
-      o.workers ? o.workers : std::max(1, default_workers(ws, J, tile, dt, method, n) / std::max(1, ctx.share));
+      heap ? 1
+           : o.workers ? o.workers
+                       : std::max(1, default_workers(ws, J, tile, dt, method, n) / std::max(1, ctx.share));
 
   if (g_trace) {
     HIP_TRY(ws->ready_at.ensure(J * 8));
@@ -695,8 +708,8 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
       cext = std::max(cext, ct.extent);
     }
     HIP_TRY(hipMemcpyAsync(coutbuf.p, co.data(), n * sizeof(CoarseOut), hipMemcpyHostToDevice, stream));
-    if (!fmm && !jacobi && (rc = setup_engine(ws->coarse, cinst, EIK_F64, EIK_EXACT, 0, -1.0, 0, 0, 0, timeout, stream,
-                                   &ce, np ? &np->cinst : nullptr)))
+    if (!fmm && !jacobi && (rc = setup_engine(ws->coarse, cinst, EIK_F64, EIK_EXACT, 0, 0, -1.0, 0, 0, 0,
+                                              timeout, stream, &ce, np ? &np->cinst : nullptr)))
       return rc;
     have_coarse = true;
     coarse_engine = !fmm && !jacobi;
@@ -795,17 +808,17 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
     ws->plans.push_back(std::move(np));
   }
   HIP_TRY(hipStreamSynchronize(stream));
-  return complete(ws, n, probs, o, ctx, inst, J, band, coarse_engine, want_resid, stream, t0, stats,
-                  info, lk, false);
+  return complete(ws, n, probs, o, ctx, inst, J, band, coarse_engine, want_resid, e.istat, stream,
+                  t0, stats, info, lk, false);
 }
 
-// After the solve's stream has completed: errors, FP32 certification, copies
-// to host outputs, diagnostics and statistics.
+// After the solve's stream has completed: errors, FP32 certification (per
+// problem), copies to host outputs, diagnostics and statistics.
 static int complete(Workspace* ws, int n, const eik_problem* probs, const eik_opts& o,
                     const RunCtx& ctx, const std::vector<Inst>& inst, int64_t J, double band,
-                    bool coarse_engine, bool want_resid, hipStream_t stream, double t0,
-                    eik_stats* stats, RunInfo* info, std::unique_lock<std::mutex>& lk,
-                    bool replayed) {
+                    bool coarse_engine, bool want_resid, const unsigned long long* istat,
+                    hipStream_t stream, double t0, eik_stats* stats, RunInfo* info,
+                    std::unique_lock<std::mutex>& lk, bool replayed) {
   const int dt = o.dtype;
   const size_t es = dsize(dt);
   const bool dev = o.device_ptrs != 0;
@@ -819,18 +832,40 @@ static int complete(Workspace* ws, int n, const eik_problem* probs, const eik_op
     return fail(EIK_ENOTCONV, "cell-visit guard tripped after %llu visits", (unsigned long long)c.visits);
   if (err & kErrDeadline) return fail(EIK_EDEVICE, "solver exceeded its time limit");
   float ms = 0.f;
-  HIP_TRY(hipEventElapsedTime(&ms, ws->ev0, ws->ev1));
-  double resid = -1.0;
-  if (want_resid) std::memcpy(&resid, &c.resid_bits, sizeof resid);
+  if (ws->ev0) HIP_TRY(hipEventElapsedTime(&ms, ws->ev0, ws->ev1));
+  // per-problem counters and residuals (batches count per problem on the
+  // device; a single problem's are the launch totals)
+  std::vector<unsigned long long> is;
+  if (n > 1 || want_resid) {
+    is.resize(4 * (size_t)n);
+    HIP_TRY(hipMemcpyAsync(is.data(), istat, is.size() * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+  }
+  std::vector<double> resid(n, -1.0), resid32(n, -1.0);
+  std::vector<int> fell(n, 0);
+  if (want_resid)
+    for (int k = 0; k < n; ++k) std::memcpy(&resid[k], &is[4 * (size_t)k + 3], sizeof(double));
 
-  // FP32: certify the result with the FP64 residual, else re-solve in FP64
-  int fell_back = 0;
-  if (dt == EIK_F32 && want_resid && !(resid <= 4.0 * std::ldexp(1.0, -24))) {
-    lk.unlock();  // the FP64 solve takes the workspace lock itself
-    rc = refine_fp64(n, probs, inst, o, stream, ctx);
-    lk.lock();
-    if (rc) return rc;
-    fell_back = 1;
+  // FP32: certify each problem by its FP64 residual, else re-solve it in FP64
+  if (dt == EIK_F32 && want_resid) {
+    const double tol = o.residual_tol > 0.0 ? o.residual_tol : 4.0 * std::ldexp(1.0, -24);
+    std::vector<int> which;
+    for (int k = 0; k < n; ++k) {
+      resid32[k] = resid[k];
+      if (!(resid[k] <= tol)) which.push_back(k);
+    }
+    if (!which.empty()) {
+      std::vector<double> r64;
+      lk.unlock();  // the FP64 solve takes the workspace lock itself
+      rc = refine_fp64(which, probs, inst, o, stream, ctx, &r64);
+      lk.lock();
+      if (rc) return rc;
+      for (size_t x = 0; x < which.size(); ++x) {
+        fell[which[x]] = 1;
+        resid[which[x]] = r64[x];
+      }
+    }
   }
   if (!dev) {
     for (int k = 0; k < n; ++k)
@@ -873,72 +908,82 @@ static int complete(Workspace* ws, int n, const eik_problem* probs, const eik_op
       S.seconds = now_s() - t0;
       S.kernel_seconds = ms * 1e-3;
       S.cells = (uint64_t)inst[k].kx * inst[k].ky;
-      S.cell_visits = c.visits;
-      S.sweeps = c.sweeps;
-      S.checks = c.checks;
+      S.cell_visits = n > 1 ? is[4 * (size_t)k] : c.visits;
+      S.sweeps = n > 1 ? is[4 * (size_t)k + 1] : c.sweeps;
+      S.checks = n > 1 ? is[4 * (size_t)k + 2] : c.checks;
       S.band_steps = c.band_steps;
       S.mon_checks = c.mon_checks;
       S.mon_ok = c.mon_ok;
-      S.max_residual = resid;
+      S.max_residual = resid[k];
       S.cell_used = inst[k].s;
       S.band_used = band;
-      S.fell_back_to_f64 = fell_back;
+      S.fell_back_to_f64 = fell[k];
       S.cells_total = (uint64_t)J;
       S.graph_replayed = replayed ? 1 : 0;
+      S.residual_f32 = resid32[k];
     }
   }
   return EIK_OK;
 }
 
 // Re-solves FP32 problems in FP64 (speeds widened on the device) and rounds
-// the result into the FP32 outputs (inst[k].u: device memory).
-int refine_fp64(int n, const eik_problem* probs, const std::vector<Inst>& inst, const eik_opts& o,
-                hipStream_t stream, const RunCtx& ctx) {
+// the results into their FP32 outputs (inst[k].u: device memory).  The FP64
+// solve computes its own residual, which is returned per problem.
+int refine_fp64(const std::vector<int>& which, const eik_problem* probs,
+                const std::vector<Inst>& inst, const eik_opts& o, hipStream_t stream,
+                const RunCtx& ctx, std::vector<double>* resid) {
   Workspace* ws = ctx.ws;
+  const int m = (int)which.size();
   int64_t total = 0;
-  for (int k = 0; k < n; ++k) total += (int64_t)probs[k].nx * probs[k].ny;
+  for (int k : which) total += (int64_t)probs[k].nx * probs[k].ny;
   if (!ctx.f64) {
     std::lock_guard<std::mutex> lk(ws->mu);
     HIP_TRY(ws->F64.ensure(total * sizeof(double)));
     HIP_TRY(ws->u64.ensure(total * sizeof(double)));
   }
-  std::vector<eik_problem> p64(probs, probs + n);
-  std::vector<double*> u64(n);
-  std::vector<void*> d64(n);
+  std::vector<eik_problem> p64(m);
+  std::vector<double*> u64(m);
+  std::vector<void*> d64(m);
   int64_t off = 0;
-  for (int k = 0; k < n; ++k) {
+  for (int x = 0; x < m; ++x) {
+    const int k = which[x];
     const int64_t nn = (int64_t)probs[k].nx * probs[k].ny;
     double* F;
     if (ctx.f64) {
       F = static_cast<double*>(ctx.f64[k]);
-      u64[k] = F + nn;
-      d64[k] = F + 2 * nn;
+      u64[x] = F + nn;
+      d64[x] = F + 2 * nn;
     } else {
       F = ws->F64.as<double>() + off;
-      u64[k] = ws->u64.as<double>() + off;
+      u64[x] = ws->u64.as<double>() + off;
     }
     HIP_TRY(launch_convert(inst[k].F, EIK_F32, F, EIK_F64, nn, stream));
-    p64[k].F = F;
-    p64[k].u_out = u64[k];
-    p64[k].mask = inst[k].mask;
-    p64[k].src = inst[k].src;
-    p64[k].q = inst[k].q;
+    p64[x] = probs[k];
+    p64[x].F = F;
+    p64[x].u_out = u64[x];
+    p64[x].mask = inst[k].mask;
+    p64[x].src = inst[k].src;
+    p64[x].q = inst[k].q;
     off += nn;
   }
   eik_opts o64 = o;
   o64.dtype = EIK_F64;
   o64.device_ptrs = 1;
-  o64.residual_check = 0;
+  o64.residual_check = 1;  // FP64: reported, never re-solved
   o64.graph = 0;
   RunCtx c64;
   c64.ws = ws;
   c64.delta = ctx.f64 ? d64.data() : nullptr;
   c64.share = ctx.share;
-  int rc = run(n, p64.data(), o64, nullptr, nullptr, &c64);
+  std::vector<eik_stats> st(m);
+  int rc = run(m, p64.data(), o64, st.data(), nullptr, &c64);
   if (rc) return rc;
-  for (int k = 0; k < n; ++k) {
+  resid->resize(m);
+  for (int x = 0; x < m; ++x) {
+    const int k = which[x];
     const int64_t nn = (int64_t)probs[k].nx * probs[k].ny;
-    HIP_TRY(launch_convert(u64[k], EIK_F64, inst[k].u, EIK_F32, nn, stream));
+    HIP_TRY(launch_convert(u64[x], EIK_F64, inst[k].u, EIK_F32, nn, stream));
+    (*resid)[x] = st[x].max_residual;
   }
   HIP_TRY(hipStreamSynchronize(stream));
   return EIK_OK;

@@ -88,10 +88,9 @@ struct Ctl {
   unsigned long long band_steps;  // cursor advances
   unsigned long long mon_checks;
   unsigned long long mon_ok;
-  unsigned long long resid_bits;  // max residual (bits of a non-negative double)
   // phase timers (wall-clock ticks summed over waves), when profiling
   unsigned long long t_idle, t_claim, t_load, t_sweep, t_publish, t_finish;
-  unsigned long long pad_s[4];
+  unsigned long long pad_s[5];
 };
 constexpr unsigned kErrSpeed = 1u, kErrSource = 2u, kErrGuard = 4u, kErrDeadline = 8u;
 
@@ -108,11 +107,19 @@ struct Engine {
   uint32_t* st;          // J state words
   uint32_t* visits;      // J removal counts
   int32_t* cell_inst;    // J instance ids (ninst > 1)
-  unsigned int* key;     // J orderable bits of the float cell value
+  unsigned long long* key;  // J orderable bits of the cell value (key_bits of a double)
   int32_t* deps;         // J unfinished earlier neighbours (dag)
   uint8_t* ord;          // J order bits (dag)
   Queue q;
   Ctl* ctl;
+  // heap schedule: one wave processes cells one at a time in increasing
+  // (cell value, cell index) order; hblk[b] = smallest key of the pending
+  // cells 64 b .. 64 b + 63 (kKeyNone: none)
+  int32_t heap;
+  unsigned long long* hblk;
+  // per instance k: istat[4k] visits, [4k+1] productive sweeps, [4k+2]
+  // no-change sweeps (batches only), [4k+3] bits of the FP64 residual
+  unsigned long long* istat;
   int32_t eager;         // publish after every productive sweep
   int32_t profile;       // accumulate phase timers in Ctl
   // diagnostic trace (null when off): per cell the wall clock when it was

@@ -155,14 +155,19 @@ __device__ __forceinline__ int opaque_lane(int lane) {
 }
 __device__ __forceinline__ unsigned long long ballot(bool p) { return __ballot(p); }
 
-// orderable encoding of a float as an unsigned int (monotone)
-__device__ __forceinline__ unsigned int key_bits(float f) {
-  const unsigned int b = __builtin_bit_cast(unsigned int, f);
-  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+// Orderable encoding of a cell value (a double, never NaN) as a 64-bit
+// unsigned integer: a < b exactly when key_bits(a) < key_bits(b), so an
+// integer atomic minimum keeps the smallest value exactly (eq. cell_value's
+// estimates are compared in the precision they are computed in).
+constexpr unsigned long long kKeyInf = 0xFFF0000000000000ull;  // key_bits(+inf)
+constexpr unsigned long long kKeyNone = ~0ull;                 // above every value
+__device__ __forceinline__ unsigned long long key_bits(double f) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, f);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
 }
-__device__ __forceinline__ float key_float(unsigned int k) {
-  const unsigned int b = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
-  return __builtin_bit_cast(float, b);
+__device__ __forceinline__ double key_value(unsigned long long k) {
+  const unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+  return __builtin_bit_cast(double, b);
 }
 
 __device__ __forceinline__ int cell_lo(int k, int n, int K, int s, int bal) {
@@ -234,9 +239,9 @@ __device__ __forceinline__ void order_acquire() {
 // cell queue (per-lane operations except q_pop)
 // ----------------------------------------------------------------------------
 
-__device__ __forceinline__ unsigned long long band_of(const Queue& q, float key) {
-  if (q.nb <= 1 || !(key > 0.0f)) return 0;
-  const double b = (double)key * q.inv_width;
+__device__ __forceinline__ unsigned long long band_of(const Queue& q, double key) {
+  if (q.nb <= 1 || !(key > 0.0)) return 0;
+  const double b = key * q.inv_width;
   return b < 1e15 ? (unsigned long long)b : 1000000000000000ull;
 }
 
@@ -248,7 +253,7 @@ __device__ __forceinline__ unsigned long long* ctr(unsigned long long* base, uin
 // [cursor, cursor + nb)).  Every cell is in the queue at most once (guarded by
 // its state word) and cap > cells, so a producer only waits for a consumer
 // that has already claimed the slot's previous ticket.
-__device__ void q_push(const Engine& e, uint32_t cell, float key) {
+__device__ void q_push(const Engine& e, uint32_t cell, double key) {
   const Queue& q = e.q;
   uint32_t r = 0;
   if (q.nb > 1) {
@@ -400,6 +405,60 @@ __device__ __forceinline__ void q_done(const Engine& e, int ring) {
 }
 
 // ----------------------------------------------------------------------------
+// heap schedule (one worker wave): the pending cell with the smallest
+// (cell value, cell index) -- the heap order of the Heap-Cell Methods
+// (Section 3.2.2) with the oracle's tie rule -- found through per-block minima
+// ----------------------------------------------------------------------------
+
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const unsigned long long y = __shfl_xor(v, o, 64);
+    v = y < v ? y : v;
+  }
+  return v;
+}
+
+// Key of cell c if it is pending and not running, else kKeyNone.
+__device__ __forceinline__ unsigned long long pending_key(const Engine& e, int c) {
+  if (c >= e.ncells) return kKeyNone;
+  const uint32_t st = ld_coh(&e.st[c]);
+  if (!(st & kPending) || (st & kRunning)) return kKeyNone;
+  return ld_coh(&e.key[c]);
+}
+
+// Recomputes the minimum of block b (wave-cooperative).
+__device__ __noinline__ void heap_fix(const Engine& e, int b, int lane) {
+  if (b < 0 || b >= ((e.ncells + 63) >> 6)) return;
+  const unsigned long long m = wave_min_u64(pending_key(e, b * 64 + lane));
+  if (lane == 0) st_coh(&e.hblk[b], m);
+}
+
+// The pending cell with the smallest (key, index), or -1 (wave-uniform).
+// Blocks are scanned in index order, so among equal minima the lowest block
+// -- which holds the lowest cell index with that key -- wins.
+__device__ __noinline__ int heap_pop(const Engine& e, int lane) {
+  const int nblk = (e.ncells + 63) >> 6;
+  unsigned long long best = kKeyNone;
+  int bb = 0x7fffffff;
+  for (int b = lane; b < nblk; b += 64) {
+    const unsigned long long v = ld_coh(&e.hblk[b]);
+    if (v < best) {
+      best = v;
+      bb = b;
+    }
+  }
+  const unsigned long long m = wave_min_u64(best);
+  if (m == kKeyNone) return -1;
+  const int blk = __builtin_amdgcn_readfirstlane(wave::min_i(best == m ? bb : 0x7fffffff));
+  const unsigned long long k = pending_key(e, blk * 64 + lane);
+  const unsigned long long km = wave_min_u64(k);
+  if (km == kKeyNone) return -1;  // not reached: the block minimum is kept current
+  const unsigned long long at = ballot(k == km);
+  return blk * 64 + __builtin_ctzll(at);
+}
+
+// ----------------------------------------------------------------------------
 // cell state transitions (one lane)
 // ----------------------------------------------------------------------------
 
@@ -408,7 +467,9 @@ __device__ __forceinline__ void q_done(const Engine& e, int ring) {
 // idle and its first processing is done; a running cell takes the request
 // itself when it finishes, and a cell still waiting for its first processing
 // reads the new values when it starts.
-__device__ void requeue(const Engine& e, int g, uint32_t fl, uint32_t sides, float key) {
+// Under the heap schedule a queued cell is only marked pending: the single
+// worker finds it by its cell value (heap_pop).
+__device__ void requeue(const Engine& e, int g, uint32_t fl, uint32_t sides, double key) {
   order_release();
   const uint32_t old =
       __hip_atomic_fetch_or(&e.st[g], kPending | (fl << kFlagShift) | (sides << kSideShift),
@@ -416,7 +477,7 @@ __device__ void requeue(const Engine& e, int g, uint32_t fl, uint32_t sides, flo
   if (!(old & (kPending | kRunning)) && (old & kDone1)) {
     atomic_add_relaxed(&e.ctl->active, 1ull);
     if (e.ready_at) e.ready_at[g] = wall_clock64();
-    q_push(e, (uint32_t)g, key);
+    if (!e.heap) q_push(e, (uint32_t)g, key);
   }
 }
 
@@ -426,7 +487,7 @@ __device__ void release_first(const Engine& e, int g) {
   order_release();
   __hip_atomic_fetch_or(&e.st[g], kPending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (e.ready_at) e.ready_at[g] = wall_clock64();
-  q_push(e, (uint32_t)g, 0.0f);
+  q_push(e, (uint32_t)g, 0.0);
 }
 
 // Takes a popped (or re-requested) cell: state -> running, keeping kDone1.
@@ -774,15 +835,11 @@ __device__ double speed_at(const Inst& I, int side, int along, int other, int wk
   return cnt ? sum / cnt : 0.0;
 }
 
-// wave-wide max of x with the lowest lane attaining it (x = -inf: none)
-__device__ __forceinline__ float wave_max(float x, int* arg) {
-  float m = x;
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    const float y = __shfl_xor(m, o, 64);
-    m = y > m ? y : m;
-  }
-  const unsigned long long at = ballot(x == m && m > -__builtin_huge_valf());
+// wave-wide max of x (never NaN) with the lowest lane attaining it
+// (x = -inf on every lane: none, *arg = -1)
+__device__ __forceinline__ double wave_max(double x, int* arg) {
+  const double m = wave::max_d(x);
+  const unsigned long long at = ballot(x == m && m > -__builtin_huge_val());
   *arg = at ? __builtin_ctzll(at) : -1;
   return m;
 }
@@ -814,7 +871,7 @@ __device__ void publish(const Engine& e, const Inst& I, const CellBox& B, int g,
   // per side: add criterion met somewhere, max finite value and its lane,
   // monotonicity; lane `side` keeps side's results
   bool my_crit = false;
-  float my_kv = -__builtin_huge_valf();
+  double my_kv = -__builtin_huge_val();
   int my_karg = -1;
   uint32_t my_mono = 3u;
 #pragma nounroll
@@ -832,7 +889,7 @@ __device__ void publish(const Engine& e, const Inst& I, const CellBox& B, int g,
     const T ps = side == 0 ? pub[0] : side == 1 ? pub[1] : side == 2 ? pub[2] : pub[3];
     const T v = tu[idx_in];
     bool c = false;
-    float vmax = -__builtin_huge_valf();
+    double vmax = -__builtin_huge_val();
     if (ok) {
       const bool is_src = td[idx_in] == INF && v != INF;
       const bool changed = v < ps || (first && is_src);
@@ -842,7 +899,7 @@ __device__ void publish(const Engine& e, const Inst& I, const CellBox& B, int g,
         st_coh(u + (size_t)jj * I.nx + ii, v);
       }
       c = changed && td[idx_out] != INF && v < tu[idx_out];
-      if (v != INF) vmax = (float)v;
+      if (v != INF) vmax = (double)v;
     }
     const T np = ok ? v : ps;
     if (side == 0) pub[0] = np;
@@ -851,7 +908,7 @@ __device__ void publish(const Engine& e, const Inst& I, const CellBox& B, int g,
     else pub[3] = np;
     const bool cr = ballot(c) != 0ull;
     int ka;
-    const float kvv = wave_max(vmax, &ka);
+    const double kvv = wave_max(vmax, &ka);
     const uint32_t mo = M == kFhcm ? line_monotone(v, ok && v != INF, lane) : 3u;
     if (lane == side) {
       my_crit = cr;
@@ -879,16 +936,16 @@ __device__ void publish(const Engine& e, const Inst& I, const CellBox& B, int g,
       wk = cell_lo(B.cy + 2, I.ny, I.ky, I.s, I.balanced) - B.y1;
     }
     if (nb >= 0) {
-      float key = __builtin_huge_valf();
+      double key = __builtin_huge_val();
       if (!e.dag && my_karg >= 0) {
         const int along = side == 0 ? B.x0 : side == 1 ? B.x1 - 1 : side == 2 ? B.y0 : B.y1 - 1;
         const int other = side <= 1 ? B.y0 + my_karg : B.x0 + my_karg;
         const double fy = speed_at<T>(I, side, along, other, wk);
         if (fy > 0.0) {
-          key = (float)((double)my_kv + (0.5 * (1 + wk) * I.h) / fy);
-          const unsigned int old = __hip_atomic_fetch_min(&e.key[nb], key_bits(key),
-                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          const float okey = key_float(old);
+          key = my_kv + (0.5 * (1 + wk) * I.h) / fy;
+          const unsigned long long old = __hip_atomic_fetch_min(
+              &e.key[nb], key_bits(key), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const double okey = key_value(old);
           if (okey < key) key = okey;
         }
       }
@@ -944,10 +1001,22 @@ __device__ void release_later(const Engine& e, int g, const Inst& I, const CellB
 // ~70-90 cycles.
 constexpr int kSolveWaves1 = 4;  // waves per worker for single problems
 
+// LDS of a tile with pitch P: one guard row, the (P x P) tile with its halo,
+// 64 per-lane dummy slots and one guard element.  The sweep reads the next
+// step's operands one step ahead, and on its last steps that read reaches one
+// row beyond the far halo row (south: row -1; north: up to P*P + P - 2); the
+// guards keep those reads, whose values are discarded, inside the array.
+template <int P>
+struct TileLds {
+  static constexpr int kBefore = P;
+  static constexpr int kSize = P + P * P + 64 + 1;
+};
+
 template <typename T, int S, int M, int NW>
 __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
   constexpr int P = S + 2;
-  __shared__ T tu[P * P + 64];  // tile + per-lane dummy slots
+  __shared__ T tu_mem[TileLds<P>::kSize];
+  T* const tu = tu_mem + TileLds<P>::kBefore;  // tile + per-lane dummy slots
   __shared__ T td[P * P];
   __shared__ TileJob job;
   const int lane = threadIdx.x & 63;
@@ -997,11 +1066,14 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
   int backoff = 0;
   unsigned long long t0 = e.profile ? wall_clock64() : 0ull;
   unsigned long long nsweeps = 0, nchecks = 0;  // this wave's totals
+  if (e.heap)  // the only worker: block minima of the cells queued so far
+    for (int b = 0; b < ((e.ncells + 63) >> 6); ++b) heap_fix(e, b, lane);
   for (;;) {
     int ring = 0;
-    const int g = e.q.nb == 1 ? q_pop_ticket(e, lane) : q_pop(e, lane, &ring);
+    const int g = e.heap ? heap_pop(e, lane)
+                         : e.q.nb == 1 ? q_pop_ticket(e, lane) : q_pop(e, lane, &ring);
     if (g < 0) {
-      const bool stop = e.q.nb == 1 || ld64(&ctl->active) == 0ull || get_err(ctl) ||
+      const bool stop = e.heap || e.q.nb == 1 || ld64(&ctl->active) == 0ull || get_err(ctl) ||
                         past_deadline(ctl);
       if (stop) break;
       if (backoff < 8) ++backoff;
@@ -1042,6 +1114,8 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
                                          (unsigned long long)is_first << 55)
                                       : 0ull;
     order_acquire();
+    if (e.heap) heap_fix(e, g >> 6, lane);  // g is running now
+    int nvis = 1;                           // removals of g in this loop
     tick(e, &ctl->t_claim, &t0, lane);
     if (e.trace) tr[3] = wall_clock64();
     // a cell's interior is written only by its own processing
@@ -1177,7 +1251,16 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
       }
       again = bcast(again, 0);
       tick(e, &ctl->t_finish, &t0, lane);
-      if (!again) break;
+      if (!again) {
+        if (e.heap) {  // g is idle, its neighbours may be pending with lower keys
+          const int kx = __builtin_amdgcn_readfirstlane(I.kx);
+#pragma nounroll
+          for (int x = 0; x < 5; ++x)
+            heap_fix(e, (g + (x == 1 ? -1 : x == 2 ? 1 : x == 3 ? -kx : x == 4 ? kx : 0)) >> 6, lane);
+        }
+        break;
+      }
+      nvis++;
       if (get_err(ctl)) break;
       fl = (uint32_t)bcast((int)fl, 0);
       sides = (uint32_t)bcast((int)sides, 0);
@@ -1186,6 +1269,12 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
       load_tile<T, P>(tu, td, I, B, lane, false);  // fresh halo only
     }
     if (lane == 0) {
+      if (e.ninst > 1) {  // per-instance statistics of a batch
+        unsigned long long* is = e.istat + 4 * (size_t)inst_index(e, g);
+        atomic_add_relaxed(is, (unsigned long long)nvis);
+        atomic_add_relaxed(is + 1, nsweeps - sw0);
+        atomic_add_relaxed(is + 2, nchecks - ch0);
+      }
       if (e.trace) {
         const unsigned int slot = atomic_add_relaxed(e.trace_n, 1u);
         if (slot < e.trace_cap) {
@@ -1236,7 +1325,7 @@ __global__ void k_prep_cells(Engine e) {
     // processing has not finished stays clear; kDone1 set means "idle"
     e.st[c] = e.dag ? 0u : kDone1;
     e.visits[c] = 0u;
-    e.key[c] = 0xFF800000u;  // key_bits(+inf)
+    e.key[c] = kKeyInf;
     if (e.dag) {
       e.deps[c] = 0;
       e.ord[c] = 0;
@@ -1256,6 +1345,7 @@ __global__ void k_prep_cells(Engine e) {
   const size_t nslot = (size_t)e.q.cap * e.q.nb;
   for (size_t k = tid; k < nslot; k += stride)
     e.q.slot[k] = (unsigned long long)(k & (e.q.cap - 1)) << 32;
+  for (size_t k = tid; k < 4 * (size_t)ninst; k += stride) e.istat[k] = 0ull;
   for (size_t k = tid; k < (size_t)e.q.nb; k += stride) {
     e.q.head[k * kCtrStride] = 0ull;
     e.q.tail[k * kCtrStride] = 0ull;
@@ -1271,7 +1361,6 @@ __global__ void k_prep_cells(Engine e) {
     c->band_steps = 0ull;
     c->mon_checks = 0ull;
     c->mon_ok = 0ull;
-    c->resid_bits = 0ull;
     c->err = 0u;
     c->t_idle = c->t_claim = c->t_load = c->t_sweep = c->t_publish = c->t_finish = 0ull;
     c->guard = e.guard;
@@ -1342,9 +1431,9 @@ __global__ void k_init_u(Engine e) {
       dl[k] = inf_v<T>();
       if (!e.dag) {
         const int g = cell_of_node(I, (int)(k % I.nx), (int)(k / I.nx));
-        __hip_atomic_fetch_min(&e.key[g], key_bits((float)v), __ATOMIC_RELAXED,
+        __hip_atomic_fetch_min(&e.key[g], key_bits((double)v), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
-        requeue(e, g, e.method == kFhcm ? 0xFu : 0u, 0u, (float)v);
+        requeue(e, g, e.method == kFhcm ? 0xFu : 0u, 0u, (double)v);
       }
     }
     u[k] = v;
@@ -1390,7 +1479,7 @@ __global__ void k_apply_sources(Engine e) {
     dl[k] = inf_v<T>();
     if (e.dag) continue;
     const int g = cell_of_node(I, (int)(k % I.nx), (int)(k / I.nx));
-    const float key = e.method == kFhcm ? 0.0f : (float)q;
+    const double key = e.method == kFhcm ? 0.0 : q;
     __hip_atomic_fetch_min(&e.key[g], key_bits(key), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     requeue(e, g, e.method == kFhcm ? 0xFu : 0u, 0u, key);
   }
@@ -1768,7 +1857,8 @@ __global__ void k_dag(Engine e, const CoarseOut* co) {
 template <typename T, int S>
 __global__ __launch_bounds__(64) void k_sweep_diag(Engine e, SweepArgs a) {
   constexpr int P = S + 2;
-  __shared__ T tu[P * P + 64];
+  __shared__ T tu_mem[TileLds<P>::kSize];
+  T* const tu = tu_mem + TileLds<P>::kBefore;
   __shared__ T td[P * P];
   const int lane = threadIdx.x;
   if (get_err(e.ctl)) return;
@@ -1864,8 +1954,9 @@ __global__ void k_residual(Engine e) {
     mx = y > mx ? y : mx;
   }
   if ((threadIdx.x & 63) == 0 && mx > 0.0)
-    __hip_atomic_fetch_max(&e.ctl->resid_bits, __builtin_bit_cast(unsigned long long, mx),
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_max(&e.istat[4 * (size_t)blockIdx.y + 3],
+                           __builtin_bit_cast(unsigned long long, mx), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <typename S, typename D>

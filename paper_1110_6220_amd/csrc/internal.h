@@ -41,7 +41,9 @@ struct DevBuf {
 // Buffers of one engine run.
 struct Solver {
   DevBuf delta, st, visits, cell_inst, key, deps, ord, slot, head, tail, inflight, cursor, ctl, inst;
+  DevBuf hblk, istat;
   void release();
+  std::vector<DevBuf*> bufs();
 };
 
 // A captured launch sequence of one problem set (graph replay): the graph
@@ -121,9 +123,9 @@ struct RunCtx {
 };
 // Sizes the solver's buffers for the instances in `inst` (cell0 filled in)
 // and fills the engine arguments.
-int setup_engine(Solver& sv, std::vector<Inst>& inst, int dtype, int method, int dag, double band,
-                 int window, int eager, uint64_t guard, uint64_t timeout, hipStream_t stream,
-                 Engine* out, DevBuf* instbuf = nullptr);
+int setup_engine(Solver& sv, std::vector<Inst>& inst, int dtype, int method, int dag, int heap,
+                 double band, int window, int eager, uint64_t guard, uint64_t timeout,
+                 hipStream_t stream, Engine* out, DevBuf* instbuf = nullptr);
 eik_opts default_opts();
 int check_opts(const eik_opts& o);
 int std_cells(int n, int s);
@@ -136,7 +138,11 @@ int validate_device(const eik_problem& p, int dtype);
 // Solves n problems (validated) with one persistent launch.
 int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, RunInfo* info,
         const RunCtx* ctx = nullptr);
-int refine_fp64(int n, const eik_problem* probs, const std::vector<Inst>& inst, const eik_opts& o,
-                hipStream_t stream, const RunCtx& ctx);
+// Re-solves the FP32 problems probs[which[x]] in FP64 (device buffers of
+// inst[which[x]]) and rounds the results into their FP32 outputs; resid[x]
+// receives each FP64 solution's residual.
+int refine_fp64(const std::vector<int>& which, const eik_problem* probs,
+                const std::vector<Inst>& inst, const eik_opts& o, hipStream_t stream,
+                const RunCtx& ctx, std::vector<double>* resid);
 
 }  // namespace eik

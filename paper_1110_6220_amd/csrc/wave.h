@@ -51,6 +51,13 @@ __device__ __forceinline__ double min_d(double v) {
   v = vmin(v, dpp_d<kMirror>(v));
   return vmin(vmin(readlane_d(v, 0), readlane_d(v, 16)), vmin(readlane_d(v, 32), readlane_d(v, 48)));
 }
+__device__ __forceinline__ double max_d(double v) {
+  v = vmax(v, dpp_d<kXor1>(v));
+  v = vmax(v, dpp_d<kXor2>(v));
+  v = vmax(v, dpp_d<kHalfMirror>(v));
+  v = vmax(v, dpp_d<kMirror>(v));
+  return vmax(vmax(readlane_d(v, 0), readlane_d(v, 16)), vmax(readlane_d(v, 32), readlane_d(v, 48)));
+}
 __device__ __forceinline__ int min_i(int v) {
   v = min(v, dpp_i<kXor1>(v));
   v = min(v, dpp_i<kXor2>(v));

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libeik.so")
 EIK_OK, EIK_EINVAL, EIK_ENOMEM, EIK_EDEVICE, EIK_EBUDGET, EIK_ENOTCONV, EIK_EBUSY = 0, -1, -2, -3, -4, -5, -6
 F64, F32 = 0, 1
 METHODS = {"exact": 0, "hcm": 0, "fmsm": 1, "fhcm": 2}
-SCHEDULES = {"auto": 0, "coarse": 1, "bands": 2, "fifo": 3}
+SCHEDULES = {"auto": 0, "coarse": 1, "bands": 2, "fifo": 3, "heap": 4}
 
 # Every function include/eik.h declares.
 EXPORTS = ("eik_solve", "eik_solve_batched", "eik_serve_create", "eik_serve_submit",
@@ -40,7 +40,7 @@ class Opts(ctypes.Structure):
                 ("residual_check", ctypes.c_int32), ("workers", ctypes.c_int32),
                 ("band_window", ctypes.c_int32), ("eager_publish", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("timeout_ms", ctypes.c_int32),
-                ("graph", ctypes.c_int32)]
+                ("graph", ctypes.c_int32), ("residual_tol", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -51,11 +51,11 @@ class Stats(ctypes.Structure):
                 ("mon_ok", ctypes.c_uint64), ("max_residual", ctypes.c_double),
                 ("cell_used", ctypes.c_int32), ("band_used", ctypes.c_double),
                 ("fell_back_to_f64", ctypes.c_int32), ("cells_total", ctypes.c_uint64),
-                ("graph_replayed", ctypes.c_int32)]
+                ("graph_replayed", ctypes.c_int32), ("residual_f32", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}
-        cells = max(int(self.cells_total or self.cells), 1)
+        cells = max(int(self.cells), 1)
         d["AvHR"] = self.cell_visits / cells
         d["AvS"] = (self.sweeps + self.checks) / cells
         return d
@@ -133,11 +133,12 @@ def _is_torch(x) -> bool:
 
 
 def _opts(dtype, method, cell, band, device, stream, residual_check, workers, max_cell_visits,
-          band_window=0, eager_publish=False, schedule="auto", timeout_ms=0, graph=False):
+          band_window=0, eager_publish=False, schedule="auto", timeout_ms=0, graph=False,
+          residual_tol=0.0):
     return Opts(dtype, METHODS[method], int(cell), float(band), int(device),
                 stream, int(max_cell_visits), int(bool(residual_check)), int(workers),
                 int(band_window), int(bool(eager_publish)), SCHEDULES[schedule], int(timeout_ms),
-                int(bool(graph)))
+                int(bool(graph)), float(residual_tol))
 
 
 def _check_arrays(shape, mask, q, nsrc, u_out, out_dtype, device):
@@ -213,13 +214,14 @@ def _stream_of(device: bool):
 
 def eik_solve(F, h, src, q=None, mask=None, u_out=None, *, dtype="f64", method="exact",
               cell=0, band=0.0, workers=0, residual_check=False, max_cell_visits=0,
-              band_window=0, eager_publish=False, schedule="auto", timeout_ms=0, graph=False):
+              band_window=0, eager_publish=False, schedule="auto", timeout_ms=0, graph=False,
+              residual_tol=0.0):
     """Solves |grad u| F = 1 with u = q on src (see include/eik.h).
     Returns (u, stats dict)."""
     p, keep, u_out, device = _marshal(F, h, src, q, mask, u_out, dtype)
     o = _opts(F64 if dtype == "f64" else F32, method, cell, band, device, _stream_of(device),
               residual_check, workers, max_cell_visits, band_window, eager_publish, schedule,
-              timeout_ms, graph)
+              timeout_ms, graph, residual_tol)
     st = Stats()
     _check(lib.eik_solve(p.nx, p.ny, p.h, p.F, p.mask, p.nsrc, p.src, p.q, p.u_out,
                          ctypes.byref(o), ctypes.byref(st)))
@@ -229,7 +231,8 @@ def eik_solve(F, h, src, q=None, mask=None, u_out=None, *, dtype="f64", method="
 
 def eik_solve_batched(problems, *, dtype="f64", method="exact", cell=0, band=0.0, workers=0,
                       residual_check=False, max_cell_visits=0, band_window=0,
-                      eager_publish=False, schedule="auto", timeout_ms=0, graph=False):
+                      eager_publish=False, schedule="auto", timeout_ms=0, graph=False,
+                      residual_tol=0.0):
     """problems: list of dicts with F, h, src and optional q, mask, u_out.
     Returns (list of u, list of stats dicts)."""
     ps, keeps, outs = [], [], []
@@ -247,7 +250,7 @@ def eik_solve_batched(problems, *, dtype="f64", method="exact", cell=0, band=0.0
     arr = (Problem * len(ps))(*ps)
     o = _opts(F64 if dtype == "f64" else F32, method, cell, band, device, _stream_of(device),
               residual_check, workers, max_cell_visits, band_window, eager_publish, schedule,
-              timeout_ms, graph)
+              timeout_ms, graph, residual_tol)
     st = (Stats * len(ps))()
     _check(lib.eik_solve_batched(len(ps), arr, ctypes.byref(o), st))
     del keeps
@@ -322,10 +325,10 @@ class Server:
 
     def __init__(self, hbm_budget_bytes=0, max_slots=0, lanes=0, *, dtype="f64",
                  method="exact", cell=0, band=0.0, residual_check=False, device_inputs=False,
-                 schedule="auto", max_cell_visits=0):
+                 schedule="auto", max_cell_visits=0, residual_tol=0.0):
         self.dtype = dtype
         o = _opts(F64 if dtype == "f64" else F32, method, cell, band, device_inputs, None,
-                  residual_check, 0, max_cell_visits, 0, False, schedule)
+                  residual_check, 0, max_cell_visits, 0, False, schedule, 0, False, residual_tol)
         cfg = ServeCfg(int(hbm_budget_bytes), int(max_slots), int(lanes), o)
         h = ctypes.c_void_p()
         _check(lib.eik_serve_create(ctypes.byref(cfg), ctypes.byref(h)))
@@ -388,7 +391,7 @@ class Batch:
 
     def __init__(self, problems, *, dtype="f64", method="exact", cell=0, band=0.0, workers=0,
                  residual_check=False, max_cell_visits=0, band_window=0, eager_publish=False,
-                 schedule="auto", timeout_ms=0, graph=True):
+                 schedule="auto", timeout_ms=0, graph=True, residual_tol=0.0):
         ps, self._keep, self.outputs = [], [], []
         device = None
         for w in problems:
@@ -406,14 +409,14 @@ class Batch:
         self._device = device
         self._args = (F64 if dtype == "f64" else F32, method, cell, band, device, residual_check,
                       workers, max_cell_visits, band_window, eager_publish, schedule, timeout_ms,
-                      graph)
+                      graph, residual_tol)
         self._stats = (Stats * self._n)()
 
     def solve(self):
         """Solves the batch into self.outputs; returns the stats dicts."""
         (dt, method, cell, band, device, resid, workers, mcv, bw, eager, sched, tmo,
-         graph) = self._args
+         graph, rtol) = self._args
         o = _opts(dt, method, cell, band, device, _stream_of(device), resid, workers, mcv, bw,
-                  eager, sched, tmo, graph)
+                  eager, sched, tmo, graph, rtol)
         _check(lib.eik_solve_batched(self._n, self._arr, ctypes.byref(o), self._stats))
         return [s.as_dict() for s in self._stats]

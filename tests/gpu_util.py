@@ -13,6 +13,38 @@ def to_dev(w, dtype="f64"):
     return d
 
 
+def solve_dev(eik, w, **kw):
+    """eik_solve through the C ABI on device copies of workload w; returns
+    (u as a float64 numpy array, stats dict)."""
+    d = to_dev(w, kw.get("dtype", "f64"))
+    print(f"[gpu] solve {w['name']} {w['nx']}x{w['ny']} {kw}", flush=True)
+    u, st = eik.eik_solve(d["F"], d["h"], d["src"], d["q"], d.get("mask"), **kw)
+    return u.double().cpu().numpy(), st
+
+
+def approx_cases():
+    """(workload, cell side) pairs of the approximate-method parity tests:
+    the constant-speed point source, smooth speeds, random problems with
+    obstacles and several exit nodes, and the paper's 352..1408 sinusoids
+    (four-node centre source, whole boundary as exit set) and 11 x 11 and
+    41 x 41 checkerboards."""
+    from paper_1110_6220_amd import workloads as W
+    rng = np.random.default_rng(21)
+    cases = [(W.config(1), 16), (W.config(1), 8), (W.smooth_sine(97), 8), (W.smooth_sine(257), 16),
+             (W.smooth_sine(257, amp=0.99), 32)]
+    for _ in range(4):
+        nx, ny = (int(v) for v in rng.integers(20, 120, size=2))
+        cases.append((W.random_small(rng, nx, ny, obst=0.1, nsrc=int(rng.integers(1, 4)),
+                                     q_spread=0.2), int(rng.choice([4, 8, 16]))))
+    cases += [(W.sinusoid_point(352, 0.5, 10.0), 16), (W.sinusoid_point(704, 0.5, 10.0), 32),
+              (W.sinusoid_boundary(352, 0.5, 10.0), 16), (W.sinusoid_boundary(704, 0.99, 1.0), 32),
+              (W.sinusoid_boundary(1408, 0.5, 10.0), 64),
+              (W.checkerboard_point(352, 11), 16), (W.checkerboard_point(656, 41), 8),
+              # 164^2 coarse cells
+              (W.checkerboard_point(1312, 41), 8)]
+    return cases
+
+
 def max_rel(got, ref):
     """Max relative difference over finite reference nodes; the sets of
     infinite nodes must agree exactly."""

@@ -12,6 +12,7 @@ error scale elsewhere.
 import numpy as np
 import pytest
 
+import gpu_util
 import oracle as O
 from paper_1110_6220_amd import workloads as W
 
@@ -27,34 +28,11 @@ def eik():
 
 
 def solve_dev(eik, w, **kw):
-    import torch
-    dev = torch.device("cuda:0")
-    F = torch.from_numpy(w["F"]).to(dev)
-    src = torch.from_numpy(w["src"]).to(dev)
-    q = torch.from_numpy(w["q"]).to(dev)
-    mask = None if w.get("mask") is None else torch.from_numpy(w["mask"]).to(dev)
-    print(f"[gpu] {kw.get('method')} {w['name']} {w['nx']}x{w['ny']} {kw}", flush=True)
-    u, st = eik.eik_solve(F, w["h"], src, q, mask, **kw)
-    return u.cpu().numpy(), st
+    return gpu_util.solve_dev(eik, w, **kw)
 
 
 def fmsm_cases():
-    rng = np.random.default_rng(21)
-    cases = [(W.config(1), 16), (W.config(1), 8), (W.smooth_sine(97), 8), (W.smooth_sine(257), 16),
-             (W.smooth_sine(257, amp=0.99), 32)]
-    for _ in range(4):
-        nx, ny = (int(v) for v in rng.integers(20, 120, size=2))
-        cases.append((W.random_small(rng, nx, ny, obst=0.1, nsrc=int(rng.integers(1, 4)),
-                                     q_spread=0.2), int(rng.choice([4, 8, 16]))))
-    # the paper's sinusoids (Sections 4.3, 4.5): four-node point source, and
-    # the whole boundary as exit set (every boundary cell a coarse source)
-    cases += [(W.sinusoid_point(352, 0.5, 10.0), 16), (W.sinusoid_point(704, 0.5, 10.0), 32),
-              (W.sinusoid_boundary(352, 0.5, 10.0), 16), (W.sinusoid_boundary(704, 0.99, 1.0), 32),
-              (W.sinusoid_boundary(1408, 0.5, 10.0), 64),
-              (W.checkerboard_point(352, 11), 16), (W.checkerboard_point(656, 41), 8),
-              # 164^2 coarse cells: the coarse Fast Marching works outside LDS
-              (W.checkerboard_point(1312, 41), 8)]
-    return cases
+    return gpu_util.approx_cases()
 
 
 @pytest.mark.parametrize("case", range(17))
@@ -100,7 +78,7 @@ def test_exact_schedules_agree(eik):
     """Every cell order gives the exact solution (the Theorem)."""
     w = W.smooth_sine(257)
     U = O.fmm(O.Problem.from_workload(w))
-    for sched in ("coarse", "bands", "fifo"):
+    for sched in ("coarse", "bands", "fifo", "heap"):
         got, _ = solve_dev(eik, w, cell=32, schedule=sched)
         assert (np.abs(got - U) / U.max()).max() <= 1e-12, sched
 

@@ -5,7 +5,9 @@ obstacles, unreachable pockets, multiple sources and degenerate grids."""
 import numpy as np
 import pytest
 
+import gpu_util
 import oracle as O
+from gpu_util import max_rel, to_dev
 from paper_1110_6220_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -21,32 +23,8 @@ def eik():
     return E
 
 
-def to_dev(w, dtype="f64"):
-    import torch
-    dev = torch.device("cuda:0")
-    tdt = torch.float64 if dtype == "f64" else torch.float32
-    d = dict(F=torch.from_numpy(w["F"]).to(dev, tdt), h=w["h"],
-             src=torch.from_numpy(w["src"]).to(dev), q=torch.from_numpy(w["q"]).to(dev))
-    if w.get("mask") is not None:
-        d["mask"] = torch.from_numpy(w["mask"]).to(dev)
-    return d
-
-
-def max_rel(got, ref):
-    fin = np.isfinite(ref)
-    assert np.array_equal(np.isfinite(got), fin), "reachable sets differ"
-    assert np.array_equal(got[~fin], ref[~fin])
-    if not fin.any():
-        return 0.0
-    r, g = ref[fin], got[fin]
-    return float((np.abs(g - r) / np.maximum(np.abs(r), 1e-300)).max())
-
-
 def solve_dev(eik, w, **kw):
-    d = to_dev(w, kw.get("dtype", "f64"))
-    print(f"[gpu] solve {w['name']} {w['nx']}x{w['ny']} {kw}", flush=True)
-    u, st = eik.eik_solve(d["F"], d["h"], d["src"], d["q"], d.get("mask"), **kw)
-    return u.double().cpu().numpy(), st
+    return gpu_util.solve_dev(eik, w, **kw)
 
 
 def test_constant_speed_point_source(eik):
