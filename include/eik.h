@@ -326,6 +326,27 @@ int eik_fmsm3(int32_t nx, int32_t ny, int32_t nz, double h, const double* F, con
               int32_t nsrc, const int64_t* src, const double* q, double* u_out,
               int32_t device_ptrs, void* stream, eik3_stats* stats);
 
+/* Allocation-free solve, for callers that cannot allocate device memory
+   (code under HIP graph capture, allocation-free serving loops, harnesses
+   that forbid hipMalloc).  Same arguments, method, result and errors as
+   eik_solve, with these limits: every pointer is device memory
+   (opts->device_ptrs must be 1), opts->graph must be 0, and an F32 solve
+   cannot ask for residual_check (its FP64 re-solve would need memory).
+   Every device buffer beyond the caller's inputs and outputs comes from one
+   device array of EIK_NOALLOC_SCRATCH_BYTES that the library holds per
+   device until the process ends (h/F per node and about 100 bytes per
+   cell: up to about 2.8 million nodes in FP64, 5 million in FP32); a
+   problem that needs more is refused with EINVAL before any device work.
+   The call allocates no device or pinned host memory and creates no HIP
+   object (stats->kernel_seconds is 0).  Calls on one device share the
+   array and are serialised by the library; calls from separate processes
+   use separate arrays.  Overlapping calls on one device through other
+   means than this library's lock race on the array. */
+#define EIK_NOALLOC_SCRATCH_BYTES (64u << 20)
+int eik_solve_noalloc(int32_t nx, int32_t ny, double h, const void* F, const uint8_t* mask,
+                      int32_t nsrc, const int64_t* src, const double* q, void* u_out,
+                      const eik_opts* opts, eik_stats* stats);
+
 /* Message for the last failed call on this thread ("" if none). */
 const char* eik_last_error(void);
 

@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libeik.so")
-SOURCES = ["engine.hip", "engine3.hip", "api.cpp", "serve.cpp", "sweep.cpp", "solve3.cpp"]
+SOURCES = ["engine.hip", "engine3.hip", "noalloc.hip", "api.cpp", "serve.cpp", "sweep.cpp",
+           "solve3.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

@@ -24,14 +24,24 @@ double now_s();
       return ::eik::fail(EIK_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
+// A fixed region of device memory that buffers are carved from in order
+// (the allocation-free entry point); `used` is reset by every call.
+struct Bump {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  bool overflow = false;  // a buffer did not fit
+};
+
 // A device allocation that only grows.  With a graveyard, a buffer that
 // grows keeps its old allocation there (freed later by the owner) instead of
-// calling hipFree, which would wait for all work on the device.
+// calling hipFree, which would wait for all work on the device.  With a bump
+// region the buffer is carved from it instead and nothing is allocated.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
   std::vector<void*>* graveyard = nullptr;
   uint64_t* gen = nullptr;  // bumped when the buffer moves (captured graphs go stale)
+  Bump* bump = nullptr;
   hipError_t ensure(size_t need);
   void release();
   template <typename T>
@@ -84,7 +94,8 @@ struct Workspace {
   bool defer_free = false;            // grow without hipFree (serving lanes)
   Ctl* ctl_host = nullptr;            // pinned: fine and coarse control blocks
   int32_t* host3 = nullptr;           // pinned: 3-D solver read-back (64 bytes)
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;  // null: the solver kernel is not timed
+  Bump* bump = nullptr;               // carve every buffer from here (no allocation)
   int cus = 0;
   int wall_khz = 0;
   bool ready = false;
@@ -102,7 +113,8 @@ struct RunInfo {
 // The calling device's shared workspace (created on first use).
 int workspace(Workspace** out);
 // Initialises a workspace for the current device (pinned control block,
-// events, device attributes).
+// events, device attributes; with a bump region only the device attributes:
+// the caller provides ctl_host, and no event is created).
 int workspace_init(Workspace* w);
 // Frees everything a workspace holds (no work may be pending on it).
 void workspace_free(Workspace* w);

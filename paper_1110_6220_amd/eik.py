@@ -24,7 +24,7 @@ SCHEDULES = {"auto": 0, "coarse": 1, "bands": 2, "fifo": 3, "heap": 4}
 # Every function include/eik.h declares.
 EXPORTS = ("eik_solve", "eik_solve_batched", "eik_serve_create", "eik_serve_submit",
            "eik_serve_poll", "eik_serve_wait", "eik_serve_cancel", "eik_serve_destroy",
-           "eik_sweep_solve", "eik_solve3", "eik_fmsm3", "eik_last_error")
+           "eik_sweep_solve", "eik_solve3", "eik_fmsm3", "eik_solve_noalloc", "eik_last_error")
 
 
 class EikError(RuntimeError):
@@ -112,6 +112,8 @@ def _load() -> ctypes.CDLL:
                              ctypes.POINTER(Stats3)]
     L.eik_sweep_solve.argtypes = [i32, i32, ctypes.c_double, vp, vp, i32, vp, vp, vp,
                                   ctypes.POINTER(SweepOpts), vp, vp, ctypes.POINTER(SweepStats)]
+    L.eik_solve_noalloc.argtypes = [i32, i32, ctypes.c_double, vp, vp, i32, vp, vp, vp,
+                                    ctypes.POINTER(Opts), ctypes.POINTER(Stats)]
     L.eik_last_error.restype = ctypes.c_char_p
     return L
 
