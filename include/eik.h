@@ -326,6 +326,15 @@ int eik_fmsm3(int32_t nx, int32_t ny, int32_t nz, double h, const double* F, con
               int32_t nsrc, const int64_t* src, const double* q, double* u_out,
               int32_t device_ptrs, void* stream, eik3_stats* stats);
 
+/* Measurement aid: the latency of one dependent step of the cell sweep.
+   One wave alone on the device sweeps one side x side tile held in LDS
+   `sweeps` times with the solver's own sweep (anti-diagonal steps, the local
+   update of Section 2, dtype storage with the FP64 two-sided branch) and
+   *seconds receives the wall time per anti-diagonal step: t_dep of the span
+   bound D t_dep of a solve whose longest chain of dependent updates has D
+   steps.  side: 32 or 64.  Errors: EINVAL, EDEVICE. */
+int eik_probe_step_latency(int32_t dtype, int32_t side, int32_t sweeps, double* seconds);
+
 /* Allocation-free solve, for callers that cannot allocate device memory
    (code under HIP graph capture, allocation-free serving loops, harnesses
    that forbid hipMalloc).  Same arguments, method, result and errors as

@@ -13,6 +13,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/eik.h"
@@ -84,8 +85,8 @@ void DevBuf::release() {
 }
 
 std::vector<DevBuf*> Solver::bufs() {
-  return {&delta, &st,   &visits, &cell_inst, &key, &deps, &ord,  &slot,
-          &head,  &tail, &inflight, &cursor,  &ctl, &inst, &hblk, &istat};
+  return {&delta, &st,   &visits,   &cell_inst, &key, &deps, &ord,  &slot,  &head,
+          &tail,  &inflight, &cursor, &ctl,      &inst, &hblk, &istat, &iact};
 }
 
 void Solver::release() {
@@ -353,6 +354,7 @@ int setup_engine(Solver& sv, std::vector<Inst>& inst, int dtype, int method, int
   HIP_TRY(sv.visits.ensure(J * sizeof(uint32_t)));
   HIP_TRY(sv.key.ensure(J * sizeof(unsigned long long)));
   HIP_TRY(sv.istat.ensure(4 * (size_t)n * sizeof(unsigned long long)));
+  HIP_TRY(sv.iact.ensure((size_t)n * sizeof(unsigned long long)));
   HIP_TRY(sv.hblk.ensure(heap ? ((J + 63) / 64) * sizeof(unsigned long long) : 8));
   HIP_TRY(sv.cell_inst.ensure(n > 1 ? J * sizeof(int32_t) : 4));
   HIP_TRY(sv.deps.ensure(dag ? J * sizeof(int32_t) : 4));
@@ -382,6 +384,8 @@ int setup_engine(Solver& sv, std::vector<Inst>& inst, int dtype, int method, int
   e.heap = heap;
   e.hblk = sv.hblk.as<unsigned long long>();
   e.istat = sv.istat.as<unsigned long long>();
+  e.iact = sv.iact.as<unsigned long long>();
+  e.idone = nullptr;
   e.deps = sv.deps.as<int32_t>();
   e.ord = sv.ord.as<uint8_t>();
   e.q.slot = sv.slot.as<unsigned long long>();
@@ -425,6 +429,12 @@ static int default_workers(const Workspace* ws, int64_t J, int tile, int dtype, 
 // ---------------------------------------------------------------------------
 
 constexpr unsigned kTraceCap = 1u << 20;  // trace records (EIK_TRACE)
+// Cell side of the cell engine when it solves a coarse grid (more than
+// kCoarseJacobiMax coarse cells) for the order of the exact method.
+#ifndef EIK_COARSE_ENGINE_CELL
+#define EIK_COARSE_ENGINE_CELL 64
+#endif
+constexpr int kCoarseEngineCell = EIK_COARSE_ENGINE_CELL;
 constexpr size_t kMaxPlans = 8;           // captured graphs kept per workspace
 
 static int complete(Workspace* ws, int n, const eik_problem* probs, const eik_opts& o,
@@ -494,7 +504,7 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
 
   // graph replay: a problem set seen before (same buffers, sizes and options)
   // runs its captured launch sequence
-  const bool use_graph = o.graph && dev && !g_trace && !g_profile && !ws->bump;
+  const bool use_graph = o.graph && dev && !g_trace && !g_profile && !ws->bump && !ctx.idone;
   const uint64_t key = use_graph ? plan_key(n, probs, o, ctx) : 0;
   ws->uses++;
   if (use_graph) {
@@ -649,6 +659,7 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
                          o.eager_publish, o.max_cell_visits, timeout, stream, &e,
                          np ? &np->inst : nullptr)))
     return rc;
+  e.idone = ctx.idone;
   const int64_t J = e.ncells;
   const int tile = tile_for(extent);
   if (extent > tile) return fail(EIK_EINVAL, "internal: a cell of %d nodes exceeds the %d-node tile", extent, tile);
@@ -729,7 +740,7 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
       C.nx = inst[k].kx;
       C.ny = inst[k].ky;
       Tiling ct;
-      make_tiling(C.nx, C.ny, 64, EIK_EXACT, &ct);
+      make_tiling(C.nx, C.ny, kCoarseEngineCell, EIK_EXACT, &ct);
       C.s = ct.s;
       C.kx = ct.kx;
       C.ky = ct.ky;
@@ -836,6 +847,16 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
     }
     ws->plans.push_back(std::move(np));
   }
+  if (ctx.poll) {  // early completion: let the caller take finished problems
+    for (;;) {
+      const hipError_t q = hipStreamQuery(stream);
+      if (q == hipSuccess) break;
+      if (q != hipErrorNotReady) return fail(EIK_EDEVICE, "solve failed: %s", hipGetErrorString(q));
+      ctx.poll(e, inst);
+      std::this_thread::sleep_for(std::chrono::microseconds(50));
+    }
+    ctx.poll(e, inst);
+  }
   HIP_TRY(hipStreamSynchronize(stream));
   return complete(ws, n, probs, o, ctx, inst, J, band, coarse_engine, want_resid, e.istat, stream,
                   t0, stats, info, lk, false);
@@ -882,7 +903,7 @@ static int complete(Workspace* ws, int n, const eik_problem* probs, const eik_op
     std::vector<int> which;
     for (int k = 0; k < n; ++k) {
       resid32[k] = resid[k];
-      if (!(resid[k] <= tol)) which.push_back(k);
+      if (!(resid[k] <= tol) && !(ctx.detached && ctx.detached[k])) which.push_back(k);
     }
     if (!which.empty()) {
       std::vector<double> r64;
@@ -1052,6 +1073,25 @@ int eik_solve_batched(int32_t n, const eik_problem* probs, const eik_opts* opts,
       return fail(rc, "problem %d: %s", k, g_err.c_str());
   }
   return run(n, probs, o, stats, nullptr);
+}
+
+int eik_probe_step_latency(int32_t dtype, int32_t side, int32_t sweeps, double* seconds) {
+  g_err.clear();
+  if ((dtype != EIK_F64 && dtype != EIK_F32) || (side != 32 && side != 64) || sweeps < 1 || !seconds)
+    return fail(EIK_EINVAL, "dtype F64/F32, side 32 or 64, sweeps >= 1 and an output are required");
+  Workspace* ws = nullptr;
+  int rc = workspace(&ws);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(ws->mu);
+  HIP_TRY(ws->sweep_stat.ensure(64));
+  unsigned long long* t = ws->sweep_stat.as<unsigned long long>();
+  HIP_TRY(launch_probe_sweep(dtype, side, 1, t, nullptr));  // warm-up
+  HIP_TRY(launch_probe_sweep(dtype, side, sweeps, t, nullptr));
+  unsigned long long ticks = 0;
+  HIP_TRY(hipMemcpy(&ticks, t, sizeof ticks, hipMemcpyDeviceToHost));
+  ticks &= ~(1ull << 63);
+  *seconds = (double)ticks / ((double)ws->wall_khz * 1e3) / ((double)sweeps * (2 * side - 1));
+  return EIK_OK;
 }
 
 const char* eik_last_error(void) { return g_err.c_str(); }

@@ -120,6 +120,11 @@ struct Engine {
   // per instance k: istat[4k] visits, [4k+1] productive sweeps, [4k+2]
   // no-change sweeps (batches only), [4k+3] bits of the FP64 residual
   unsigned long long* istat;
+  // early completion (null when off): iact[k] = cells of instance k waiting,
+  // queued or running; when it drops to zero the instance is solved and
+  // idone[k] (host-visible memory) is set to 1 with system-scope release
+  unsigned long long* iact;
+  unsigned int* idone;
   int32_t eager;         // publish after every productive sweep
   int32_t profile;       // accumulate phase timers in Ctl
   // diagnostic trace (null when off): per cell the wall clock when it was
@@ -157,7 +162,9 @@ hipError_t launch_prepare(const Engine& e, int64_t max_nodes, hipStream_t stream
 hipError_t launch_solve(const Engine& e, int workers, int tile, hipStream_t stream);
 // Solver waves that fit on one compute unit at once (registers and LDS).
 int solve_waves_per_cu(int dtype, int method, int tile);
-hipError_t launch_residual(const Engine& e, int64_t max_nodes, hipStream_t stream);
+// FP64 residual of instances [inst0, inst0 + count) (count 0: all) into istat
+hipError_t launch_residual(const Engine& e, int64_t max_nodes, hipStream_t stream, int inst0 = 0,
+                           int count = 0);
 // coarse speeds, masks and exit costs of every fine cell (cells of instance k
 // at co[k].*[cell - cell0])
 hipError_t launch_coarse_inputs(const Engine& fine, const CoarseOut* co_dev, int max_cells,
@@ -203,6 +210,10 @@ struct WallIn {
 };
 hipError_t launch_wall_density(const WallIn* in_dev, int n, int64_t max_nodes,
                                unsigned long long* counts, hipStream_t stream);
+// one wave sweeping one tile `sweeps` times: wall-clock ticks into ticks[0]
+// (bits 0..62; side 32 or 64)
+hipError_t launch_probe_sweep(int dtype, int side, int sweeps, unsigned long long* ticks,
+                              hipStream_t stream);
 // element-wise copies between precisions (FP32 results re-solved in FP64)
 hipError_t launch_convert(const void* src, int src_dtype, void* dst, int dst_dtype, int64_t n,
                           hipStream_t stream);

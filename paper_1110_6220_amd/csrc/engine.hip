@@ -428,7 +428,7 @@ __device__ __forceinline__ unsigned long long pending_key(const Engine& e, int c
 }
 
 // Recomputes the minimum of block b (wave-cooperative).
-__device__ __noinline__ void heap_fix(const Engine& e, int b, int lane) {
+__device__ __forceinline__ void heap_fix(const Engine& e, int b, int lane) {
   if (b < 0 || b >= ((e.ncells + 63) >> 6)) return;
   const unsigned long long m = wave_min_u64(pending_key(e, b * 64 + lane));
   if (lane == 0) st_coh(&e.hblk[b], m);
@@ -437,7 +437,7 @@ __device__ __noinline__ void heap_fix(const Engine& e, int b, int lane) {
 // The pending cell with the smallest (key, index), or -1 (wave-uniform).
 // Blocks are scanned in index order, so among equal minima the lowest block
 // -- which holds the lowest cell index with that key -- wins.
-__device__ __noinline__ int heap_pop(const Engine& e, int lane) {
+__device__ __forceinline__ int heap_pop(const Engine& e, int lane) {
   const int nblk = (e.ncells + 63) >> 6;
   unsigned long long best = kKeyNone;
   int bb = 0x7fffffff;
@@ -458,6 +458,21 @@ __device__ __noinline__ int heap_pop(const Engine& e, int lane) {
   return blk * 64 + __builtin_ctzll(at);
 }
 
+// Per-instance counts of cells waiting, queued or running (early
+// completion): +1 when a cell of the instance becomes active, -1 when it
+// goes idle; the wave whose decrement empties the count publishes the
+// instance's completion to the host (its values were stored with
+// device-scope accesses before every decrement of the chain).
+__device__ __forceinline__ void inst_active_add(const Engine& e, int g) {
+  if (e.idone) atomic_add_relaxed(&e.iact[inst_index(e, g)], 1ull);
+}
+__device__ __forceinline__ void inst_active_done(const Engine& e, int g) {
+  if (!e.idone) return;
+  const int k = inst_index(e, g);
+  if (atomic_add_relaxed(&e.iact[k], ~0ull) == 1ull)
+    __hip_atomic_store(&e.idone[k], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // ----------------------------------------------------------------------------
 // cell state transitions (one lane)
 // ----------------------------------------------------------------------------
@@ -476,6 +491,7 @@ __device__ void requeue(const Engine& e, int g, uint32_t fl, uint32_t sides, dou
                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (!(old & (kPending | kRunning)) && (old & kDone1)) {
     atomic_add_relaxed(&e.ctl->active, 1ull);
+    inst_active_add(e, g);
     if (e.ready_at) e.ready_at[g] = wall_clock64();
     if (!e.heap) q_push(e, (uint32_t)g, key);
   }
@@ -1012,7 +1028,9 @@ struct TileLds {
   static constexpr int kSize = P + P * P + 64 + 1;
 };
 
-template <typename T, int S, int M, int NW>
+// HEAP: the heap schedule's single worker (a kernel of its own, so that the
+// other schedules carry none of its code).
+template <typename T, int S, int M, int NW, bool HEAP = false>
 __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
   constexpr int P = S + 2;
   __shared__ T tu_mem[TileLds<P>::kSize];
@@ -1066,14 +1084,14 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
   int backoff = 0;
   unsigned long long t0 = e.profile ? wall_clock64() : 0ull;
   unsigned long long nsweeps = 0, nchecks = 0;  // this wave's totals
-  if (e.heap)  // the only worker: block minima of the cells queued so far
+  if constexpr (HEAP)  // the only worker: block minima of the cells queued so far
     for (int b = 0; b < ((e.ncells + 63) >> 6); ++b) heap_fix(e, b, lane);
   for (;;) {
     int ring = 0;
-    const int g = e.heap ? heap_pop(e, lane)
-                         : e.q.nb == 1 ? q_pop_ticket(e, lane) : q_pop(e, lane, &ring);
+    const int g = HEAP ? heap_pop(e, lane)
+                       : e.q.nb == 1 ? q_pop_ticket(e, lane) : q_pop(e, lane, &ring);
     if (g < 0) {
-      const bool stop = e.heap || e.q.nb == 1 || ld64(&ctl->active) == 0ull || get_err(ctl) ||
+      const bool stop = HEAP || e.q.nb == 1 || ld64(&ctl->active) == 0ull || get_err(ctl) ||
                         past_deadline(ctl);
       if (stop) break;
       if (backoff < 8) ++backoff;
@@ -1114,7 +1132,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
                                          (unsigned long long)is_first << 55)
                                       : 0ull;
     order_acquire();
-    if (e.heap) heap_fix(e, g >> 6, lane);  // g is running now
+    if constexpr (HEAP) heap_fix(e, g >> 6, lane);  // g is running now
     int nvis = 1;                           // removals of g in this loop
     tick(e, &ctl->t_claim, &t0, lane);
     if (e.trace) tr[3] = wall_clock64();
@@ -1235,6 +1253,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
         if (idle) {
           if (M == kFmsm) st_coh(&e.st[g], kDone1);
           atomic_add_relaxed(&ctl->active, ~0ull);
+          inst_active_done(e, g);
           q_done(e, ring);
         } else {
           // re-requested while running: take it again at once
@@ -1252,7 +1271,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
       again = bcast(again, 0);
       tick(e, &ctl->t_finish, &t0, lane);
       if (!again) {
-        if (e.heap) {  // g is idle, its neighbours may be pending with lower keys
+        if constexpr (HEAP) {  // g is idle, its neighbours may be pending with lower keys
           const int kx = __builtin_amdgcn_readfirstlane(I.kx);
 #pragma nounroll
           for (int x = 0; x < 5; ++x)
@@ -1269,7 +1288,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
       load_tile<T, P>(tu, td, I, B, lane, false);  // fresh halo only
     }
     if (lane == 0) {
-      if (e.ninst > 1) {  // per-instance statistics of a batch
+      if (NW == 1 && e.ninst > 1) {  // per-instance statistics of a batch
         unsigned long long* is = e.istat + 4 * (size_t)inst_index(e, g);
         atomic_add_relaxed(is, (unsigned long long)nvis);
         atomic_add_relaxed(is + 1, nsweeps - sw0);
@@ -1346,6 +1365,8 @@ __global__ void k_prep_cells(Engine e) {
   for (size_t k = tid; k < nslot; k += stride)
     e.q.slot[k] = (unsigned long long)(k & (e.q.cap - 1)) << 32;
   for (size_t k = tid; k < 4 * (size_t)ninst; k += stride) e.istat[k] = 0ull;
+  if (e.idone)
+    for (size_t k = tid; k < (size_t)ninst; k += stride) e.iact[k] = 0ull;
   for (size_t k = tid; k < (size_t)e.q.nb; k += stride) {
     e.q.head[k * kCtrStride] = 0ull;
     e.q.tail[k * kCtrStride] = 0ull;
@@ -1845,6 +1866,7 @@ __global__ void k_dag(Engine e, const CoarseOut* co) {
     e.ord[g] = o;
     e.deps[g] = n;
     atomic_add_relaxed(&e.ctl->active, 1ull);
+    inst_active_add(e, g);
     if (n == 0 && !get_err(e.ctl)) release_first(e, g);
   }
 }
@@ -1924,8 +1946,9 @@ __global__ void k_sweep_seed(Engine e, uint8_t* dirty) {
 // Fixed-point residual max |T(u)_k - u_k| / u_k in FP64 over accessible,
 // non-exit nodes with finite u (inf where u is inf but T(u) is finite).
 template <typename T>
-__global__ void k_residual(Engine e) {
-  const Inst I = inst_at(e, blockIdx.y);
+__global__ void k_residual(Engine e, int inst0) {
+  const int ki = inst0 + (int)blockIdx.y;
+  const Inst I = inst_at(e, ki);
   const T* u = static_cast<const T*>(I.u);
   const T* F = static_cast<const T*>(I.F);
   const T* dl = static_cast<const T*>(I.delta);
@@ -1954,7 +1977,7 @@ __global__ void k_residual(Engine e) {
     mx = y > mx ? y : mx;
   }
   if ((threadIdx.x & 63) == 0 && mx > 0.0)
-    __hip_atomic_fetch_max(&e.istat[4 * (size_t)blockIdx.y + 3],
+    __hip_atomic_fetch_max(&e.istat[4 * (size_t)ki + 3],
                            __builtin_bit_cast(unsigned long long, mx), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -1966,11 +1989,52 @@ __global__ void k_convert(const S* src, D* dst, int64_t n) {
     dst[k] = (D)src[k];
 }
 
+// Latency of the sweep's dependent chain: one wave alone sweeps one S x S
+// tile in LDS `sweeps` times (direction SW; exit node at the south-west
+// corner, +inf elsewhere, so every sweep runs the same branch-free steps as
+// in the solver) and reports the wall-clock ticks of the loop.  One sweep is
+// 2S - 1 anti-diagonal steps, each one dependent local update per lane.
+template <typename T, int S>
+__global__ __launch_bounds__(64) void k_probe_sweep(int sweeps, unsigned long long* ticks) {
+  constexpr int P = S + 2;
+  __shared__ T tu_mem[TileLds<P>::kSize];
+  T* const tu = tu_mem + TileLds<P>::kBefore;
+  __shared__ T td[P * P];
+  const int lane = threadIdx.x;
+  for (int k = lane; k < P * P; k += 64) {
+    tu[k] = inf_v<T>();
+    td[k] = (T)(1.0 / S);
+  }
+  __syncthreads();
+  if (lane == 0) tu[P + 1] = (T)0;  // the exit node
+  __syncthreads();
+  const unsigned long long t0 = wall_clock64();
+  uint32_t acc = 0;
+  for (int r = 0; r < sweeps; ++r) acc += sweep_tile<T, P, false>(tu, td, S, S, 0, lane);
+  const unsigned long long t1 = wall_clock64();
+  if (lane == 0) ticks[0] = (t1 - t0) | ((unsigned long long)(acc & 1u) << 63);
+}
+
 }  // namespace
 
 // ----------------------------------------------------------------------------
 // launchers
 // ----------------------------------------------------------------------------
+
+hipError_t launch_probe_sweep(int dtype, int side, int sweeps, unsigned long long* ticks,
+                              hipStream_t stream) {
+  if (dtype == 0 && side == 64)
+    hipLaunchKernelGGL((k_probe_sweep<double, 64>), dim3(1), dim3(64), 0, stream, sweeps, ticks);
+  else if (dtype == 0 && side == 32)
+    hipLaunchKernelGGL((k_probe_sweep<double, 32>), dim3(1), dim3(64), 0, stream, sweeps, ticks);
+  else if (dtype == 1 && side == 64)
+    hipLaunchKernelGGL((k_probe_sweep<float, 64>), dim3(1), dim3(64), 0, stream, sweeps, ticks);
+  else if (dtype == 1 && side == 32)
+    hipLaunchKernelGGL((k_probe_sweep<float, 32>), dim3(1), dim3(64), 0, stream, sweeps, ticks);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
 
 static int grid_for(int64_t n, int block, int cap) {
   int64_t g = (n + block - 1) / block;
@@ -1994,15 +2058,18 @@ hipError_t launch_prepare(const Engine& e, int64_t max_nodes, hipStream_t stream
   return hipGetLastError();
 }
 
-template <typename T, int M, int NW>
+template <typename T, int M, int NW, bool HEAP = false>
 static void launch_solve_w(const Engine& e, dim3 g, int tile, hipStream_t stream) {
-  if (tile <= 16) hipLaunchKernelGGL((k_solve<T, 16, M, NW>), g, dim3(64 * NW), 0, stream, e);
-  else if (tile <= 32) hipLaunchKernelGGL((k_solve<T, 32, M, NW>), g, dim3(64 * NW), 0, stream, e);
-  else hipLaunchKernelGGL((k_solve<T, 64, M, NW>), g, dim3(64 * NW), 0, stream, e);
+  if (tile <= 16) hipLaunchKernelGGL((k_solve<T, 16, M, NW, HEAP>), g, dim3(64 * NW), 0, stream, e);
+  else if (tile <= 32) hipLaunchKernelGGL((k_solve<T, 32, M, NW, HEAP>), g, dim3(64 * NW), 0, stream, e);
+  else hipLaunchKernelGGL((k_solve<T, 64, M, NW, HEAP>), g, dim3(64 * NW), 0, stream, e);
 }
-// single problems: four waves per worker share the tile transfers
+// single problems: four waves per worker share the tile transfers; the heap
+// schedule: one single-wave worker
 template <typename T, int M>
 static void launch_solve_t(const Engine& e, dim3 g, int tile, hipStream_t stream) {
+  if constexpr (M != kFmsm)
+    if (e.heap) return launch_solve_w<T, M, 1, true>(e, g, tile, stream);
   if (e.ninst == 1) launch_solve_w<T, M, kSolveWaves1>(e, g, tile, stream);
   else launch_solve_w<T, M, 1>(e, g, tile, stream);
 }
@@ -2045,10 +2112,12 @@ hipError_t launch_solve(const Engine& e, int workers, int tile, hipStream_t stre
   return hipGetLastError();
 }
 
-hipError_t launch_residual(const Engine& e, int64_t max_nodes, hipStream_t stream) {
-  const dim3 gn(grid_for(max_nodes, 256, e.ninst > 1 ? 256 : 4096), e.ninst);
-  if (e.dtype == 0) hipLaunchKernelGGL(k_residual<double>, gn, dim3(256), 0, stream, e);
-  else hipLaunchKernelGGL(k_residual<float>, gn, dim3(256), 0, stream, e);
+hipError_t launch_residual(const Engine& e, int64_t max_nodes, hipStream_t stream, int inst0,
+                           int count) {
+  const int n = count > 0 ? count : e.ninst;
+  const dim3 gn(grid_for(max_nodes, 256, n > 1 ? 256 : 4096), n);
+  if (e.dtype == 0) hipLaunchKernelGGL(k_residual<double>, gn, dim3(256), 0, stream, e, inst0);
+  else hipLaunchKernelGGL(k_residual<float>, gn, dim3(256), 0, stream, e, inst0);
   return hipGetLastError();
 }
 

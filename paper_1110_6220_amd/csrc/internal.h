@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <functional>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -51,7 +52,7 @@ struct DevBuf {
 // Buffers of one engine run.
 struct Solver {
   DevBuf delta, st, visits, cell_inst, key, deps, ord, slot, head, tail, inflight, cursor, ctl, inst;
-  DevBuf hblk, istat;
+  DevBuf hblk, istat, iact;
   void release();
   std::vector<DevBuf*> bufs();
 };
@@ -132,6 +133,13 @@ struct RunCtx {
                                  // for the FP64 re-solve of FP32 problems
   int share = 1;                 // the run gets 1/share of the default waves
   const double* density = nullptr;  // per problem: wall density, if known
+  // early completion: per problem a host-visible flag the solver sets when
+  // that problem is solved (idone, zeroed by the caller), and a function
+  // called repeatedly while the solver runs; problems whose results the
+  // caller has taken (detached[k] != 0) get no FP64 re-solve afterwards
+  unsigned int* idone = nullptr;
+  std::function<void(const Engine&, const std::vector<Inst>&)> poll;
+  const char* detached = nullptr;
 };
 // Sizes the solver's buffers for the instances in `inst` (cell0 filled in)
 // and fills the engine arguments.

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <condition_variable>
 #include <cstdio>
 #include <cstdlib>
@@ -153,10 +154,50 @@ struct eik_server {
   std::vector<std::thread> threads;
   std::vector<hipStream_t> streams;
   std::vector<std::unique_ptr<Workspace>> ws;
+  // early completion, per lane: a side stream for the finished problems'
+  // residual checks and downloads, and pinned host memory the solver writes
+  // each problem's completion flag into (kMaxBatch flags) plus a read-back
+  // area for the problems' counters (4 x kMaxBatch)
+  std::vector<hipStream_t> side;
+  std::vector<unsigned int*> flags;
+  std::vector<unsigned long long*> counters;
 
   void lane(int id);
   void solve(int id, std::vector<Req*>& batch);
+  void finish(Req* r);
+  // frees the lanes' streams, workspaces and pinned memory and the arenas
+  void free_lanes() {
+    for (auto& w : ws) workspace_free(w.get());
+    for (hipStream_t x : streams) (void)hipStreamDestroy(x);
+    for (hipStream_t x : side) (void)hipStreamDestroy(x);
+    for (unsigned int* f : flags) (void)hipHostFree(f);
+    for (unsigned long long* c : counters) (void)hipHostFree(c);
+    ws.clear();
+    streams.clear();
+    side.clear();
+    flags.clear();
+    counters.clear();
+    if (base) (void)hipFree(base);
+    base = nullptr;
+    if (pinned) (void)hipHostFree(pinned);
+    pinned = nullptr;
+  }
 };
+
+// Hands a solved request back (result in place, stats set): frees its
+// arena block and wakes waiters and idle lanes.
+void eik_server::finish(Req* r) {
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    arena.release(r->off, r->bytes);
+    if (r->hbytes) host_arena.release(r->hoff, r->hbytes);
+    r->hbytes = 0;
+    r->state = kReqDone;
+    in_flight--;
+  }
+  cv_work.notify_all();
+  cv_done.notify_all();
+}
 
 // Takes the requests at the head of the queue while a slot and arena space
 // are free (first come, first served: a request that does not fit holds back
@@ -188,19 +229,7 @@ void eik_server::lane(int id) {
       }
       if (batch.empty()) return;
     }
-    solve(id, batch);
-    {
-      std::lock_guard<std::mutex> lk(mu);
-      for (Req* r : batch) {
-        arena.release(r->off, r->bytes);
-        if (r->hbytes) host_arena.release(r->hoff, r->hbytes);
-        r->hbytes = 0;
-        r->state = kReqDone;
-        in_flight--;
-      }
-    }
-    cv_work.notify_all();
-    cv_done.notify_all();
+    solve(id, batch);  // finishes every request of the batch
   }
 }
 
@@ -255,11 +284,74 @@ void eik_server::solve(int id, std::vector<Req*>& batch) {
   ctx.f64 = f64.data();
   ctx.share = lanes;
   if (!cfg.opts.device_ptrs) ctx.density = density.data();
+  // Early completion: while the launch runs, a problem whose cells are all
+  // done is checked (FP32: its FP64 residual), downloaded and handed back at
+  // once, so a small request does not wait for the largest one of its
+  // launch.  A problem that fails its residual check stays for the FP64
+  // re-solve at the end of the launch.
+  std::vector<char> detached(n, 0), seen(n, 0);
+  std::vector<double> t_early(n, 0.0);
+  unsigned int* fl = flags[id];
+  unsigned long long* cnt = counters[id];
+  const bool early = n > 1;
+  const bool check32 = o.dtype == EIK_F32 && o.residual_check;
+  const double tol = o.residual_tol > 0.0 ? o.residual_tol : 4.0 * std::ldexp(1.0, -24);
+  if (early) {
+    std::memset(fl, 0, n * sizeof(unsigned int));
+    ctx.idone = fl;
+    ctx.detached = detached.data();
+    ctx.poll = [&](const Engine& e, const std::vector<Inst>& inst) {
+      for (int k = 0; k < n; ++k) {
+        if (seen[k] || !__atomic_load_n(&fl[k], __ATOMIC_ACQUIRE)) continue;
+        seen[k] = 1;
+        Req* r = batch[k];
+        hipStream_t ss = side[id];
+        const size_t nn = (size_t)r->p.nx * r->p.ny;
+        hipError_t e1 = check32 ? launch_residual(e, (int64_t)nn, ss, k, 1) : hipSuccess;
+        if (e1 == hipSuccess)
+          e1 = hipMemcpyAsync(cnt + 4 * k, e.istat + 4 * k, 4 * sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, ss);
+        if (e1 == hipSuccess)
+          e1 = hipMemcpyAsync(r->p.u_out, probs[k].u_out, nn * es, hipMemcpyDeviceToHost, ss);
+        if (e1 == hipSuccess) e1 = hipStreamSynchronize(ss);
+        if (e1 != hipSuccess) continue;  // left to the end of the launch
+        double resid = -1.0;
+        if (check32) std::memcpy(&resid, &cnt[4 * k + 3], sizeof resid);
+        if (check32 && !(resid <= tol)) continue;  // FP64 re-solve at the end
+        eik_stats& S = r->st;
+        std::memset(&S, 0, sizeof S);
+        const double t = now_s();
+        S.seconds = t - r->t_submit;
+        S.kernel_seconds = t - t_up1;  // launch start to completion (host clock)
+        S.cells = (uint64_t)inst[k].kx * inst[k].ky;
+        S.cells_total = (uint64_t)e.ncells;
+        S.cell_used = inst[k].s;
+        S.cell_visits = cnt[4 * k];
+        S.sweeps = cnt[4 * k + 1];
+        S.checks = cnt[4 * k + 2];
+        S.max_residual = check32 ? resid : -1.0;
+        S.residual_f32 = check32 ? resid : -1.0;
+        S.band_used = -1.0;
+        r->rc = EIK_OK;
+        detached[k] = 1;
+        t_early[k] = t;
+        std::vector<char>().swap(r->F);
+        std::vector<uint8_t>().swap(r->mask);
+        std::vector<int64_t>().swap(r->src);
+        std::vector<double>().swap(r->q);
+        finish(r);
+      }
+    };
+  }
   if (!rc) rc = run(n, probs.data(), o, stats.data(), nullptr, &ctx);
   if (rc && n > 1) {
-    // isolate the failing request(s)
+    // isolate the failing request(s) (none finished early: a failed launch
+    // reports no completed problem before its device-side error)
     for (int k = 0; k < n; ++k) {
-      RunCtx one = ctx;  // the request's own arena buffers
+      if (detached[k]) continue;
+      RunCtx one;  // the request's own arena buffers
+      one.ws = ctx.ws;
+      one.share = ctx.share;
       one.delta = &delta[k];
       one.f64 = &f64[k];
       one.density = ctx.density ? &density[k] : nullptr;
@@ -268,6 +360,7 @@ void eik_server::solve(int id, std::vector<Req*>& batch) {
     }
   } else {
     for (int k = 0; k < n; ++k) {
+      if (detached[k]) continue;
       batch[k]->rc = rc;
       if (rc) batch[k]->err = g_err;
     }
@@ -275,7 +368,7 @@ void eik_server::solve(int id, std::vector<Req*>& batch) {
   const double t_solved = now_s();
   for (int k = 0; k < n; ++k) {
     Req* r = batch[k];
-    if (r->rc) continue;
+    if (r->rc || detached[k]) continue;
     const size_t nn = (size_t)r->p.nx * r->p.ny;
     hipError_t e = hipMemcpyAsync(r->p.u_out, probs[k].u_out, nn * es, hipMemcpyDeviceToHost, st);
     if (e != hipSuccess) {
@@ -287,19 +380,26 @@ void eik_server::solve(int id, std::vector<Req*>& batch) {
   const double t = now_s();
   if (g_serve_log) {
     double nodes = 0;
-    for (Req* r : batch) nodes += (double)r->p.nx * r->p.ny;
-    std::fprintf(stderr, "[eik serve] lane %d: %d requests, %.2f Mnodes; upload %.2f ms, solve %.2f ms "
-                 "(kernel %.2f ms), download %.2f ms\n", id, n, nodes * 1e-6, (t_up1 - t_up) * 1e3,
-                 (t_solved - t_up1) * 1e3, stats[0].kernel_seconds * 1e3, (t - t_solved) * 1e3);
+    int ne = 0;
+    for (int k = 0; k < n; ++k) {
+      nodes += (double)batch[k]->p.nx * batch[k]->p.ny;
+      ne += detached[k];
+    }
+    std::fprintf(stderr, "[eik serve] lane %d: %d requests (%d finished early), %.2f Mnodes; upload "
+                 "%.2f ms, solve %.2f ms (kernel %.2f ms), download %.2f ms\n", id, n, ne,
+                 nodes * 1e-6, (t_up1 - t_up) * 1e3, (t_solved - t_up1) * 1e3,
+                 stats[0].kernel_seconds * 1e3, (t - t_solved) * 1e3);
   }
   for (int k = 0; k < n; ++k) {
     Req* r = batch[k];
+    if (detached[k]) continue;
     r->st = stats[k];
     r->st.seconds = t - r->t_submit;
     std::vector<char>().swap(r->F);
     std::vector<uint8_t>().swap(r->mask);
     std::vector<int64_t>().swap(r->src);
     std::vector<double>().swap(r->q);
+    finish(r);
   }
 }
 
@@ -336,20 +436,29 @@ int eik_serve_create(const eik_serve_cfg* cfg, eik_server** out) {
   for (int i = 0; i < s->lanes; ++i) {
     hipStream_t st = nullptr;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
-      for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
-      for (auto& w : s->ws) workspace_free(w.get());
-      (void)hipFree(s->base);
-      if (s->pinned) (void)hipHostFree(s->pinned);
+      s->free_lanes();
       return fail(EIK_EDEVICE, "cannot create a stream");
     }
     s->streams.push_back(st);
+    hipStream_t ss = nullptr;
+    void* f = nullptr;
+    void* c = nullptr;
+    if (hipStreamCreateWithFlags(&ss, hipStreamNonBlocking) != hipSuccess ||
+        hipHostMalloc(&f, kMaxBatch * sizeof(unsigned int),
+                      hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess ||
+        hipHostMalloc(&c, 4 * kMaxBatch * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) {
+      if (ss) (void)hipStreamDestroy(ss);
+      if (f) (void)hipHostFree(f);
+      s->free_lanes();
+      return fail(EIK_EDEVICE, "cannot create a lane's side stream or completion flags");
+    }
+    s->side.push_back(ss);
+    s->flags.push_back(static_cast<unsigned int*>(f));
+    s->counters.push_back(static_cast<unsigned long long*>(c));
     s->ws.emplace_back(new Workspace());
     workspace_defer_frees(s->ws.back().get());
     if ((rc = workspace_init(s->ws.back().get()))) {
-      for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
-      for (auto& w : s->ws) workspace_free(w.get());
-      (void)hipFree(s->base);
-      if (s->pinned) (void)hipHostFree(s->pinned);
+      s->free_lanes();
       return rc;
     }
   }
@@ -481,10 +590,7 @@ int eik_serve_destroy(eik_server* s) {
   }
   s->cv_work.notify_all();
   for (auto& t : s->threads) t.join();
-  for (auto& w : s->ws) workspace_free(w.get());
-  for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
-  (void)hipFree(s->base);
-  if (s->pinned) (void)hipHostFree(s->pinned);
+  s->free_lanes();
   delete s;
   return EIK_OK;
 }

@@ -24,7 +24,8 @@ SCHEDULES = {"auto": 0, "coarse": 1, "bands": 2, "fifo": 3, "heap": 4}
 # Every function include/eik.h declares.
 EXPORTS = ("eik_solve", "eik_solve_batched", "eik_serve_create", "eik_serve_submit",
            "eik_serve_poll", "eik_serve_wait", "eik_serve_cancel", "eik_serve_destroy",
-           "eik_sweep_solve", "eik_solve3", "eik_fmsm3", "eik_solve_noalloc", "eik_last_error")
+           "eik_sweep_solve", "eik_solve3", "eik_fmsm3", "eik_solve_noalloc", "eik_probe_step_latency",
+           "eik_last_error")
 
 
 class EikError(RuntimeError):
@@ -114,6 +115,7 @@ def _load() -> ctypes.CDLL:
                                   ctypes.POINTER(SweepOpts), vp, vp, ctypes.POINTER(SweepStats)]
     L.eik_solve_noalloc.argtypes = [i32, i32, ctypes.c_double, vp, vp, i32, vp, vp, vp,
                                     ctypes.POINTER(Opts), ctypes.POINTER(Stats)]
+    L.eik_probe_step_latency.argtypes = [i32, i32, i32, ctypes.POINTER(ctypes.c_double)]
     L.eik_last_error.restype = ctypes.c_char_p
     return L
 
@@ -316,6 +318,15 @@ def eik_solve3(F, h, src, q=None, mask=None, u_out=None, *, method="exact"):
     _check(fn(nx, ny, nz, float(h), ptr(F_), ptr(m_), nsrc, ptr(src_), ptr(q_), ptr(u),
               int(device), _stream_of(device), ctypes.byref(st)))
     return u, {f: getattr(st, f) for f, _ in st._fields_}
+
+
+def probe_step_latency(dtype="f64", side=64, sweeps=200) -> float:
+    """Seconds per dependent anti-diagonal step of the cell sweep, one wave
+    alone (eik_probe_step_latency of include/eik.h)."""
+    t = ctypes.c_double()
+    _check(lib.eik_probe_step_latency(F64 if dtype == "f64" else F32, int(side), int(sweeps),
+                                      ctypes.byref(t)))
+    return t.value
 
 
 class Server:

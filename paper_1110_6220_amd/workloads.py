@@ -154,48 +154,60 @@ def batch_bumps(count: int = 256, seed: int = 4, n_lo: int = 65, n_hi: int = 102
 
 
 def kruskal_maze(n: int, rng: np.random.Generator, w_lo: int = 4, w_hi: int = 16):
-    """Maze on an n x n grid: rooms of width w ~ U{w_lo..w_hi} on a lattice of
-    pitch w + 2 (2-node walls), passages carved by randomized Kruskal over the
-    lattice edges; speed ~ U[0.5, 2] per room and per carved passage; one
-    source at a random corridor node."""
+    """Maze on an n x n grid: rooms of width w ~ U{w_lo..w_hi} on an m x m
+    lattice of pitch w + 2 (2-node walls), passages carved by randomized
+    Kruskal over the lattice edges (edges taken in a uniformly random order,
+    an edge carved when it joins two components: the minimum spanning tree
+    of distinct random edge weights); speed ~ U[0.5, 2] per room and per
+    carved passage; one source at a random corridor node."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import minimum_spanning_tree
     w = int(rng.integers(w_lo, w_hi + 1))
     p = w + 2
     m = max((n - 2) // p, 1)
+    f_room = rng.uniform(0.5, 2.0, size=(m, m))           # [b, a]: room (a, b)
+    # lattice edges: east of room (a, b) for a < m - 1, north of it for b < m - 1
+    ea, eb = np.meshgrid(np.arange(m - 1), np.arange(m), indexing="xy")
+    na, nb = np.meshgrid(np.arange(m), np.arange(m - 1), indexing="xy")
+    u = np.concatenate([(eb * m + ea).ravel(), (nb * m + na).ravel()])
+    v = np.concatenate([(eb * m + ea + 1).ravel(), ((nb + 1) * m + na).ravel()])
+    ne = (m - 1) * m
+    order = rng.permutation(len(u))                        # Kruskal's processing order
+    weight = np.empty(len(u))
+    weight[order] = np.arange(1, len(u) + 1)
+    f_pass = rng.uniform(0.5, 2.0, size=len(u))
+    carved = np.zeros(len(u), dtype=bool)
+    if len(u):
+        T = minimum_spanning_tree(coo_matrix((weight, (u, v)), shape=(m * m, m * m))).tocoo()
+        carved[order[(T.data - 1).astype(np.int64)]] = True
+    east = np.zeros((m, max(m - 1, 0)), dtype=bool)
+    north = np.zeros((max(m - 1, 0), m), dtype=bool)
+    east.ravel()[:] = carved[:ne]
+    north.ravel()[:] = carved[ne:]
+    f_east = f_pass[:ne].reshape(m, max(m - 1, 0))
+    f_north = f_pass[ne:].reshape(max(m - 1, 0), m)
+    # lattice coordinates of every node row / column
+    z = np.arange(n) - 2
+    blk, off = z // p, z % p
+    inside = (z >= 0) & (blk < m)
+    room = inside & (off < w)                              # inside a room's span
+    wall = inside & (off >= w) & (blk < m - 1)             # between rooms blk and blk + 1
+    bi = np.clip(blk, 0, m - 1)
+    bw = np.clip(blk, 0, max(m - 2, 0))
     F = np.ones((n, n))
     mask = np.zeros((n, n), dtype=np.uint8)
-
-    def room(a, b):
-        return (slice(2 + b * p, 2 + b * p + w), slice(2 + a * p, 2 + a * p + w))
-
-    for a in range(m):
-        for b in range(m):
-            sl = room(a, b)
-            mask[sl] = 1
-            F[sl] = rng.uniform(0.5, 2.0)
-    edges = [(a, b, 0) for a in range(m - 1) for b in range(m)] + \
-            [(a, b, 1) for a in range(m) for b in range(m - 1)]
-    order = rng.permutation(len(edges))
-    parent = list(range(m * m))
-
-    def find(x):
-        while parent[x] != x:
-            parent[x] = parent[parent[x]]
-            x = parent[x]
-        return x
-
-    for e in order:
-        a, b, d = edges[e]
-        a2, b2 = (a + 1, b) if d == 0 else (a, b + 1)
-        r1, r2 = find(b * m + a), find(b2 * m + a2)
-        if r1 == r2:
-            continue
-        parent[r1] = r2
-        if d == 0:  # passage east of room (a, b)
-            sl = (slice(2 + b * p, 2 + b * p + w), slice(2 + a * p + w, 2 + (a + 1) * p))
-        else:       # passage north of room (a, b)
-            sl = (slice(2 + b * p + w, 2 + (b + 1) * p), slice(2 + a * p, 2 + a * p + w))
-        mask[sl] = 1
-        F[sl] = rng.uniform(0.5, 2.0)
+    R = room[:, None] & room[None, :]
+    F[R] = f_room[bi[:, None], bi[None, :]][R]
+    mask[R] = 1
+    if m > 1:
+        E = room[:, None] & wall[None, :]
+        E &= east[bi[:, None], bw[None, :]]
+        F[E] = f_east[bi[:, None], bw[None, :]][E]
+        mask[E] = 1
+        N = wall[:, None] & room[None, :]
+        N &= north[bw[:, None], bi[None, :]]
+        F[N] = f_north[bw[:, None], bi[None, :]][N]
+        mask[N] = 1
     acc = np.flatnonzero(mask.ravel())
     src = int(acc[rng.integers(0, len(acc))])
     h = 1.0 / (n - 1)

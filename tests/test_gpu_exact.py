@@ -188,3 +188,16 @@ def test_time_limit_is_reported(eik):
     assert e.value.code == eik.EIK_EDEVICE
     got, _ = solve_dev(eik, w)  # the next solve is unaffected
     assert max_rel(got, O.fmm(O.Problem.from_workload(w))) <= TOL64
+
+
+def test_probe_step_latency(eik):
+    """The sweep-step latency probe (the t_dep of the span bound) returns a
+    positive time of the order of one dependent FP64 update (tens to
+    hundreds of nanoseconds), and rejects what it does not measure."""
+    for dt in ("f64", "f32"):
+        for side in (32, 64):
+            t = eik.probe_step_latency(dt, side, 50)
+            print(f"  t_dep {dt} side {side}: {t * 1e9:.1f} ns", flush=True)
+            assert 5e-9 < t < 5e-6
+    with pytest.raises(eik.EikError):
+        eik.probe_step_latency("f64", 16, 10)
