@@ -83,8 +83,8 @@ typedef struct {
   eik_dtype dtype;          /* storage and sweep precision of u and F          */
   eik_method method;
   int32_t cell;             /* cell side s in nodes, 4..64; 0 = tuned choice    */
-  double band;              /* BANDS: band width in units of u; 0 = one cell
-                               crossing at unit speed (s * h)                   */
+  double band;              /* BANDS: band width in units of u, the same for
+                               every problem; 0 = band_cells                    */
   int32_t device_ptrs;      /* 1: all pointers are device memory                */
   void* stream;             /* hipStream_t, or NULL for the null stream         */
   uint64_t max_cell_visits; /* guard on total cell visits; 0 = 64 * cells + 1024 */
@@ -93,7 +93,8 @@ typedef struct {
                                exceeds residual_tol (F64: only report it)     */
   int32_t workers;          /* persistent waves; 0 = chosen from the problem    */
   int32_t band_window;      /* bands above the lowest unfinished band whose
-                               cells may start, 0..63 (band <= 0: unused)       */
+                               cells may start, 0..63 (with band = band_cells =
+                               0 the tuned window is used instead)             */
   int32_t eager_publish;    /* 1: re-queue neighbours after every sweep that
                                changed a value; 0: once per removal, after the
                                cell converged (the paper's order)              */
@@ -109,6 +110,10 @@ typedef struct {
                                library's workspace has to grow.              */
   double residual_tol;      /* residual_check bound on max |T(u)-u|/u; 0 = 4 * 2^-24
                                (must be >= 0 and finite)                       */
+  double band_cells;        /* BANDS with band = 0: band width in cell crossings
+                               at unit speed (s * h of each problem); 0 = the
+                               tuned width and window (csrc/tuned_bands.h).
+                               In a batch every problem has bands of its own. */
 } eik_opts;
 
 /* Statistics of one problem.  In a batch, cells, cell_visits, sweeps,

@@ -1,4 +1,5 @@
-"""Cell-side autotuner for the exact method.
+"""Autotuner for the cell side of the exact method and for the band width
+of the band schedule.
 
 The exact method's result does not depend on the cell side (the Theorem of
 Section 3.2.1 of Chacon & Vladimirsky: label-correcting on cells converges to
@@ -8,7 +9,17 @@ of each class (precision, single problem or batch, grid size, open grid or
 dense walls) on the current device and writes the table the library compiles
 in (csrc/tuned_cells.h).
 
+The band schedule takes cells from the lowest bands of their cell values; a
+band's width (in cell crossings s h at unit speed) and the number of bands
+above the lowest that may start (the window) set how far the concurrent
+order strays from the heap order of Section 3.2.2.  For the exact method that
+is again speed only.  For FHCM it also moves the error, so a width qualifies
+only if the FHCM result stays as close to the exact discrete solution as the
+serial heap order's (max error at most 1.1 times the heap order's on every
+sample).  --bands times the candidates and writes csrc/tuned_bands.h.
+
     python -m paper_1110_6220_amd.autotune --out paper_1110_6220_amd/csrc/tuned_cells.h
+    python -m paper_1110_6220_amd.autotune --bands --out paper_1110_6220_amd/csrc/tuned_bands.h
 
 Rebuild the library afterwards (__graft_entry__.build()).
 """
@@ -113,6 +124,107 @@ def tune(dtypes=("f64", "f32"), log=print):
     return rows, notes
 
 
+BAND_FACTORS = (0.5, 1.0, 2.0, 4.0, 8.0)
+BAND_WINDOWS = (0, 1, 3)
+FHCM_ERR_SLACK = 1.1
+
+
+def _band_samples(batched, rng):
+    if batched:
+        sides = rng.integers(65, 514, size=16)
+        return [W.gaussian_bumps(int(n), rng) for n in sides]
+    return [W.smooth_sine(513, 0.5), W.gaussian_bumps(385, rng),
+            W.sinusoid_point(352, 0.5, 10.0), W.checkerboard_point(352, 11)]
+
+
+def tune_bands(dtypes=("f64", "f32"), log=print):
+    """Rows (method, dtype code, batched, width in cell crossings, window)
+    and notes with the measurements."""
+    import torch
+
+    from . import eik
+    dev = torch.device("cuda:0")
+    rows, notes = [], []
+    for method, mcode in (("exact", 0), ("fhcm", 2)):
+        for dt_code, dtype in enumerate(("f64", "f32")):
+            if dtype not in dtypes:
+                continue
+            tdt = torch.float64 if dtype == "f64" else torch.float32
+            for batched in (0, 1):
+                rng = np.random.default_rng(2000 + 7 * mcode + 3 * dt_code + batched)
+                ws = _band_samples(batched, rng)
+                ds = []
+                for w in ws:
+                    d = dict(F=torch.from_numpy(w["F"]).to(dev, tdt), h=w["h"],
+                             src=torch.from_numpy(w["src"]).to(dev),
+                             q=torch.from_numpy(w["q"]).to(dev))
+                    if w.get("mask") is not None:
+                        d["mask"] = torch.from_numpy(w["mask"]).to(dev)
+                    ds.append(d)
+
+                def solve_all(**kw):
+                    if batched:
+                        us, _ = eik.eik_solve_batched(ds, dtype=dtype, method=method,
+                                                      schedule="bands", **kw)
+                        return us
+                    return [eik.eik_solve(d["F"], d["h"], d["src"], d["q"], d.get("mask"),
+                                          dtype=dtype, method=method, schedule="bands", **kw)[0]
+                            for d in ds]
+
+                ok_err = None
+                if method == "fhcm":
+                    # the exact discrete solutions and the serial heap order's errors
+                    ex = [eik.eik_solve(d["F"], d["h"], d["src"], d["q"], d.get("mask"), dtype=dtype)[0]
+                          for d in ds]
+                    hp = [eik.eik_solve(d["F"], d["h"], d["src"], d["q"], d.get("mask"), dtype=dtype,
+                                        method="fhcm", schedule="heap")[0] for d in ds]
+                    ok_err = [float((a.double() - b.double()).abs().nan_to_num(0.0).max()) for a, b in zip(hp, ex)]
+                times, errs = {}, {}
+                for f in BAND_FACTORS:
+                    for win in BAND_WINDOWS:
+                        # an explicit width: f cell crossings of each problem
+                        kw = dict(band_cells=f, band_window=win)
+                        times[(f, win)] = _time(lambda: solve_all(**kw))
+                        if ok_err is not None:
+                            us = solve_all(**kw)
+                            errs[(f, win)] = max(
+                                float((u.double() - e.double()).abs().nan_to_num(0.0).max()) / max(o, 1e-300)
+                                for u, e, o in zip(us, ex, ok_err))
+                ok = [c for c in times if ok_err is None or errs[c] <= FHCM_ERR_SLACK]
+                if not ok:
+                    ok = [(1.0, 0)]
+                best = min(ok, key=times.get)
+                rows.append((mcode, dt_code, batched, best[0], best[1]))
+                sides = [w["nx"] for w in ws]
+                note = (f"{method} {dtype} batched={batched} ({len(ws)} problems, sides "
+                        f"{min(sides)}..{max(sides)}): "
+                        + ", ".join(f"{c[0]:g}/{c[1]}: {times[c] * 1e3:.2f} ms"
+                                    + (f" err x{errs[c]:.2f}" if c in errs else "")
+                                    for c in sorted(times))
+                        + f" -> {best[0]:g}/{best[1]}")
+                notes.append(note)
+                log(note)
+    return rows, notes
+
+
+def write_bands_header(path, rows, notes, device_name):
+    lines = [
+        "// Band widths of the band schedule, written by paper_1110_6220_amd/autotune.py",
+        "// (--bands) on " + device_name + ".  Row: method (0 exact, 2 FHCM), dtype",
+        "// (0 f64, 1 f32), batched (problems per launch > 1), width in cell",
+        "// crossings s h, window.  Measurements (median of 3; width/window: time,",
+        f"// FHCM: max error / the heap order's, must be <= {FHCM_ERR_SLACK}):",
+    ]
+    lines += ["//   " + n for n in notes]
+    lines += ["#pragma once", "namespace eik {", "struct TunedBand {", "  int method, dtype, batched;",
+              "  double factor;", "  int window;", "};", "constexpr TunedBand kTunedBands[] = {"]
+    for r in rows:
+        lines.append(f"    {{{r[0]}, {r[1]}, {r[2]}, {r[3]!r}, {r[4]}}},")
+    lines += ["};", "}  // namespace eik", ""]
+    with open(path, "w") as f:
+        f.write("\n".join(lines))
+
+
 def write_header(path, rows, notes, device_name):
     lines = [
         "// Cell sides chosen by paper_1110_6220_amd/autotune.py on " + device_name + ".",
@@ -137,10 +249,17 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--out", required=True, help="header to write")
     ap.add_argument("--dtype", action="append", choices=["f64", "f32"])
+    ap.add_argument("--bands", action="store_true", help="tune the band schedule instead")
     args = ap.parse_args()
     import torch
-    rows, notes = tune(tuple(args.dtype or ("f64", "f32")), log=lambda s: print(s, flush=True))
-    write_header(args.out, rows, notes, torch.cuda.get_device_name(0))
+    dts = tuple(args.dtype or ("f64", "f32"))
+    log = lambda s: print(s, flush=True)  # noqa: E731
+    if args.bands:
+        rows, notes = tune_bands(dts, log=log)
+        write_bands_header(args.out, rows, notes, torch.cuda.get_device_name(0))
+    else:
+        rows, notes = tune(dts, log=log)
+        write_header(args.out, rows, notes, torch.cuda.get_device_name(0))
     print("wrote", args.out, flush=True)
 
 

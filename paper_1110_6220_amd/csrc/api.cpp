@@ -19,6 +19,7 @@
 #include "../../include/eik.h"
 #include "engine.h"
 #include "internal.h"
+#include "tuned_bands.h"
 #include "tuned_cells.h"
 
 namespace eik {
@@ -86,7 +87,7 @@ void DevBuf::release() {
 
 std::vector<DevBuf*> Solver::bufs() {
   return {&delta, &st,   &visits,   &cell_inst, &key, &deps, &ord,  &slot,  &head,
-          &tail,  &inflight, &cursor, &ctl,      &inst, &hblk, &istat, &iact};
+          &tail,  &inflight, &cursor, &ctl,      &inst, &hblk, &istat, &iact, &qgrp};
 }
 
 void Solver::release() {
@@ -199,6 +200,8 @@ int check_opts(const eik_opts& o) {
   if (o.cell != 0 && (o.cell < 4 || o.cell > 64))
     return fail(EIK_EINVAL, "cell side %d outside [4, 64]", (int)o.cell);
   if (!(o.band == o.band) || std::isinf(o.band)) return fail(EIK_EINVAL, "band must be finite");
+  if (!(o.band_cells >= 0.0) || std::isinf(o.band_cells))
+    return fail(EIK_EINVAL, "band_cells must be >= 0 and finite");
   if (o.workers < 0) return fail(EIK_EINVAL, "workers must be >= 0");
   if (o.band_window < 0 || o.band_window > 63) return fail(EIK_EINVAL, "band_window outside [0, 63]");
   if (o.timeout_ms < 0) return fail(EIK_EINVAL, "timeout_ms must be >= 0");
@@ -264,6 +267,19 @@ static int tuned_cell(int dtype, bool batched, int nx, int ny, double wall_densi
     if (t.dtype == dtype && t.batched == (batched ? 1 : 0) && t.dense == dense && n <= t.nmax)
       return t.cell;
   return default_cell(nx, ny, EIK_EXACT);
+}
+
+// Band width (in cell crossings s h at unit speed) and window of the band
+// schedule from the tuned table.
+static void tuned_band(int method, int dtype, bool batched, double* factor, int* window) {
+  *factor = 1.0;
+  *window = 0;
+  for (const TunedBand& t : kTunedBands)
+    if (t.method == method && t.dtype == dtype && t.batched == (batched ? 1 : 0)) {
+      *factor = t.factor;
+      *window = t.window;
+      return;
+    }
 }
 
 // Wall density of host masks: the share of accessible nodes with an
@@ -338,7 +354,7 @@ int validate_shape(const eik_problem& p) {
 // Sizes the solver's buffers for the instances in `inst` (cell0 filled in
 // here) and fills the engine arguments.
 int setup_engine(Solver& sv, std::vector<Inst>& inst, int dtype, int method, int dag, int heap,
-                 double band, int window, int eager, uint64_t guard, uint64_t timeout,
+                 const BandSpec* band, int window, int eager, uint64_t guard, uint64_t timeout,
                  hipStream_t stream, Engine* out, DevBuf* instbuf) {
   DevBuf& ib = instbuf ? *instbuf : sv.inst;
   int64_t J = 0;
@@ -347,9 +363,18 @@ int setup_engine(Solver& sv, std::vector<Inst>& inst, int dtype, int method, int
     J += (int64_t)I.kx * I.ky;
   }
   if (J > (1ll << 30)) return fail(EIK_EINVAL, "too many cells");
-  const uint32_t nb = band > 0.0 ? 64u : 1u;
-  const uint32_t cap = pow2_at_least((uint64_t)J + 1);
   const int n = (int)inst.size();
+  // bands: one queue of 64 bands; a batch gets a group of bands per problem
+  // (16, or enough for the window)
+  const bool groups = band && n > 1;
+  const uint32_t nb = !band ? 1u : groups ? std::max<uint32_t>(16u, pow2_at_least((uint64_t)window + 2)) : 64u;
+  const uint32_t cap = pow2_at_least((uint64_t)J + 1);
+  const uint32_t ng = groups ? (uint32_t)n : 1u;
+  uint64_t nslot = (uint64_t)cap * nb;
+  if (groups) {  // the preparation kernel lays the groups out the same way
+    nslot = 0;
+    for (int k = 0; k < n; ++k) nslot += (uint64_t)pow2_at_least((uint64_t)inst[k].kx * inst[k].ky + 1) * nb;
+  }
   HIP_TRY(sv.st.ensure(J * sizeof(uint32_t)));
   HIP_TRY(sv.visits.ensure(J * sizeof(uint32_t)));
   HIP_TRY(sv.key.ensure(J * sizeof(unsigned long long)));
@@ -359,11 +384,12 @@ int setup_engine(Solver& sv, std::vector<Inst>& inst, int dtype, int method, int
   HIP_TRY(sv.cell_inst.ensure(n > 1 ? J * sizeof(int32_t) : 4));
   HIP_TRY(sv.deps.ensure(dag ? J * sizeof(int32_t) : 4));
   HIP_TRY(sv.ord.ensure(dag ? J : 4));
-  HIP_TRY(sv.slot.ensure((size_t)cap * nb * sizeof(unsigned long long)));
-  HIP_TRY(sv.head.ensure((size_t)nb * kCtrStride * sizeof(unsigned long long)));
-  HIP_TRY(sv.tail.ensure((size_t)nb * kCtrStride * sizeof(unsigned long long)));
-  HIP_TRY(sv.inflight.ensure((size_t)nb * kCtrStride * sizeof(unsigned long long)));
-  HIP_TRY(sv.cursor.ensure(128));
+  HIP_TRY(sv.slot.ensure((size_t)nslot * sizeof(unsigned long long)));
+  HIP_TRY(sv.head.ensure((size_t)ng * nb * kCtrStride * sizeof(unsigned long long)));
+  HIP_TRY(sv.tail.ensure((size_t)ng * nb * kCtrStride * sizeof(unsigned long long)));
+  HIP_TRY(sv.inflight.ensure((size_t)ng * nb * kCtrStride * sizeof(unsigned long long)));
+  HIP_TRY(sv.cursor.ensure((size_t)ng * kCtrStride * sizeof(unsigned long long)));
+  HIP_TRY(sv.qgrp.ensure((size_t)ng * sizeof(QGroup)));
   HIP_TRY(sv.ctl.ensure(sizeof(Ctl)));
   HIP_TRY(ib.ensure(n * sizeof(Inst)));
   HIP_TRY(hipMemcpyAsync(ib.p, inst.data(), n * sizeof(Inst), hipMemcpyHostToDevice, stream));
@@ -393,10 +419,15 @@ int setup_engine(Solver& sv, std::vector<Inst>& inst, int dtype, int method, int
   e.q.tail = sv.tail.as<unsigned long long>();
   e.q.inflight = sv.inflight.as<unsigned long long>();
   e.q.cursor = sv.cursor.as<unsigned long long>();
+  e.q.grp = sv.qgrp.as<QGroup>();
   e.q.cap = cap;
   e.q.nb = nb;
   e.q.window = (uint32_t)window;
-  e.q.inv_width = band > 0.0 ? 1.0 / band : 0.0;
+  e.q.ng = ng;
+  e.q.inv_width = band ? 1.0 / band->width_of(inst[0]) : 0.0;
+  e.q.nslot = nslot;
+  e.q.width = band ? band->width : 0.0;
+  e.q.width_cells = band ? band->cells : 0.0;
   e.ctl = sv.ctl.as<Ctl>();
   e.eager = eager;
   e.profile = g_profile;
@@ -438,7 +469,7 @@ constexpr int kCoarseEngineCell = EIK_COARSE_ENGINE_CELL;
 constexpr size_t kMaxPlans = 8;           // captured graphs kept per workspace
 
 static int complete(Workspace* ws, int n, const eik_problem* probs, const eik_opts& o,
-                    const RunCtx& ctx, const std::vector<Inst>& inst, int64_t J, double band,
+                    const RunCtx& ctx, const std::vector<Inst>& inst, int64_t J, const std::vector<double>& widths,
                     bool coarse_engine, bool want_resid, const unsigned long long* istat,
                     hipStream_t stream, double t0, eik_stats* stats, RunInfo* info,
                     std::unique_lock<std::mutex>& lk, bool replayed);
@@ -470,6 +501,7 @@ static uint64_t plan_key(int n, const eik_problem* probs, const eik_opts& o, con
                           o.eager_publish, o.schedule, o.residual_check, o.timeout_ms, ctx.share})
     mix(&v, sizeof v);
   mix(&o.band, sizeof o.band);
+  mix(&o.band_cells, sizeof o.band_cells);
   mix(&o.max_cell_visits, sizeof o.max_cell_visits);
   return hsh;
 }
@@ -522,7 +554,7 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
       HIP_TRY(hipEventRecord(ws->ev1, stream));
       HIP_TRY(hipGraphLaunch(pl->post, stream));
       HIP_TRY(hipStreamSynchronize(stream));
-      return complete(ws, n, probs, o, ctx, pl->host_inst, pl->J, pl->band, pl->coarse_engine,
+      return complete(ws, n, probs, o, ctx, pl->host_inst, pl->J, pl->widths, pl->coarse_engine,
                       pl->want_resid, pl->e.istat, stream, t0, stats, info, lk, true);
     }
   }
@@ -570,7 +602,6 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
   std::vector<Tiling> til(n);
   int64_t total_nodes = 0, max_nodes = 0, max_src = 0;
   int extent = 0;
-  double hs_max = 0.0;
   // A launch sizes every wave's LDS for its widest cell: a batch keeps its
   // cells within 32 nodes (several waves per compute unit) unless every
   // problem asks for 64.
@@ -593,7 +624,6 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
     total_nodes += (int64_t)p.nx * p.ny;
     max_nodes = std::max<int64_t>(max_nodes, (int64_t)p.nx * p.ny);
     max_src = std::max<int64_t>(max_src, p.nsrc);
-    hs_max = std::max(hs_max, p.h * til[k].s);
   }
 
   // staging of host inputs
@@ -651,11 +681,17 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
     off += nn;
   }
 
-  double band = -1.0;
-  if (sched == EIK_SCHED_BANDS) band = o.band > 0.0 ? o.band : hs_max;  // one cell crossing at unit speed
+  // band widths: the given one, else the tuned multiple of each problem's
+  // own cell crossing at unit speed (s h)
+  BandSpec bs{o.band > 0.0 ? o.band : 0.0, o.band_cells};
+  int window = o.band_window;
+  if (!(o.band > 0.0) && !(o.band_cells > 0.0)) tuned_band(method, dt, n > 1, &bs.cells, &window);
+  std::vector<double> widths;
+  if (sched == EIK_SCHED_BANDS)
+    for (int k = 0; k < n; ++k) widths.push_back(bs.width_of(inst[k]));
   const uint64_t timeout = (uint64_t)ws->wall_khz * (uint64_t)(o.timeout_ms ? o.timeout_ms : 10000);
   Engine e;
-  if ((rc = setup_engine(ws->fine, inst, dt, method, dag, heap, band, o.band_window,
+  if ((rc = setup_engine(ws->fine, inst, dt, method, dag, heap, widths.empty() ? nullptr : &bs, window,
                          o.eager_publish, o.max_cell_visits, timeout, stream, &e,
                          np ? &np->inst : nullptr)))
     return rc;
@@ -748,7 +784,7 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
       cext = std::max(cext, ct.extent);
     }
     HIP_TRY(hipMemcpyAsync(coutbuf.p, co.data(), n * sizeof(CoarseOut), hipMemcpyHostToDevice, stream));
-    if (!fmm && !jacobi && (rc = setup_engine(ws->coarse, cinst, EIK_F64, EIK_EXACT, 0, 0, -1.0, 0, 0, 0,
+    if (!fmm && !jacobi && (rc = setup_engine(ws->coarse, cinst, EIK_F64, EIK_EXACT, 0, 0, nullptr, 0, 0, 0,
                                               timeout, stream, &ce, np ? &np->cinst : nullptr)))
       return rc;
     have_coarse = true;
@@ -834,7 +870,7 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
     np->last_use = ws->uses;
     np->host_inst = inst;
     np->J = J;
-    np->band = band;
+    np->widths = widths;
     np->coarse_engine = coarse_engine;
     np->want_resid = want_resid;
     if (ws->plans.size() >= kMaxPlans) {
@@ -858,14 +894,14 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
     ctx.poll(e, inst);
   }
   HIP_TRY(hipStreamSynchronize(stream));
-  return complete(ws, n, probs, o, ctx, inst, J, band, coarse_engine, want_resid, e.istat, stream,
+  return complete(ws, n, probs, o, ctx, inst, J, widths, coarse_engine, want_resid, e.istat, stream,
                   t0, stats, info, lk, false);
 }
 
 // After the solve's stream has completed: errors, FP32 certification (per
 // problem), copies to host outputs, diagnostics and statistics.
 static int complete(Workspace* ws, int n, const eik_problem* probs, const eik_opts& o,
-                    const RunCtx& ctx, const std::vector<Inst>& inst, int64_t J, double band,
+                    const RunCtx& ctx, const std::vector<Inst>& inst, int64_t J, const std::vector<double>& widths,
                     bool coarse_engine, bool want_resid, const unsigned long long* istat,
                     hipStream_t stream, double t0, eik_stats* stats, RunInfo* info,
                     std::unique_lock<std::mutex>& lk, bool replayed) {
@@ -966,7 +1002,7 @@ static int complete(Workspace* ws, int n, const eik_problem* probs, const eik_op
       S.mon_ok = c.mon_ok;
       S.max_residual = resid[k];
       S.cell_used = inst[k].s;
-      S.band_used = band;
+      S.band_used = widths.empty() ? -1.0 : widths[k];
       S.fell_back_to_f64 = fell[k];
       S.cells_total = (uint64_t)J;
       S.graph_replayed = replayed ? 1 : 0;

@@ -48,6 +48,17 @@ struct Inst {
   int32_t nsrc;
 };
 
+// One problem's bands when a batch runs under the band schedule: each
+// problem has its own rings, cursor and band width, so no problem waits for
+// another's band to drain.
+struct QGroup {
+  unsigned long long off;  // first slot of the group's nb rings
+  uint32_t cap;            // power of two > the problem's cells
+  uint32_t pad;
+  double inv_width;        // 1 / band width
+  double pad2;
+};
+
 // Multi-producer multi-consumer cell queue.  Band b holds a ring of `cap`
 // slots; a slot is (sequence << 32 | cell).  Keys map to absolute band index
 // floor(key / width); the ring is that index modulo nb.  inflight[b] counts
@@ -55,17 +66,25 @@ struct Inst {
 // band only once its count is zero (the band is closed with kClosed while the
 // cursor moves, then reopened for band + nb).  Cells are popped only from the
 // `window` + 1 bands starting at the cursor.  nb = 1 is a plain FIFO.
+// With ng > 1 groups (one per problem of a batch) every group is such a
+// queue of its own: counters of ring r of group g at index g * nb + r, the
+// cursor of group g at g * kCtrStride, slots and width from grp[g] (filled by
+// the preparation kernel: width `width` if > 0, else width_cells times the
+// problem's s h).
 struct Queue {
-  unsigned long long* slot;      // nb * cap
-  unsigned long long* head;      // nb entries, stride kCtrStride
-  unsigned long long* tail;      // nb entries, stride kCtrStride
-  unsigned long long* inflight;  // nb entries, stride kCtrStride
-  unsigned long long* cursor;    // 1
-  uint32_t cap;                  // power of two > number of cells
+  unsigned long long* slot;      // nb * cap (ng > 1: sum over groups of nb * cap)
+  unsigned long long* head;      // ng * nb entries, stride kCtrStride
+  unsigned long long* tail;      // ng * nb entries, stride kCtrStride
+  unsigned long long* inflight;  // ng * nb entries, stride kCtrStride
+  unsigned long long* cursor;    // ng entries, stride kCtrStride
+  QGroup* grp;                   // ng entries (ng > 1)
+  uint32_t cap;                  // power of two > number of cells (ng = 1)
   uint32_t nb;                   // power of two
   uint32_t window;
-  uint32_t pad;
-  double inv_width;              // 1 / band width
+  uint32_t ng;                   // groups (1: one queue for all cells)
+  double inv_width;              // 1 / band width (ng = 1)
+  unsigned long long nslot;      // slots in all
+  double width, width_cells;     // band width of the groups (see above)
 };
 constexpr int kCtrStride = 16;  // 128 bytes between hot counters
 constexpr unsigned long long kClosed = 1ull << 62;

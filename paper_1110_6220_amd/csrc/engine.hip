@@ -37,6 +37,7 @@
 #include "engine.h"
 #include "wave.h"
 
+
 namespace eik {
 namespace {
 
@@ -101,14 +102,17 @@ __device__ __forceinline__ double sqrt_pos(double x) {
 // Local update of Section 2 from a (x-neighbour value) and b (y-neighbour
 // value): the one-sided value min(a,b) + delta when |a - b| >= delta,
 // otherwise the root >= max(a,b) of (U-a)^2 + (U-b)^2 = delta^2.  The
-// expression order matches the CPU oracle and the build disables contraction,
-// so both round identically.  a = b = +inf gives NaN, which the caller's
-// minimum with the old value turns into "no update".
+// two-sided value rounds exactly as the CPU oracle's 0.5 * ((a + b) + s): the
+// fused 0.5 * s + 0.5 * (a + b) is that sum halved before its one rounding,
+// and halving commutes with rounding (no operand is near the underflow
+// range).  Contraction is otherwise off, so the remaining terms round as in
+// the oracle too.  a = b = +inf gives NaN, which the caller's minimum with the
+// old value turns into "no update".
 __device__ __forceinline__ double local_update(double a, double b, double dl) {
   const double lo = wave::vmin(a, b);  // a and b are never NaN
   const double d = a - b;
   const double one = lo + dl;
-  const double two = 0.5 * (a + b + sqrt_pos(2.0 * dl * dl - d * d));
+  const double two = fma(0.5, sqrt_pos(2.0 * dl * dl - d * d), 0.5 * (a + b));
   return (fabs(d) >= dl) ? one : two;
 }
 
@@ -118,7 +122,7 @@ __device__ __forceinline__ float local_update(float a, float b, float dl) {
   const float lo = wave::vmin(a, b);
   const double da = a, db = b, dd = da - db, ddl = dl;
   const float one = lo + dl;
-  const float two = (float)(0.5 * (da + db + sqrt_pos(2.0 * ddl * ddl - dd * dd)));
+  const float two = (float)fma(0.5, sqrt_pos(2.0 * ddl * ddl - dd * dd), 0.5 * (da + db));
   return (fabs(dd) >= ddl) ? one : two;
 }
 
@@ -239,46 +243,63 @@ __device__ __forceinline__ void order_acquire() {
 // cell queue (per-lane operations except q_pop)
 // ----------------------------------------------------------------------------
 
-__device__ __forceinline__ unsigned long long band_of(const Queue& q, double key) {
-  if (q.nb <= 1 || !(key > 0.0)) return 0;
-  const double b = key * q.inv_width;
-  return b < 1e15 ? (unsigned long long)b : 1000000000000000ull;
-}
-
 __device__ __forceinline__ unsigned long long* ctr(unsigned long long* base, uint32_t r) {
   return base + (size_t)r * kCtrStride;
 }
 
+// The rings of one group: the whole queue (ng = 1) or one problem's.
+// Counter index of the group's ring r: base + r.
+struct QView {
+  unsigned long long* slot;
+  unsigned long long* cursor;
+  uint32_t cap, base;
+  double inv_width;
+};
+__device__ __forceinline__ QView qview(const Queue& q, uint32_t g) {
+  if (q.ng <= 1) return QView{q.slot, q.cursor, q.cap, 0u, q.inv_width};
+  const QGroup G = q.grp[g];
+  return QView{q.slot + G.off, q.cursor + (size_t)g * kCtrStride, G.cap, g * q.nb, G.inv_width};
+}
+
+__device__ __forceinline__ unsigned long long band_of(const Queue& q, const QView& v, double key) {
+  if (q.nb <= 1 || !(key > 0.0)) return 0;
+  const double b = key * v.inv_width;
+  return b < 1e15 ? (unsigned long long)b : 1000000000000000ull;
+}
+
 // Appends `cell` to the ring of its band (clamped to the open bands
-// [cursor, cursor + nb)).  Every cell is in the queue at most once (guarded by
-// its state word) and cap > cells, so a producer only waits for a consumer
-// that has already claimed the slot's previous ticket.
+// [cursor, cursor + nb)) in its problem's group.  Every cell is in the queue
+// at most once (guarded by its state word) and cap > cells of the group, so a
+// producer only waits for a consumer that has already claimed the slot's
+// previous ticket.
 __device__ void q_push(const Engine& e, uint32_t cell, double key) {
   const Queue& q = e.q;
+  const QView v = qview(q, q.ng > 1 ? (uint32_t)e.cell_inst[cell] : 0u);
   uint32_t r = 0;
   if (q.nb > 1) {
-    const unsigned long long kb = band_of(q, key);
+    const unsigned long long kb = band_of(q, v, key);
     for (;;) {
-      const unsigned long long c = ld64(q.cursor);
+      const unsigned long long c = ld64(v.cursor);
       unsigned long long b = kb < c ? c : kb;
       if (b > c + q.nb - 1) b = c + q.nb - 1;
       r = (uint32_t)(b & (q.nb - 1));
-      const unsigned long long old = atomic_add_relaxed(ctr(q.inflight, r), 1ull);
+      const unsigned long long old = atomic_add_relaxed(ctr(q.inflight, v.base + r), 1ull);
       order_acquire();
       // band b still open and not yet passed by the cursor: the count now
       // held keeps the cursor from passing it
-      if (!(old & kClosed) && ld64(q.cursor) <= b) break;
-      atomic_add_relaxed(ctr(q.inflight, r), ~0ull);
+      if (!(old & kClosed) && ld64(v.cursor) <= b) break;
+      atomic_add_relaxed(ctr(q.inflight, v.base + r), ~0ull);
       if (past_deadline(e.ctl)) {
         set_err(e.ctl, kErrDeadline);
         return;
       }
     }
+    order_release();
   }
-  order_release();
-  const unsigned long long t = atomic_add_relaxed(ctr(q.tail, r), 1ull);
-  unsigned long long* s = q.slot + (size_t)r * q.cap + (t & (q.cap - 1));
-  while ((uint32_t)(ld64(s) >> 32) != (uint32_t)t) {
+  const unsigned long long t = atomic_add_relaxed(ctr(q.tail, v.base + r), 1ull);
+  unsigned long long* s = v.slot + (size_t)r * v.cap + (t & (v.cap - 1));
+  // on the ring's first lap every slot is free
+  while (t >= v.cap && (uint32_t)(ld64(s) >> 32) != (uint32_t)t) {
     if (past_deadline(e.ctl)) {
       set_err(e.ctl, kErrDeadline);
       return;
@@ -289,35 +310,67 @@ __device__ void q_push(const Engine& e, uint32_t cell, double key) {
   st_coh(s, ((t + 1ull) << 32) | cell);
 }
 
-// Moves the cursor past its band when no cell of that band is queued or
-// running.  One lane.
-__device__ void q_try_advance(const Engine& e) {
+// Moves a group's cursor past its band c when no cell of that band is queued
+// or running.  One lane.
+__device__ void q_advance(const Engine& e, const QView& v, unsigned long long c) {
   const Queue& q = e.q;
-  const unsigned long long c = ld64(q.cursor);
-  unsigned long long* fl = ctr(q.inflight, (uint32_t)(c & (q.nb - 1)));
+  unsigned long long* fl = ctr(q.inflight, v.base + (uint32_t)(c & (q.nb - 1)));
   unsigned long long z = 0ull;
   if (!__hip_atomic_compare_exchange_strong(fl, &z, kClosed, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                             __HIP_MEMORY_SCOPE_AGENT))
     return;
   order_acquire();
   unsigned long long cc = c;
-  const bool moved = __hip_atomic_compare_exchange_strong(q.cursor, &cc, c + 1ull, __ATOMIC_RELAXED,
+  const bool moved = __hip_atomic_compare_exchange_strong(v.cursor, &cc, c + 1ull, __ATOMIC_RELAXED,
                                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   order_release();
   __hip_atomic_fetch_and(fl, ~kClosed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (moved) atomic_add_relaxed(&e.ctl->band_steps, 1ull);
 }
 
+// Takes the cell at ticket h of counter ring r (group ring r - v.base) if
+// the head is still there (a few retries while h < t).  One lane; -1 if
+// nothing was taken.
+__device__ int q_take(const Engine& e, const QView& v, uint32_t r, unsigned long long h,
+                      unsigned long long t) {
+  const Queue& q = e.q;
+  unsigned long long* hp = ctr(q.head, r);
+  bool got = false;
+  for (int tries = 0; tries < 8 && h < t; ++tries) {
+    unsigned long long exp = h;
+    if (__hip_atomic_compare_exchange_strong(hp, &exp, h + 1ull, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+      got = true;
+      break;
+    }
+    h = exp;
+    t = ld64(ctr(q.tail, r));
+  }
+  if (!got) return -1;
+  unsigned long long* s = v.slot + (size_t)(r - v.base) * v.cap + (h & (v.cap - 1));
+  unsigned long long w;
+  for (;;) {
+    w = ld64(s);
+    if ((uint32_t)(w >> 32) == (uint32_t)(h + 1ull)) break;
+    if (past_deadline(e.ctl)) {
+      set_err(e.ctl, kErrDeadline);
+      return -1;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  st_coh(s, (h + (unsigned long long)v.cap) << 32);
+  return (int)(uint32_t)w;
+}
+
 // Wave-cooperative pop from the lowest non-empty band within the window;
-// returns the cell (or -1) and its ring in *ring.
+// returns the cell (or -1) and its counter ring in *ring.
 __device__ int q_pop(const Engine& e, int lane, int* ring) {
   const Queue& q = e.q;
-  unsigned long long cur = 0;
-  if (q.nb > 1) cur = ld64(q.cursor);
-  const uint32_t span = q.nb > 1 ? q.window + 1u : 1u;
+  const QView v = qview(q, 0u);
+  const unsigned long long cur = ld64(v.cursor);
   unsigned long long h = 0, t = 0;
   bool has = false;
-  if ((uint32_t)lane < span) {
+  if ((uint32_t)lane <= q.window) {
     const uint32_t r = (uint32_t)((cur + lane) & (q.nb - 1));
     h = ld64(ctr(q.head, r));
     t = ld64(ctr(q.tail, r));
@@ -325,46 +378,54 @@ __device__ int q_pop(const Engine& e, int lane, int* ring) {
   }
   const unsigned long long m = ballot(has);
   if (!m) {
-    if (q.nb > 1 && lane == 0) q_try_advance(e);
+    if (lane == 0) q_advance(e, v, cur);
     return -1;
   }
   const int k = __builtin_ctzll(m);
-  int cell = -1;
   const uint32_t r = (uint32_t)((cur + k) & (q.nb - 1));
-  if (lane == k) {
-    unsigned long long* hp = ctr(q.head, r);
-    bool got = false;
-    for (int tries = 0; tries < 8 && h < t; ++tries) {
-      unsigned long long exp = h;
-      if (__hip_atomic_compare_exchange_strong(hp, &exp, h + 1ull, __ATOMIC_RELAXED,
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-        got = true;
-        break;
-      }
-      h = exp;
-      t = ld64(ctr(q.tail, r));
-    }
-    if (got) {
-      unsigned long long* s = q.slot + (size_t)r * q.cap + (h & (q.cap - 1));
-      unsigned long long v;
-      for (;;) {
-        v = ld64(s);
-        if ((uint32_t)(v >> 32) == (uint32_t)(h + 1ull)) break;
-        if (past_deadline(e.ctl)) {
-          set_err(e.ctl, kErrDeadline);
-          v = ~0ull;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-      if (v != ~0ull) {
-        cell = (int)(uint32_t)v;
-        st_coh(s, (h + (unsigned long long)q.cap) << 32);
-      }
-    }
-  }
+  int cell = -1;
+  if (lane == k) cell = q_take(e, v, r, h, t);
   *ring = (int)r;
   return bcast(cell, k);
+}
+
+// Pop with one group per problem: lane l looks at group home + l (then
+// home + 64 + l, ...), the lowest non-empty band of that group's window, and
+// moves the cursor of a group whose window is empty; the first lane that
+// found a cell takes it.  Returns the cell (or -1) and its counter ring.
+__device__ int q_pop_groups(const Engine& e, int lane, uint32_t home, int* ring) {
+  const Queue& q = e.q;
+  for (uint32_t base = 0; base < q.ng; base += 64u) {
+    const uint32_t gi = base + (uint32_t)lane;
+    bool has = false;
+    uint32_t g = 0, r = 0;
+    unsigned long long h = 0, t = 0;
+    if (gi < q.ng) {
+      g = home + gi;
+      if (g >= q.ng) g -= q.ng;
+      const QView v = qview(q, g);
+      const unsigned long long cur = ld64(v.cursor);
+      for (uint32_t w = 0; w <= q.window; ++w) {
+        r = v.base + (uint32_t)((cur + w) & (q.nb - 1));
+        h = ld64(ctr(q.head, r));
+        t = ld64(ctr(q.tail, r));
+        if (h < t) {
+          has = true;
+          break;
+        }
+      }
+      if (!has && ld64(ctr(q.inflight, v.base + (uint32_t)(cur & (q.nb - 1)))) == 0ull)
+        q_advance(e, v, cur);
+    }
+    const unsigned long long m = ballot(has);
+    if (!m) continue;
+    const int k = __builtin_ctzll(m);
+    int cell = -1;
+    if (lane == k) cell = q_take(e, qview(q, g), r, h, t);
+    *ring = bcast((int)r, k);
+    return bcast(cell, k);
+  }
+  return -1;
 }
 
 // Blocking pop from a single FIFO ring (nb = 1).  The wave takes the next
@@ -1086,10 +1147,14 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
   unsigned long long nsweeps = 0, nchecks = 0;  // this wave's totals
   if constexpr (HEAP)  // the only worker: block minima of the cells queued so far
     for (int b = 0; b < ((e.ncells + 63) >> 6); ++b) heap_fix(e, b, lane);
+  // under per-problem groups a wave looks at the group of its own index first
+  const uint32_t home = e.q.ng > 1 ? blockIdx.x % e.q.ng : 0u;
   for (;;) {
     int ring = 0;
-    const int g = HEAP ? heap_pop(e, lane)
-                       : e.q.nb == 1 ? q_pop_ticket(e, lane) : q_pop(e, lane, &ring);
+    const int g = HEAP            ? heap_pop(e, lane)
+                  : e.q.nb == 1   ? q_pop_ticket(e, lane)
+                  : e.q.ng > 1    ? q_pop_groups(e, lane, home, &ring)
+                                  : q_pop(e, lane, &ring);
     if (g < 0) {
       const bool stop = HEAP || e.q.nb == 1 || ld64(&ctl->active) == 0ull || get_err(ctl) ||
                         past_deadline(ctl);
@@ -1108,24 +1173,23 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
     uint32_t fl = 0, ordb = 0, sides = 0;
     int first = 0, done1 = 0;
     uint32_t run_state = kRunning;  // the state word written by claim (lane 0)
+    // the claim's bookkeeping is spread over lanes 1-3 and issued before the
+    // claim itself, so the device-scope round trips overlap
+    if (lane == 1) first = atomic_add_relaxed(&e.visits[g], 1u) == 0u ? 1 : 0;
+    if (lane == 2 && atomic_add_relaxed(&ctl->visits, 1ull) >= e.guard) set_err(ctl, kErrGuard);
+    if (lane == 3 && e.dag) ordb = e.ord[g];
     if (lane == 0) {
       const uint32_t old = claim(e, g);
       run_state = (old & kDone1) | kRunning;
       fl = (old >> kFlagShift) & 0xFu;
       sides = (old >> kSideShift) & 0xFu;
       done1 = (old & kDone1) != 0u;
-      const uint32_t v = ld_coh(&e.visits[g]);
-      st_coh(&e.visits[g], v + 1u);
-      first = v == 0u;
-      if (e.dag) ordb = e.ord[g];
-      const unsigned long long tot = atomic_add_relaxed(&ctl->visits, 1ull);
-      if (tot >= ctl->guard) set_err(ctl, kErrGuard);
     }
     fl = (uint32_t)bcast((int)fl, 0);
     sides = (uint32_t)bcast((int)sides, 0);
-    ordb = (uint32_t)bcast((int)ordb, 0);
+    ordb = (uint32_t)bcast((int)ordb, 3);
     done1 = bcast(done1, 0);
-    bool is_first = bcast(first, 0) != 0;
+    bool is_first = bcast(first, 1) != 0;
     if (e.dag && !done1) sides |= ordb & 0xFu;
     // trace only: sweep history of the exact method, inflow sides and flags
     unsigned long long hist = e.trace ? ((unsigned long long)sides << 60 | (unsigned long long)fl << 56 |
@@ -1361,19 +1425,31 @@ __global__ void k_prep_cells(Engine e) {
       e.cell_inst[c] = lo;
     }
   }
-  const size_t nslot = (size_t)e.q.cap * e.q.nb;
-  for (size_t k = tid; k < nslot; k += stride)
-    e.q.slot[k] = (unsigned long long)(k & (e.q.cap - 1)) << 32;
+  // sequence 0: on the first lap a consumer waits for its producer (ticket
+  // h waits for sequence h + 1 >= 1) and a producer does not look
+  for (size_t k = tid; k < (size_t)e.q.nslot; k += stride) e.q.slot[k] = 0ull;
   for (size_t k = tid; k < 4 * (size_t)ninst; k += stride) e.istat[k] = 0ull;
   if (e.idone)
     for (size_t k = tid; k < (size_t)ninst; k += stride) e.iact[k] = 0ull;
-  for (size_t k = tid; k < (size_t)e.q.nb; k += stride) {
+  for (size_t k = tid; k < (size_t)e.q.nb * e.q.ng; k += stride) {
     e.q.head[k * kCtrStride] = 0ull;
     e.q.tail[k * kCtrStride] = 0ull;
     e.q.inflight[k * kCtrStride] = 0ull;
   }
+  for (size_t k = tid; k < (size_t)e.q.ng; k += stride) e.q.cursor[k * kCtrStride] = 0ull;
+  if (tid == 0 && e.q.ng > 1) {
+    // one group of bands per problem, in problem order
+    unsigned long long off = 0ull;
+    for (int k = 0; k < ninst; ++k) {
+      const Inst& I = e.inst[k];
+      uint32_t cap = 1u;
+      while (cap < (uint32_t)(I.kx * I.ky) + 1u) cap <<= 1;
+      const double w = e.q.width > 0.0 ? e.q.width : e.q.width_cells * I.s * I.h;
+      e.q.grp[k] = QGroup{off, cap, 0u, 1.0 / w, 0.0};
+      off += (unsigned long long)cap * e.q.nb;
+    }
+  }
   if (tid == 0) {
-    *e.q.cursor = 0ull;
     Ctl* c = e.ctl;
     c->active = 0ull;
     c->visits = 0ull;
@@ -2045,8 +2121,7 @@ static int grid_for(int64_t n, int block, int cap) {
 
 hipError_t launch_prepare(const Engine& e, int64_t max_nodes, hipStream_t stream) {
   const int gy = e.ninst;
-  const int64_t cwork = (int64_t)e.ncells > (int64_t)e.q.cap * e.q.nb
-                            ? (int64_t)e.ncells : (int64_t)e.q.cap * e.q.nb;
+  const int64_t cwork = (int64_t)e.ncells > (int64_t)e.q.nslot ? (int64_t)e.ncells : (int64_t)e.q.nslot;
   hipLaunchKernelGGL(k_prep_cells, dim3(grid_for(cwork, 256, 4096)), dim3(256), 0, stream, e);
   const dim3 gn(grid_for(max_nodes, 256, gy > 1 ? 512 : 8192), gy);
   if (e.dtype == 0) hipLaunchKernelGGL(k_prep_nodes<double>, gn, dim3(256), 0, stream, e);

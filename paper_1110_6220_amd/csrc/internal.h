@@ -52,7 +52,7 @@ struct DevBuf {
 // Buffers of one engine run.
 struct Solver {
   DevBuf delta, st, visits, cell_inst, key, deps, ord, slot, head, tail, inflight, cursor, ctl, inst;
-  DevBuf hblk, istat, iact;
+  DevBuf hblk, istat, iact, qgrp;
   void release();
   std::vector<DevBuf*> bufs();
 };
@@ -70,7 +70,7 @@ struct Plan {
   DevBuf inst, cinst, cout;
   std::vector<Inst> host_inst;
   int64_t J = 0;
-  double band = -1.0;
+  std::vector<double> widths;  // band widths (empty: no bands)
   bool coarse_engine = false, want_resid = false;
 };
 
@@ -141,10 +141,17 @@ struct RunCtx {
   std::function<void(const Engine&, const std::vector<Inst>&)> poll;
   const char* detached = nullptr;
 };
+// Band width of the band schedule: `width` if > 0, else `cells` times the
+// problem's cell crossing at unit speed (s h).
+struct BandSpec {
+  double width, cells;
+  double width_of(const Inst& I) const { return width > 0.0 ? width : cells * I.s * I.h; }
+};
 // Sizes the solver's buffers for the instances in `inst` (cell0 filled in)
-// and fills the engine arguments.
+// and fills the engine arguments.  band: the band schedule's widths, or
+// nullptr (no bands).
 int setup_engine(Solver& sv, std::vector<Inst>& inst, int dtype, int method, int dag, int heap,
-                 double band, int window, int eager, uint64_t guard, uint64_t timeout,
+                 const BandSpec* band, int window, int eager, uint64_t guard, uint64_t timeout,
                  hipStream_t stream, Engine* out, DevBuf* instbuf = nullptr);
 eik_opts default_opts();
 int check_opts(const eik_opts& o);

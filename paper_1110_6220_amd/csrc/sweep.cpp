@@ -74,7 +74,7 @@ int sweep_solve(const eik_problem& p, const eik_sweep_opts& o, double* max_chang
   std::vector<Inst> inst{I};
   Engine e;
   const uint64_t timeout = (uint64_t)ws->wall_khz * 10000ull;
-  if ((rc = setup_engine(ws->fine, inst, dt, EIK_EXACT, 0, 0, -1.0, 0, 0, 0, timeout, stream, &e))) return rc;
+  if ((rc = setup_engine(ws->fine, inst, dt, EIK_EXACT, 0, 0, nullptr, 0, 0, 0, timeout, stream, &e))) return rc;
   const int kx = I.kx, ky = I.ky, J = kx * ky;
   HIP_TRY(ws->sweep_stat.ensure(4 * sizeof(unsigned long long)));
   HIP_TRY(ws->sweep_dirty.ensure(J));

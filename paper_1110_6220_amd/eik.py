@@ -41,7 +41,8 @@ class Opts(ctypes.Structure):
                 ("residual_check", ctypes.c_int32), ("workers", ctypes.c_int32),
                 ("band_window", ctypes.c_int32), ("eager_publish", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("timeout_ms", ctypes.c_int32),
-                ("graph", ctypes.c_int32), ("residual_tol", ctypes.c_double)]
+                ("graph", ctypes.c_int32), ("residual_tol", ctypes.c_double),
+                ("band_cells", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -138,11 +139,11 @@ def _is_torch(x) -> bool:
 
 def _opts(dtype, method, cell, band, device, stream, residual_check, workers, max_cell_visits,
           band_window=0, eager_publish=False, schedule="auto", timeout_ms=0, graph=False,
-          residual_tol=0.0):
+          residual_tol=0.0, band_cells=0.0):
     return Opts(dtype, METHODS[method], int(cell), float(band), int(device),
                 stream, int(max_cell_visits), int(bool(residual_check)), int(workers),
                 int(band_window), int(bool(eager_publish)), SCHEDULES[schedule], int(timeout_ms),
-                int(bool(graph)), float(residual_tol))
+                int(bool(graph)), float(residual_tol), float(band_cells))
 
 
 def _check_arrays(shape, mask, q, nsrc, u_out, out_dtype, device):
@@ -219,13 +220,13 @@ def _stream_of(device: bool):
 def eik_solve(F, h, src, q=None, mask=None, u_out=None, *, dtype="f64", method="exact",
               cell=0, band=0.0, workers=0, residual_check=False, max_cell_visits=0,
               band_window=0, eager_publish=False, schedule="auto", timeout_ms=0, graph=False,
-              residual_tol=0.0):
+              residual_tol=0.0, band_cells=0.0):
     """Solves |grad u| F = 1 with u = q on src (see include/eik.h).
     Returns (u, stats dict)."""
     p, keep, u_out, device = _marshal(F, h, src, q, mask, u_out, dtype)
     o = _opts(F64 if dtype == "f64" else F32, method, cell, band, device, _stream_of(device),
               residual_check, workers, max_cell_visits, band_window, eager_publish, schedule,
-              timeout_ms, graph, residual_tol)
+              timeout_ms, graph, residual_tol, band_cells)
     st = Stats()
     _check(lib.eik_solve(p.nx, p.ny, p.h, p.F, p.mask, p.nsrc, p.src, p.q, p.u_out,
                          ctypes.byref(o), ctypes.byref(st)))
@@ -236,7 +237,7 @@ def eik_solve(F, h, src, q=None, mask=None, u_out=None, *, dtype="f64", method="
 def eik_solve_batched(problems, *, dtype="f64", method="exact", cell=0, band=0.0, workers=0,
                       residual_check=False, max_cell_visits=0, band_window=0,
                       eager_publish=False, schedule="auto", timeout_ms=0, graph=False,
-                      residual_tol=0.0):
+                      residual_tol=0.0, band_cells=0.0):
     """problems: list of dicts with F, h, src and optional q, mask, u_out.
     Returns (list of u, list of stats dicts)."""
     ps, keeps, outs = [], [], []
@@ -254,7 +255,7 @@ def eik_solve_batched(problems, *, dtype="f64", method="exact", cell=0, band=0.0
     arr = (Problem * len(ps))(*ps)
     o = _opts(F64 if dtype == "f64" else F32, method, cell, band, device, _stream_of(device),
               residual_check, workers, max_cell_visits, band_window, eager_publish, schedule,
-              timeout_ms, graph, residual_tol)
+              timeout_ms, graph, residual_tol, band_cells)
     st = (Stats * len(ps))()
     _check(lib.eik_solve_batched(len(ps), arr, ctypes.byref(o), st))
     del keeps
@@ -404,7 +405,7 @@ class Batch:
 
     def __init__(self, problems, *, dtype="f64", method="exact", cell=0, band=0.0, workers=0,
                  residual_check=False, max_cell_visits=0, band_window=0, eager_publish=False,
-                 schedule="auto", timeout_ms=0, graph=True, residual_tol=0.0):
+                 schedule="auto", timeout_ms=0, graph=True, residual_tol=0.0, band_cells=0.0):
         ps, self._keep, self.outputs = [], [], []
         device = None
         for w in problems:
@@ -422,14 +423,14 @@ class Batch:
         self._device = device
         self._args = (F64 if dtype == "f64" else F32, method, cell, band, device, residual_check,
                       workers, max_cell_visits, band_window, eager_publish, schedule, timeout_ms,
-                      graph, residual_tol)
+                      graph, residual_tol, band_cells)
         self._stats = (Stats * self._n)()
 
     def solve(self):
         """Solves the batch into self.outputs; returns the stats dicts."""
         (dt, method, cell, band, device, resid, workers, mcv, bw, eager, sched, tmo,
-         graph, rtol) = self._args
+         graph, rtol, bcells) = self._args
         o = _opts(dt, method, cell, band, device, _stream_of(device), resid, workers, mcv, bw,
-                  eager, sched, tmo, graph, rtol)
+                  eager, sched, tmo, graph, rtol, bcells)
         _check(lib.eik_solve_batched(self._n, self._arr, ctypes.byref(o), self._stats))
         return [s.as_dict() for s in self._stats]

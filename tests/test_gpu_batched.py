@@ -58,6 +58,40 @@ def test_small_batch_fp32_with_residual_check(eik):
     assert 0.0 <= st[0]["max_residual"]
 
 
+def test_batch_band_groups(eik):
+    """Batches under the band schedule: each problem has its own group of
+    bands (own cursor, width a multiple of its own s h).  Exact results under
+    the tuned width and under explicit widths and windows (the Theorem of
+    Section 3.2.1: any order converges to the discrete solution); FHCM in a
+    batch within the accuracy of the serial oracle FHCM."""
+    ws = W.batch_bumps(count=20, seed=44, n_lo=17, n_hi=260)
+    ws += [W.random_small(np.random.default_rng(45), 90, 70, obst=0.1, nsrc=2, q_spread=0.2),
+           W.random_small(np.random.default_rng(46), 1, 40)]
+    refs = [O.fmm(O.Problem.from_workload(w)) for w in ws]
+    for kw in ({}, dict(band=0.05, band_window=3), dict(band=1e-9), dict(band=1e9, band_window=63),
+               dict(band_cells=2.0, band_window=1)):
+        got, st = run_batched(eik, ws, schedule="bands", **kw)
+        for w, g, U in zip(ws, got, refs):
+            assert max_rel(g, U) <= 1e-12, (w["name"], kw)
+        if "band" in kw:
+            assert all(s["band_used"] == kw["band"] for s in st)
+        else:
+            # a multiple of each problem's own cell crossing s h
+            ratio = [s["band_used"] / (s["cell_used"] * w["h"]) for s, w in zip(st, ws)]
+            assert min(ratio) > 0 and max(ratio) <= min(ratio) * (1 + 1e-12), ratio
+            if "band_cells" in kw:
+                assert abs(ratio[0] - kw["band_cells"]) <= 1e-12
+        assert st[0]["band_steps"] > 0
+    fh = [W.smooth_sine(97), W.smooth_sine(129, amp=0.99), W.gaussian_bumps(150, np.random.default_rng(47))]
+    got, st = run_batched(eik, fh, method="fhcm", cell=16)
+    for w, g in zip(fh, got):
+        p = O.Problem.from_workload(w)
+        U = O.fmm(p)
+        Vo, _ = O.fhcm(p, 16)
+        assert (g >= U * (1 - 1e-14)).all(), w["name"]
+        assert np.abs(g - U).max() <= 10 * np.abs(Vo - U).max() + 1e-12, w["name"]
+
+
 def test_fmsm_batched_bitwise(eik):
     ws = W.batch_bumps(count=8, seed=43, n_lo=40, n_hi=180)
     got, _ = run_batched(eik, ws, method="fmsm", cell=16)
