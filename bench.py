@@ -178,7 +178,7 @@ def main():
                     help="also run a plain device copy of known size (counter scaling)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the sub-records (batched, serving, studies)")
-    ap.add_argument("--serve-requests", type=int, default=500)
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--no-comparator", action="store_true",
                     help="batched: skip the one-launch-per-instance comparator (profiling runs)")
     ap.add_argument("--no-graph", action="store_true",

@@ -15,8 +15,10 @@ above the lowest that may start (the window) set how far the concurrent
 order strays from the heap order of Section 3.2.2.  For the exact method that
 is again speed only.  For FHCM it also moves the error, so a width qualifies
 only if the FHCM result stays as close to the exact discrete solution as the
-serial heap order's (max error at most 1.1 times the heap order's on every
-sample).  --bands times the candidates and writes csrc/tuned_bands.h.
+serial heap order's: max error over the samples at most 1.1 times the heap
+order's, in the worse of two runs, both measured in FP64 (for the FP32 rows
+too: FP32 rounding would mask the order's effect).  --bands times the candidates and
+writes csrc/tuned_bands.h.
 
     python -m paper_1110_6220_amd.autotune --out paper_1110_6220_amd/csrc/tuned_cells.h
     python -m paper_1110_6220_amd.autotune --bands --out paper_1110_6220_amd/csrc/tuned_bands.h
@@ -151,7 +153,9 @@ def tune_bands(dtypes=("f64", "f32"), log=print):
                 continue
             tdt = torch.float64 if dtype == "f64" else torch.float32
             for batched in (0, 1):
-                rng = np.random.default_rng(2000 + 7 * mcode + 3 * dt_code + batched)
+                # the same samples for both precisions (FHCM's choice rests on
+                # FP64 errors either way)
+                rng = np.random.default_rng(2000 + 7 * mcode + batched)
                 ws = _band_samples(batched, rng)
                 ds = []
                 for w in ws:
@@ -162,35 +166,43 @@ def tune_bands(dtypes=("f64", "f32"), log=print):
                         d["mask"] = torch.from_numpy(w["mask"]).to(dev)
                     ds.append(d)
 
-                def solve_all(**kw):
+                ds64 = [dict(d, F=d["F"].double()) for d in ds]
+
+                def solve_all(prec=dtype, **kw):
+                    dd = ds if prec == dtype else ds64
                     if batched:
-                        us, _ = eik.eik_solve_batched(ds, dtype=dtype, method=method,
+                        us, _ = eik.eik_solve_batched(dd, dtype=prec, method=method,
                                                       schedule="bands", **kw)
                         return us
                     return [eik.eik_solve(d["F"], d["h"], d["src"], d["q"], d.get("mask"),
-                                          dtype=dtype, method=method, schedule="bands", **kw)[0]
-                            for d in ds]
+                                          dtype=prec, method=method, schedule="bands", **kw)[0]
+                            for d in dd]
 
-                ok_err = None
+                heap_err = None
                 if method == "fhcm":
-                    # the exact discrete solutions and the serial heap order's errors
-                    ex = [eik.eik_solve(d["F"], d["h"], d["src"], d["q"], d.get("mask"), dtype=dtype)[0]
-                          for d in ds]
-                    hp = [eik.eik_solve(d["F"], d["h"], d["src"], d["q"], d.get("mask"), dtype=dtype,
-                                        method="fhcm", schedule="heap")[0] for d in ds]
-                    ok_err = [float((a.double() - b.double()).abs().nan_to_num(0.0).max()) for a, b in zip(hp, ex)]
+                    # errors are taken in FP64 for both precisions (FP32
+                    # rounding would mask the order's effect): the exact
+                    # discrete solutions and the serial heap order's error
+                    # over the samples
+                    ex = [eik.eik_solve(d["F"], d["h"], d["src"], d["q"], d.get("mask"))[0] for d in ds64]
+
+                    def err(us):
+                        return max(float((u.double() - e).abs().nan_to_num(0.0).max())
+                                   for u, e in zip(us, ex))
+                    heap_err = err([eik.eik_solve(d["F"], d["h"], d["src"], d["q"], d.get("mask"),
+                                                  method="fhcm", schedule="heap")[0] for d in ds64])
                 times, errs = {}, {}
                 for f in BAND_FACTORS:
                     for win in BAND_WINDOWS:
                         # an explicit width: f cell crossings of each problem
                         kw = dict(band_cells=f, band_window=win)
                         times[(f, win)] = _time(lambda: solve_all(**kw))
-                        if ok_err is not None:
-                            us = solve_all(**kw)
-                            errs[(f, win)] = max(
-                                float((u.double() - e.double()).abs().nan_to_num(0.0).max()) / max(o, 1e-300)
-                                for u, e, o in zip(us, ex, ok_err))
-                ok = [c for c in times if ok_err is None or errs[c] <= FHCM_ERR_SLACK]
+                        if heap_err is not None:
+                            # the concurrent order varies from run to run:
+                            # the worse of two runs
+                            errs[(f, win)] = max(err(solve_all("f64", **kw)),
+                                                 err(solve_all("f64", **kw))) / max(heap_err, 1e-300)
+                ok = [c for c in times if heap_err is None or errs[c] <= FHCM_ERR_SLACK]
                 if not ok:
                     ok = [(1.0, 0)]
                 best = min(ok, key=times.get)
@@ -213,7 +225,7 @@ def write_bands_header(path, rows, notes, device_name):
         "// (--bands) on " + device_name + ".  Row: method (0 exact, 2 FHCM), dtype",
         "// (0 f64, 1 f32), batched (problems per launch > 1), width in cell",
         "// crossings s h, window.  Measurements (median of 3; width/window: time,",
-        f"// FHCM: max error / the heap order's, must be <= {FHCM_ERR_SLACK}):",
+        f"// FHCM: max error / the heap order's, worse of 2 runs, must be <= {FHCM_ERR_SLACK}):",
     ]
     lines += ["//   " + n for n in notes]
     lines += ["#pragma once", "namespace eik {", "struct TunedBand {", "  int method, dtype, batched;",

@@ -87,7 +87,7 @@ void DevBuf::release() {
 
 std::vector<DevBuf*> Solver::bufs() {
   return {&delta, &st,   &visits,   &cell_inst, &key, &deps, &ord,  &slot,  &head,
-          &tail,  &inflight, &cursor, &ctl,      &inst, &hblk, &istat, &iact, &qgrp};
+          &tail,  &inflight, &cursor, &ctl,      &inst, &hblk, &istat, &iact, &qgrp, &queued};
 }
 
 void Solver::release() {
@@ -389,6 +389,7 @@ int setup_engine(Solver& sv, std::vector<Inst>& inst, int dtype, int method, int
   HIP_TRY(sv.tail.ensure((size_t)ng * nb * kCtrStride * sizeof(unsigned long long)));
   HIP_TRY(sv.inflight.ensure((size_t)ng * nb * kCtrStride * sizeof(unsigned long long)));
   HIP_TRY(sv.cursor.ensure((size_t)ng * kCtrStride * sizeof(unsigned long long)));
+  HIP_TRY(sv.queued.ensure((size_t)ng * kCtrStride * sizeof(unsigned long long)));
   HIP_TRY(sv.qgrp.ensure((size_t)ng * sizeof(QGroup)));
   HIP_TRY(sv.ctl.ensure(sizeof(Ctl)));
   HIP_TRY(ib.ensure(n * sizeof(Inst)));
@@ -419,6 +420,7 @@ int setup_engine(Solver& sv, std::vector<Inst>& inst, int dtype, int method, int
   e.q.tail = sv.tail.as<unsigned long long>();
   e.q.inflight = sv.inflight.as<unsigned long long>();
   e.q.cursor = sv.cursor.as<unsigned long long>();
+  e.q.queued = sv.queued.as<unsigned long long>();
   e.q.grp = sv.qgrp.as<QGroup>();
   e.q.cap = cap;
   e.q.nb = nb;

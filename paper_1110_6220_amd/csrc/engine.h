@@ -77,6 +77,8 @@ struct Queue {
   unsigned long long* tail;      // ng * nb entries, stride kCtrStride
   unsigned long long* inflight;  // ng * nb entries, stride kCtrStride
   unsigned long long* cursor;    // ng entries, stride kCtrStride
+  unsigned long long* queued;    // ng > 1: per group the cells pushed and not yet
+                                 // popped (a hint for the scan), stride kCtrStride
   QGroup* grp;                   // ng entries (ng > 1)
   uint32_t cap;                  // power of two > number of cells (ng = 1)
   uint32_t nb;                   // power of two

@@ -198,13 +198,16 @@ __device__ __forceinline__ unsigned get_err(const Ctl* c) {
                            __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Adds the ticks since *t0 to counter c (lane 0, when profiling) and
-// restarts the clock.
-__device__ __forceinline__ void tick(const Engine& e, unsigned long long* c,
-                                     unsigned long long* t0, int lane) {
+// Profiling phases of a wave's time (summed in registers, added to the
+// control block's t_idle .. t_finish once when the wave leaves).
+enum Phase { kPhIdle, kPhClaim, kPhLoad, kPhSweep, kPhPublish, kPhFinish, kPhases };
+
+// Adds the ticks since *t0 to phase k (when profiling) and restarts the clock.
+__device__ __forceinline__ void tick(const Engine& e, unsigned long long* ph, int k,
+                                     unsigned long long* t0) {
   if (!e.profile) return;
   const unsigned long long t = wall_clock64();
-  if (lane == 0) atomic_add_relaxed(c, t - *t0);
+  ph[k] += t - *t0;
   *t0 = t;
 }
 
@@ -308,6 +311,7 @@ __device__ void q_push(const Engine& e, uint32_t cell, double key) {
   }
   order_release();
   st_coh(s, ((t + 1ull) << 32) | cell);
+  if (q.ng > 1) atomic_add_relaxed(q.queued + (size_t)(v.base / q.nb) * kCtrStride, 1ull);
 }
 
 // Moves a group's cursor past its band c when no cell of that band is queued
@@ -390,9 +394,11 @@ __device__ int q_pop(const Engine& e, int lane, int* ring) {
 }
 
 // Pop with one group per problem: lane l looks at group home + l (then
-// home + 64 + l, ...), the lowest non-empty band of that group's window, and
-// moves the cursor of a group whose window is empty; the first lane that
-// found a cell takes it.  Returns the cell (or -1) and its counter ring.
+// home + 64 + l, ...).  A group with cells queued: the lowest non-empty band
+// of its window, or, with the window empty, its cursor moves on; the first
+// lane that found a cell takes it.  Returns the cell (or -1) and its counter
+// ring.  The queued counts only steer the scan: a count read too low delays a
+// cell to a later scan, one read too high costs a look at the group.
 __device__ int q_pop_groups(const Engine& e, int lane, uint32_t home, int* ring) {
   const Queue& q = e.q;
   for (uint32_t base = 0; base < q.ng; base += 64u) {
@@ -403,6 +409,8 @@ __device__ int q_pop_groups(const Engine& e, int lane, uint32_t home, int* ring)
     if (gi < q.ng) {
       g = home + gi;
       if (g >= q.ng) g -= q.ng;
+    }
+    if (gi < q.ng && ld64(q.queued + (size_t)g * kCtrStride) != 0ull) {
       const QView v = qview(q, g);
       const unsigned long long cur = ld64(v.cursor);
       for (uint32_t w = 0; w <= q.window; ++w) {
@@ -421,7 +429,10 @@ __device__ int q_pop_groups(const Engine& e, int lane, uint32_t home, int* ring)
     if (!m) continue;
     const int k = __builtin_ctzll(m);
     int cell = -1;
-    if (lane == k) cell = q_take(e, qview(q, g), r, h, t);
+    if (lane == k) {
+      cell = q_take(e, qview(q, g), r, h, t);
+      if (cell >= 0) atomic_add_relaxed(q.queued + (size_t)g * kCtrStride, ~0ull);
+    }
     *ring = bcast((int)r, k);
     return bcast(cell, k);
   }
@@ -1076,7 +1087,10 @@ __device__ void release_later(const Engine& e, int g, const Inst& I, const CellB
 // problems, where compute units are plentiful) waves 1..NW-1 only share the
 // tile loads and stores, which one wave issues at one row transfer per
 // ~70-90 cycles.
-constexpr int kSolveWaves1 = 4;  // waves per worker for single problems
+#ifndef EIK_SOLVE_WAVES1
+#define EIK_SOLVE_WAVES1 4
+#endif
+constexpr int kSolveWaves1 = EIK_SOLVE_WAVES1;  // waves per worker for single problems
 
 // LDS of a tile with pitch P: one guard row, the (P x P) tile with its halo,
 // 64 per-lane dummy slots and one guard element.  The sweep reads the next
@@ -1144,6 +1158,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
   if (!get_err(ctl)) {
   int backoff = 0;
   unsigned long long t0 = e.profile ? wall_clock64() : 0ull;
+  unsigned long long ph[kPhases] = {0, 0, 0, 0, 0, 0};
   unsigned long long nsweeps = 0, nchecks = 0;  // this wave's totals
   if constexpr (HEAP)  // the only worker: block minima of the cells queued so far
     for (int b = 0; b < ((e.ncells + 63) >> 6); ++b) heap_fix(e, b, lane);
@@ -1161,10 +1176,11 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
       if (stop) break;
       if (backoff < 8) ++backoff;
       for (int z = 0; z < backoff; ++z) __builtin_amdgcn_s_sleep(2);
-      tick(e, &ctl->t_idle, &t0, lane);
+      tick(e, ph, kPhIdle, &t0);
       continue;
     }
     backoff = 0;
+    tick(e, ph, kPhIdle, &t0);  // waiting for a cell, the pop included
     unsigned long long tr[5] = {0, 0, 0, 0, 0};
     const unsigned long long sw0 = nsweeps, ch0 = nchecks;
     if (e.trace) tr[0] = wall_clock64();
@@ -1198,7 +1214,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
     order_acquire();
     if constexpr (HEAP) heap_fix(e, g >> 6, lane);  // g is running now
     int nvis = 1;                           // removals of g in this loop
-    tick(e, &ctl->t_claim, &t0, lane);
+    tick(e, ph, kPhClaim, &t0);
     if (e.trace) tr[3] = wall_clock64();
     // a cell's interior is written only by its own processing
     tile_load(I, B, g, true, e.dag && is_first && !(ordb & kOrdSource));
@@ -1207,7 +1223,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
     pub[1] = lane < B.hgt ? tu[(lane + 1) * P + B.w] : inf_v<T>();
     pub[2] = lane < B.w ? tu[P + lane + 1] : inf_v<T>();
     pub[3] = lane < B.w ? tu[B.hgt * P + lane + 1] : inf_v<T>();
-    tick(e, &ctl->t_load, &t0, lane);
+    tick(e, ph, kPhLoad, &t0);
     if (e.trace) tr[1] = wall_clock64();
     bool aborted = false;
     for (;;) {
@@ -1231,7 +1247,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
               if (ch) nsweeps++; else nchecks++;
             }
         }
-        tick(e, &ctl->t_sweep, &t0, lane);
+        tick(e, ph, kPhSweep, &t0);
       } else if constexpr (M == kFhcm) {
         // one non-directional sweep per flagged direction, canonical order
 #pragma nounroll
@@ -1240,10 +1256,10 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
             const bool ch = sweep_tile<T, P, false>(tu, td, B.w, B.hgt, d, lane) & 1u;
             if (ch) nsweeps++; else nchecks++;
           }
-        tick(e, &ctl->t_sweep, &t0, lane);
+        tick(e, ph, kPhSweep, &t0);
         publish<T, P, M>(e, I, B, g, tu, td, pub, is_first, lane);
         is_first = false;
-        tick(e, &ctl->t_publish, &t0, lane);
+        tick(e, ph, kPhPublish, &t0);
       } else {
         // exact: the first sweep starts in a corner between two sides with
         // inflow (one-axis inflow: a corner of such a side), else in a
@@ -1259,11 +1275,11 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
           const uint32_t res = sweep_tile<T, P, false>(tu, td, B.w, B.hgt, dir, lane);
           const bool ch = res & 1u;
           if (ch) nsweeps++; else nchecks++;
-          tick(e, &ctl->t_sweep, &t0, lane);
+          tick(e, ph, kPhSweep, &t0);
           if (e.eager && (ch || is_first)) {
             publish<T, P, M>(e, I, B, g, tu, td, pub, is_first, lane);
             is_first = false;
-            tick(e, &ctl->t_publish, &t0, lane);
+            tick(e, ph, kPhPublish, &t0);
           }
           if (e.trace && k < 11) hist |= (unsigned long long)(dir | (res << 2)) << (5 * k);
           if (!(res & 6u)) break;  // no change, or no backflow: converged
@@ -1289,7 +1305,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
         if (!e.eager) {
           publish<T, P, M>(e, I, B, g, tu, td, pub, is_first, lane);
           is_first = false;
-          tick(e, &ctl->t_publish, &t0, lane);
+          tick(e, ph, kPhPublish, &t0);
         }
       }
       if (aborted) break;
@@ -1333,7 +1349,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
         }
       }
       again = bcast(again, 0);
-      tick(e, &ctl->t_finish, &t0, lane);
+      tick(e, ph, kPhFinish, &t0);
       if (!again) {
         if constexpr (HEAP) {  // g is idle, its neighbours may be pending with lower keys
           const int kx = __builtin_amdgcn_readfirstlane(I.kx);
@@ -1382,6 +1398,10 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
     if (!get_err(ctl) && ld64(&ctl->active) != 0ull) set_err(ctl, kErrDeadline);
     atomic_add_relaxed(&ctl->sweeps, nsweeps);
     atomic_add_relaxed(&ctl->checks, nchecks);
+    if (e.profile) {
+      unsigned long long* c = &ctl->t_idle;  // t_idle .. t_finish in phase order
+      for (int k = 0; k < kPhases; ++k) atomic_add_relaxed(c + k, ph[k]);
+    }
   }
   }  // !get_err at entry
   if constexpr (NW > 1) {  // release the helper waves
@@ -1436,7 +1456,10 @@ __global__ void k_prep_cells(Engine e) {
     e.q.tail[k * kCtrStride] = 0ull;
     e.q.inflight[k * kCtrStride] = 0ull;
   }
-  for (size_t k = tid; k < (size_t)e.q.ng; k += stride) e.q.cursor[k * kCtrStride] = 0ull;
+  for (size_t k = tid; k < (size_t)e.q.ng; k += stride) {
+    e.q.cursor[k * kCtrStride] = 0ull;
+    e.q.queued[k * kCtrStride] = 0ull;
+  }
   if (tid == 0 && e.q.ng > 1) {
     // one group of bands per problem, in problem order
     unsigned long long off = 0ull;
@@ -1698,7 +1721,6 @@ __device__ void coarse_fmm(const CoarseOut& C, int kx, int ky, double hc, int la
                            double* dl, double* fv, IdxT* st, IdxT* fi) {
   const int J = kx * ky;
   const double INF = __builtin_huge_val();
-  auto fval = [&](int t) { return FV ? fv[t] : V[fi[t]]; };
   auto step_sync = [] {
     if constexpr (FV) {
       __syncthreads();

@@ -52,7 +52,7 @@ struct DevBuf {
 // Buffers of one engine run.
 struct Solver {
   DevBuf delta, st, visits, cell_inst, key, deps, ord, slot, head, tail, inflight, cursor, ctl, inst;
-  DevBuf hblk, istat, iact, qgrp;
+  DevBuf hblk, istat, iact, qgrp, queued;
   void release();
   std::vector<DevBuf*> bufs();
 };

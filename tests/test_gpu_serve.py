@@ -32,7 +32,7 @@ def test_alone_equals_mix(eik, dtype):
     U = O.fmm(O.Problem.from_workload(target))
     with eik.Server(256 << 20, lanes=4, dtype=dtype, residual_check=(dtype == "f32")) as srv:
         print(f"[gpu] serve alone {target['name']} {dtype}", flush=True)
-        alone, _ = srv.wait(submit(srv, target))
+        alone, st_alone = srv.wait(submit(srv, target))
         print(f"[gpu] serve mix of {len(reqs)} {dtype}", flush=True)
         tickets = [submit(srv, w) for w in reqs]
         res = [srv.wait(t) for t in tickets]
@@ -48,7 +48,12 @@ def test_alone_equals_mix(eik, dtype):
         b = f32_bound(target, U)
         assert max_abs(alone.astype(np.float64), U) <= b
         assert max_abs(mix.astype(np.float64), U) <= b
-        assert max_abs(mix.astype(np.float64), alone.astype(np.float64)) <= b
+        # FP32 storage: every update is evaluated in FP64 and rounded once, a
+        # monotone map, so the fixed point does not depend on the order in
+        # which cells were processed: bit for bit the same alone and in the
+        # mix (unless exactly one of the two runs fell back to FP64)
+        if bool(st_alone["fell_back_to_f64"]) == bool(res[7][1]["fell_back_to_f64"]):
+            assert np.array_equal(mix, alone)
 
 
 def test_small_budget_admits_in_turn(eik):
