@@ -42,7 +42,9 @@ double now_s() {
 }
 
 // EIK_PROFILE=1 makes the solver accumulate per-phase wall-clock ticks,
-// reported on stderr after each call (a diagnostic, off by default).
+// reported on stderr after each call (a diagnostic, off by default; the
+// device side is compiled in only when the library is built with
+// -DEIK_PROFILING).
 static const bool g_profile = [] {
   const char* v = std::getenv("EIK_PROFILE");
   return v && v[0] == '1';

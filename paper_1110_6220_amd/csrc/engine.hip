@@ -198,17 +198,26 @@ __device__ __forceinline__ unsigned get_err(const Ctl* c) {
                            __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Profiling phases of a wave's time (summed in registers, added to the
-// control block's t_idle .. t_finish once when the wave leaves).
+// Profiling phases of a wave's time, summed in registers and added to the
+// control block's t_idle .. t_finish once when the wave leaves.  Compiled in
+// only with -DEIK_PROFILING (the sums cost registers); then EIK_PROFILE=1
+// switches them on.
 enum Phase { kPhIdle, kPhClaim, kPhLoad, kPhSweep, kPhPublish, kPhFinish, kPhases };
+#ifdef EIK_PROFILING
+constexpr bool kProfiling = true;
+#else
+constexpr bool kProfiling = false;
+#endif
 
 // Adds the ticks since *t0 to phase k (when profiling) and restarts the clock.
 __device__ __forceinline__ void tick(const Engine& e, unsigned long long* ph, int k,
                                      unsigned long long* t0) {
-  if (!e.profile) return;
-  const unsigned long long t = wall_clock64();
-  ph[k] += t - *t0;
-  *t0 = t;
+  if constexpr (kProfiling) {
+    if (!e.profile) return;
+    const unsigned long long t = wall_clock64();
+    ph[k] += t - *t0;
+    *t0 = t;
+  }
 }
 
 // Ordering between waves.  Every value the waves share (solution values,
@@ -1087,10 +1096,7 @@ __device__ void release_later(const Engine& e, int g, const Inst& I, const CellB
 // problems, where compute units are plentiful) waves 1..NW-1 only share the
 // tile loads and stores, which one wave issues at one row transfer per
 // ~70-90 cycles.
-#ifndef EIK_SOLVE_WAVES1
-#define EIK_SOLVE_WAVES1 4
-#endif
-constexpr int kSolveWaves1 = EIK_SOLVE_WAVES1;  // waves per worker for single problems
+constexpr int kSolveWaves1 = 4;  // waves per worker for single problems
 
 // LDS of a tile with pitch P: one guard row, the (P x P) tile with its halo,
 // 64 per-lane dummy slots and one guard element.  The sweep reads the next
@@ -1157,7 +1163,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
   Ctl* ctl = e.ctl;
   if (!get_err(ctl)) {
   int backoff = 0;
-  unsigned long long t0 = e.profile ? wall_clock64() : 0ull;
+  unsigned long long t0 = kProfiling && e.profile ? wall_clock64() : 0ull;
   unsigned long long ph[kPhases] = {0, 0, 0, 0, 0, 0};
   unsigned long long nsweeps = 0, nchecks = 0;  // this wave's totals
   if constexpr (HEAP)  // the only worker: block minima of the cells queued so far
@@ -1398,7 +1404,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
     if (!get_err(ctl) && ld64(&ctl->active) != 0ull) set_err(ctl, kErrDeadline);
     atomic_add_relaxed(&ctl->sweeps, nsweeps);
     atomic_add_relaxed(&ctl->checks, nchecks);
-    if (e.profile) {
+    if (kProfiling && e.profile) {
       unsigned long long* c = &ctl->t_idle;  // t_idle .. t_finish in phase order
       for (int k = 0; k < kPhases; ++k) atomic_add_relaxed(c + k, ph[k]);
     }
