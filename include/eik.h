@@ -206,7 +206,7 @@ int eik_solve_batched(int32_t n, const eik_problem* probs, const eik_opts* opts,
 typedef struct {
   uint64_t hbm_budget_bytes;  /* device arena; 0 = 64 GiB                      */
   int32_t max_slots;          /* requests admitted at once; 0 = 1024           */
-  int32_t lanes;              /* concurrent launches, 0..16; 0 = 4             */
+  int32_t lanes;              /* concurrent launches, 0..16; 0 = 2             */
   eik_opts opts;
 } eik_serve_cfg;
 
