@@ -796,8 +796,9 @@ __device__ __forceinline__ CellBox cell_box(const Inst& I, int local) {
 // delta into LDS; outside the grid: +inf.  Rows go straight from memory into
 // LDS (global_load_lds: each active lane moves 16 bytes of the row), so the
 // loads of every row of the tile are in flight together without holding any
-// data in registers; u is read with the coherent policy (sc1) because
-// neighbouring cells write it concurrently.  The west and east halo columns
+// data in registers (the cell solver uses load_tile_v below, through
+// registers, which is faster where the registers suffice); u is read with the
+// coherent policy (sc1) because neighbouring cells write it concurrently.  The west and east halo columns
 // (one element per row) go through registers.  One wait at the end.
 // fresh: the cell has never been processed and holds no exit node, so its
 // interior values are all +inf and only delta and the halo are read.
@@ -881,6 +882,99 @@ __device__ void load_tile(T* tu, T* td, const Inst& I, const CellBox& B, int lan
   }
   // the row transfers write LDS asynchronously: wait for all of them
   __builtin_amdgcn_s_waitcnt(0);
+}
+
+// The same tile load through registers: the lanes move 16-byte pieces of
+// the rows with buffer loads, a fixed number of lanes per row (the row's
+// pieces, rounded up to a power of two) and several rows per instruction,
+// all of a lane's pieces in flight at once (u with the coherent sc1 policy;
+// loads past the array's end return zeros and are never used), then write
+// the elements that belong to the row into LDS.  Rows as in load_tile: this
+// wave loads rows ri = part, part + NW, ... of the rows the call loads (at
+// most ROWS).  Arrays of 4 GiB or more, and tiles with more than nine
+// instructions' worth of rows per wave (64-node cells loaded by one wave),
+// take load_tile.
+template <typename T, int P, int NW, int ROWS = P>
+__device__ void load_tile_v(T* tu, T* td, const Inst& I, const CellBox& B, int lane,
+                            bool with_interior, bool fresh, int part) {
+  typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+  constexpr int kEl = 16 / (int)sizeof(T);  // elements per piece
+  constexpr int kPieces = (P - 2 + kEl - 1) / kEl;
+  constexpr int kLanesPerRow = kPieces <= 4 ? 4 : kPieces <= 8 ? 8 : kPieces <= 16 ? 16 : 32;
+  constexpr int kRowsPerInstr = 64 / kLanesPerRow;
+  constexpr int kRowsPerWave = (ROWS + NW - 1) / NW;
+  constexpr int kMax = (kRowsPerWave + kRowsPerInstr - 1) / kRowsPerInstr;
+  constexpr int kCohPolicy = 16;  // sc1
+  if constexpr (kMax > 9) {  // more rows per wave than registers to hold them
+    load_tile<T, P>(tu, td, I, B, lane, with_interior, fresh, part, NW);
+    return;
+  }
+  if ((size_t)I.nx * I.ny * sizeof(T) >= (1ull << 32)) {
+    load_tile<T, P>(tu, td, I, B, lane, with_interior, fresh, part, NW);
+    return;
+  }
+  lane = opaque_lane(lane);
+  const T INF = inf_v<T>();
+  const int nx = __builtin_amdgcn_readfirstlane(I.nx), ny = __builtin_amdgcn_readfirstlane(I.ny);
+  const int bw = __builtin_amdgcn_readfirstlane(B.w), bh = __builtin_amdgcn_readfirstlane(B.hgt);
+  const int bx0 = __builtin_amdgcn_readfirstlane(B.x0), by0 = __builtin_amdgcn_readfirstlane(B.y0);
+  const int nrow_all = with_interior ? bh + 2 : 2;
+  const uint32_t bytes = (uint32_t)((size_t)nx * ny * sizeof(T));
+  const __amdgpu_buffer_rsrc_t ru =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(I.u), 0, bytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rd =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(I.delta), 0, bytes, 0x00020000);
+  const int col = (lane % kLanesPerRow) * kEl;  // first element of the lane's piece
+  const int sub = lane / kLanesPerRow;          // row within an instruction's rows
+  v4u pu[kMax], pd[kMax];
+#pragma unroll
+  for (int k = 0; k < kMax; ++k) {
+    const int ri = part + NW * (k * kRowsPerInstr + sub);
+    const int r = with_interior ? ri - 1 : (ri == 0 ? -1 : bh);
+    const int j = by0 + r;
+    const bool live = ri < nrow_all && col < bw && j >= 0 && j < ny;
+    const bool want_u = live && (!fresh || r < 0 || r == bh);
+    const uint32_t off = live ? (uint32_t)(j * nx + bx0 + col) * (uint32_t)sizeof(T) : 0u;
+    pu[k] = want_u ? __builtin_amdgcn_raw_buffer_load_b128(ru, off, 0, kCohPolicy) : v4u{0u, 0u, 0u, 0u};
+    pd[k] = live ? __builtin_amdgcn_raw_buffer_load_b128(rd, off, 0, 0) : v4u{0u, 0u, 0u, 0u};
+  }
+#pragma unroll
+  for (int k = 0; k < kMax; ++k) {
+    const int ri = part + NW * (k * kRowsPerInstr + sub);
+    const int r = with_interior ? ri - 1 : (ri == 0 ? -1 : bh);
+    const int j = by0 + r;
+    if (ri >= nrow_all || col >= bw) continue;
+    const bool in_grid = j >= 0 && j < ny;
+    const bool want_u = in_grid && (!fresh || r < 0 || r == bh);
+    T eu[kEl], ed[kEl];
+    __builtin_memcpy(eu, &pu[k], 16);
+    __builtin_memcpy(ed, &pd[k], 16);
+    T* lu = tu + (r + 1) * P + 1 + col;
+    T* ld = td + (r + 1) * P + 1 + col;
+#pragma unroll
+    for (int m = 0; m < kEl; ++m) {
+      if (col + m < bw) {
+        lu[m] = want_u ? eu[m] : INF;
+        ld[m] = in_grid ? ed[m] : INF;
+      }
+    }
+  }
+  if (part == 0) {
+    const gptr<const T> u = to_global(static_cast<const T*>(I.u));
+    const gptr<const T> dl = to_global(static_cast<const T*>(I.delta));
+    const int jr = B.y0 + (lane < B.hgt ? lane : 0);
+    const size_t rowi = (size_t)jr * nx;
+    const int iw = B.x0 > 0 ? B.x0 - 1 : 0;
+    const int ie = B.x1 < nx ? B.x1 : nx - 1;
+    const T vw = ld_coh(u + rowi + iw), dw = dl[rowi + iw];
+    const T ve = ld_coh(u + rowi + ie), de = dl[rowi + ie];
+    if (lane < B.hgt) {
+      tu[(lane + 1) * P] = B.x0 > 0 ? vw : INF;
+      td[(lane + 1) * P] = B.x0 > 0 ? dw : INF;
+      tu[(lane + 1) * P + B.w + 1] = B.x1 < nx ? ve : INF;
+      td[(lane + 1) * P + B.w + 1] = B.x1 < nx ? de : INF;
+    }
+  }
 }
 
 // Writes the whole tile back to u.
@@ -1131,7 +1225,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
         const Inst I = inst_of(e, g);
         const CellBox B = cell_box(I, g - I.cell0);
         if (op == 1) {
-          load_tile<T, P>(tu, td, I, B, lane, (flags & 1) != 0, (flags & 2) != 0, part, NW);
+          load_tile_v<T, P, NW>(tu, td, I, B, lane, (flags & 1) != 0, (flags & 2) != 0, part);
         } else {
           store_tile<T, P>(tu, I, B, lane, part, NW);
           __builtin_amdgcn_s_waitcnt(0);
@@ -1142,11 +1236,11 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
   }
   auto tile_load = [&](const Inst& I, const CellBox& B, int g, bool with_interior, bool fresh) {
     if constexpr (NW == 1) {
-      load_tile<T, P>(tu, td, I, B, lane, with_interior, fresh);
+      load_tile_v<T, P, 1>(tu, td, I, B, lane, with_interior, fresh, 0);
     } else {
       if (lane == 0) job = TileJob{1, g, (with_interior ? 1 : 0) | (fresh ? 2 : 0)};
       __syncthreads();  // A
-      load_tile<T, P>(tu, td, I, B, lane, with_interior, fresh, 0, NW);
+      load_tile_v<T, P, NW>(tu, td, I, B, lane, with_interior, fresh, 0);
       __syncthreads();  // B: every part has landed
     }
   };
@@ -1371,7 +1465,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
       sides = (uint32_t)bcast((int)sides, 0);
       done1 = 1;
       order_acquire();
-      load_tile<T, P>(tu, td, I, B, lane, false);  // fresh halo only
+      load_tile_v<T, P, 1, 2>(tu, td, I, B, lane, false, false, 0);  // fresh halo only
     }
     if (lane == 0) {
       if (NW == 1 && e.ninst > 1) {  // per-instance statistics of a batch
