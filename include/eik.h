@@ -87,7 +87,9 @@ typedef struct {
                                every problem; 0 = band_cells                    */
   int32_t device_ptrs;      /* 1: all pointers are device memory                */
   void* stream;             /* hipStream_t, or NULL for the null stream         */
-  uint64_t max_cell_visits; /* guard on total cell visits; 0 = 64 * cells + 1024 */
+  uint64_t max_cell_visits; /* guard on total cell visits; 0 = 64 * cells + 1024
+                               (a batch: each problem against its share,
+                               max_cell_visits * J_k / J, or 64 J_k + 1024) */
   int32_t residual_check;   /* F32: recheck the fixed-point residual in FP64 and
                                re-solve in FP64 each problem whose residual
                                exceeds residual_tol (F64: only report it)     */

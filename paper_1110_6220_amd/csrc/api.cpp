@@ -436,6 +436,7 @@ int setup_engine(Solver& sv, std::vector<Inst>& inst, int dtype, int method, int
   e.eager = eager;
   e.profile = g_profile;
   e.guard = guard ? guard : 64ull * (uint64_t)J + 1024ull;
+  e.guard_given = guard ? 1 : 0;
   e.timeout_ticks = timeout;
   return EIK_OK;
 }

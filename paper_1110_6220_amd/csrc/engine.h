@@ -155,6 +155,9 @@ struct Engine {
   unsigned int* trace_n;
   unsigned int trace_cap;
   unsigned long long guard;          // limit on total cell visits
+  int32_t guard_given;               // 1: guard was set by the caller (batches:
+                                     // each problem gets its share of it), 0:
+                                     // default (each problem 64 J_k + 1024)
   unsigned long long timeout_ticks;  // wall_clock64 ticks before workers give up
 };
 

@@ -544,14 +544,48 @@ __device__ __forceinline__ int heap_pop(const Engine& e, int lane) {
 // goes idle; the wave whose decrement empties the count publishes the
 // instance's completion to the host (its values were stored with
 // device-scope accesses before every decrement of the chain).
-__device__ __forceinline__ void inst_active_add(const Engine& e, int g) {
-  if (e.idone) atomic_add_relaxed(&e.iact[inst_index(e, g)], 1ull);
+// Active cells (waiting, queued or running).  A single problem keeps one
+// count, ctl->active.  A batch keeps a count per problem (iact) and in
+// ctl->active the number of problems with active cells: the per-visit
+// updates spread over the problems' counters instead of meeting on one
+// address, and ctl->active still reaches zero exactly when no cell is
+// active.  A problem's count reaches zero once, when it is solved (a cell
+// becomes active only through an active neighbour, and the preparation
+// kernels have counted every initially active cell before the solver starts).
+__device__ __forceinline__ void cell_active(const Engine& e, int g) {
+  if (e.ninst > 1) atomic_add_relaxed(&e.iact[inst_index(e, g)], 1ull);
+  else atomic_add_relaxed(&e.ctl->active, 1ull);
 }
-__device__ __forceinline__ void inst_active_done(const Engine& e, int g) {
-  if (!e.idone) return;
+__device__ __forceinline__ void cell_idle(const Engine& e, int g) {
+  if (e.ninst == 1) {
+    atomic_add_relaxed(&e.ctl->active, ~0ull);
+    return;
+  }
   const int k = inst_index(e, g);
-  if (atomic_add_relaxed(&e.iact[k], ~0ull) == 1ull)
-    __hip_atomic_store(&e.idone[k], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  if (atomic_add_relaxed(&e.iact[k], ~0ull) == 1ull) {
+    if (e.idone) __hip_atomic_store(&e.idone[k], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    atomic_add_relaxed(&e.ctl->active, ~0ull);
+  }
+}
+
+// Counts a cell removal against the visit guard (one lane).  A batch counts
+// per problem (istat[4k], the problem's statistic too) against the problem's
+// share of the guard: 64 J_k + 1024 by default, else the caller's limit
+// scaled by J_k / J (at least 1).  A single problem counts in ctl->visits.
+__device__ __forceinline__ void count_visit(const Engine& e, const Inst& I, int g) {
+  if (e.ninst > 1) {
+    const unsigned long long jk = (unsigned long long)I.kx * I.ky;
+    unsigned long long lim = 64ull * jk + 1024ull;
+    if (e.guard_given) {  // guard * jk / J without overflow (jk <= J < 2^31)
+      const unsigned long long J = (unsigned long long)e.ncells, q = e.guard / J;
+      lim = q > ~0ull / jk ? ~0ull : q * jk + (e.guard % J) * jk / J;
+      if (lim < 1ull) lim = 1ull;
+    }
+    if (atomic_add_relaxed(e.istat + 4 * (size_t)inst_index(e, g), 1ull) >= lim)
+      set_err(e.ctl, kErrGuard);
+    return;
+  }
+  if (atomic_add_relaxed(&e.ctl->visits, 1ull) >= e.guard) set_err(e.ctl, kErrGuard);
 }
 
 // ----------------------------------------------------------------------------
@@ -571,8 +605,7 @@ __device__ void requeue(const Engine& e, int g, uint32_t fl, uint32_t sides, dou
       __hip_atomic_fetch_or(&e.st[g], kPending | (fl << kFlagShift) | (sides << kSideShift),
                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (!(old & (kPending | kRunning)) && (old & kDone1)) {
-    atomic_add_relaxed(&e.ctl->active, 1ull);
-    inst_active_add(e, g);
+    cell_active(e, g);
     if (e.ready_at) e.ready_at[g] = wall_clock64();
     if (!e.heap) q_push(e, (uint32_t)g, key);
   }
@@ -1292,7 +1325,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
     // the claim's bookkeeping is spread over lanes 1-3 and issued before the
     // claim itself, so the device-scope round trips overlap
     if (lane == 1) first = atomic_add_relaxed(&e.visits[g], 1u) == 0u ? 1 : 0;
-    if (lane == 2 && atomic_add_relaxed(&ctl->visits, 1ull) >= e.guard) set_err(ctl, kErrGuard);
+    if (lane == 2) count_visit(e, I, g);
     if (lane == 3 && e.dag) ordb = e.ord[g];
     if (lane == 0) {
       const uint32_t old = claim(e, g);
@@ -1313,7 +1346,6 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
                                       : 0ull;
     order_acquire();
     if constexpr (HEAP) heap_fix(e, g >> 6, lane);  // g is running now
-    int nvis = 1;                           // removals of g in this loop
     tick(e, ph, kPhClaim, &t0);
     if (e.trace) tr[3] = wall_clock64();
     // a cell's interior is written only by its own processing
@@ -1432,8 +1464,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (idle) {
           if (M == kFmsm) st_coh(&e.st[g], kDone1);
-          atomic_add_relaxed(&ctl->active, ~0ull);
-          inst_active_done(e, g);
+          cell_idle(e, g);
           q_done(e, ring);
         } else {
           // re-requested while running: take it again at once
@@ -1443,8 +1474,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
           sides = (old >> kSideShift) & 0xFu;
           const uint32_t v = ld_coh(&e.visits[g]);
           st_coh(&e.visits[g], v + 1u);
-          const unsigned long long tot = atomic_add_relaxed(&ctl->visits, 1ull);
-          if (tot >= ctl->guard) set_err(ctl, kErrGuard);
+          count_visit(e, I, g);
           again = 1;
         }
       }
@@ -1459,7 +1489,6 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
         }
         break;
       }
-      nvis++;
       if (get_err(ctl)) break;
       fl = (uint32_t)bcast((int)fl, 0);
       sides = (uint32_t)bcast((int)sides, 0);
@@ -1468,9 +1497,8 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
       load_tile_v<T, P, 1, 2>(tu, td, I, B, lane, false, false, 0);  // fresh halo only
     }
     if (lane == 0) {
-      if (NW == 1 && e.ninst > 1) {  // per-instance statistics of a batch
+      if (NW == 1 && e.ninst > 1) {  // per-instance statistics of a batch (visits: count_visit)
         unsigned long long* is = e.istat + 4 * (size_t)inst_index(e, g);
-        atomic_add_relaxed(is, (unsigned long long)nvis);
         atomic_add_relaxed(is + 1, nsweeps - sw0);
         atomic_add_relaxed(is + 2, nchecks - ch0);
       }
@@ -1549,7 +1577,7 @@ __global__ void k_prep_cells(Engine e) {
   // h waits for sequence h + 1 >= 1) and a producer does not look
   for (size_t k = tid; k < (size_t)e.q.nslot; k += stride) e.q.slot[k] = 0ull;
   for (size_t k = tid; k < 4 * (size_t)ninst; k += stride) e.istat[k] = 0ull;
-  if (e.idone)
+  if (ninst > 1)
     for (size_t k = tid; k < (size_t)ninst; k += stride) e.iact[k] = 0ull;
   for (size_t k = tid; k < (size_t)e.q.nb * e.q.ng; k += stride) {
     e.q.head[k * kCtrStride] = 0ull;
@@ -1574,7 +1602,7 @@ __global__ void k_prep_cells(Engine e) {
   }
   if (tid == 0) {
     Ctl* c = e.ctl;
-    c->active = 0ull;
+    c->active = ninst > 1 ? (unsigned long long)ninst : 0ull;  // problems / cells active
     c->visits = 0ull;
     c->sweeps = 0ull;
     c->checks = 0ull;
@@ -2063,8 +2091,7 @@ __global__ void k_dag(Engine e, const CoarseOut* co) {
     }
     e.ord[g] = o;
     e.deps[g] = n;
-    atomic_add_relaxed(&e.ctl->active, 1ull);
-    inst_active_add(e, g);
+    cell_active(e, g);
     if (n == 0 && !get_err(e.ctl)) release_first(e, g);
   }
 }
