@@ -65,7 +65,11 @@ struct QGroup {
 // the cells of band b that are queued or running; the cursor moves past a
 // band only once its count is zero (the band is closed with kClosed while the
 // cursor moves, then reopened for band + nb).  Cells are popped only from the
-// `window` + 1 bands starting at the cursor.  nb = 1 is a plain FIFO.
+// `window` + 1 bands starting at the cursor.  nb = 1 is a FIFO, for batches
+// split into nring rings (no more rings than waves) so that the pushes and
+// pops of many waves do not all meet on one head and one tail: a cell goes
+// to ring (cell mod nring), a wave waits on ring (its workgroup index mod
+// nring).
 // With ng > 1 groups (one per problem of a batch) every group is such a
 // queue of its own: counters of ring r of group g at index g * nb + r, the
 // cursor of group g at g * kCtrStride, slots and width from grp[g] (filled by
@@ -87,8 +91,13 @@ struct Queue {
   double inv_width;              // 1 / band width (ng = 1)
   unsigned long long nslot;      // slots in all
   double width, width_cells;     // band width of the groups (see above)
+  uint32_t nring;                // nb = 1: FIFO rings, a power of two (cell g in
+                                 // ring g mod nring, each of `cap` slots at
+                                 // slot + r * cap)
+  uint32_t pad_r;
 };
 constexpr int kCtrStride = 16;  // 128 bytes between hot counters
+constexpr uint32_t kFifoRings = 8;  // rings of the FIFO queue
 constexpr unsigned long long kClosed = 1ull << 62;
 
 // Device control block.  Counters that many waves update while cells are

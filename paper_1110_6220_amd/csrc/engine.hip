@@ -284,10 +284,13 @@ __device__ __forceinline__ unsigned long long band_of(const Queue& q, const QVie
 // at most once (guarded by its state word) and cap > cells of the group, so a
 // producer only waits for a consumer that has already claimed the slot's
 // previous ticket.
+// RINGS = false: the caller knows the FIFO has one ring (the single-problem
+// solver, which thus carries none of the ring arithmetic).
+template <bool RINGS = true>
 __device__ void q_push(const Engine& e, uint32_t cell, double key) {
   const Queue& q = e.q;
   const QView v = qview(q, q.ng > 1 ? (uint32_t)e.cell_inst[cell] : 0u);
-  uint32_t r = 0;
+  uint32_t r = RINGS && q.nb == 1 ? cell & (q.nring - 1u) : 0u;
   if (q.nb > 1) {
     const unsigned long long kb = band_of(q, v, key);
     for (;;) {
@@ -453,12 +456,14 @@ __device__ int q_pop_groups(const Engine& e, int lane, uint32_t home, int* ring)
 // addresses instead of competing for the head.  Returns the cell, or -1 once
 // no cell is waiting, queued or running (or on error/timeout).  A ticket is
 // given up only then: no cell will be queued any more.
-__device__ int q_pop_ticket(const Engine& e, int lane) {
+template <bool RINGS>
+__device__ int q_pop_ticket(const Engine& e, int lane, uint32_t ring) {
   const Queue& q = e.q;
   int cell = -1;
+  if (!RINGS) ring = 0u;
   if (lane == 0) {
-    const unsigned long long h = atomic_add_relaxed(q.head, 1ull);
-    unsigned long long* s = q.slot + (h & (q.cap - 1));
+    const unsigned long long h = atomic_add_relaxed(ctr(q.head, ring), 1ull);
+    unsigned long long* s = q.slot + (size_t)ring * q.cap + (h & (q.cap - 1));
     int spins = 0;
     for (;;) {
       const unsigned long long v = ld64(s);
@@ -599,6 +604,7 @@ __device__ __forceinline__ void count_visit(const Engine& e, const Inst& I, int 
 // reads the new values when it starts.
 // Under the heap schedule a queued cell is only marked pending: the single
 // worker finds it by its cell value (heap_pop).
+template <bool RINGS = true>
 __device__ void requeue(const Engine& e, int g, uint32_t fl, uint32_t sides, double key) {
   order_release();
   const uint32_t old =
@@ -607,17 +613,18 @@ __device__ void requeue(const Engine& e, int g, uint32_t fl, uint32_t sides, dou
   if (!(old & (kPending | kRunning)) && (old & kDone1)) {
     cell_active(e, g);
     if (e.ready_at) e.ready_at[g] = wall_clock64();
-    if (!e.heap) q_push(e, (uint32_t)g, key);
+    if (!e.heap) q_push<RINGS>(e, (uint32_t)g, key);
   }
 }
 
 // The last earlier neighbour of cell g finished its first processing: g is
 // enqueued (only this path enqueues a cell before its first processing).
+template <bool RINGS = true>
 __device__ void release_first(const Engine& e, int g) {
   order_release();
   __hip_atomic_fetch_or(&e.st[g], kPending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (e.ready_at) e.ready_at[g] = wall_clock64();
-  q_push(e, (uint32_t)g, 0.0);
+  q_push<RINGS>(e, (uint32_t)g, 0.0);
 }
 
 // Takes a popped (or re-requested) cell: state -> running, keeping kDone1.
@@ -1086,7 +1093,7 @@ __device__ uint32_t line_monotone(T v, bool fin, int lane) {
 // last published, re-queues neighbours by the add criterion of Algorithm
 // generic_LC_cells (FHCM narrows the raised directions by the monotonicity
 // check of Algorithm FHCM), and lowers their cell values (eq. cell_value).
-template <typename T, int P, int M>
+template <typename T, int P, int M, bool RINGS>
 __device__ void publish(const Engine& e, const Inst& I, const CellBox& B, int g, T* tu,
                         const T* td, T pub[4], bool first, int lane) {
   lane = opaque_lane(lane);
@@ -1191,7 +1198,7 @@ __device__ void publish(const Engine& e, const Inst& I, const CellBox& B, int g,
             dirs = nondec ? a : b;
           }
         }
-        requeue(e, nb, dirs, 1u << recv, key);
+        requeue<RINGS>(e, nb, dirs, 1u << recv, key);
       }
     }
   }
@@ -1207,6 +1214,7 @@ __device__ void publish(const Engine& e, const Inst& I, const CellBox& B, int g,
 // dependency and starts when none is left.  Lanes 0..3 call it for one side
 // each, so the four dependency counts and queue pushes (chains of
 // device-scope atomics) proceed at once.
+template <bool RINGS>
 __device__ void release_later(const Engine& e, int g, const Inst& I, const CellBox& B,
                               uint32_t ordb, int side) {
   int nb = -1;
@@ -1216,7 +1224,7 @@ __device__ void release_later(const Engine& e, int g, const Inst& I, const CellB
   if (side == 3 && B.cy + 1 < I.ky) nb = g + I.kx;
   if (nb < 0 || (ordb & (1u << side))) return;  // none, or earlier
   if (e.ord[nb] & kOrdEmpty) return;
-  if (atomic_add_relaxed(&e.deps[nb], -1) == 1) release_first(e, nb);
+  if (atomic_add_relaxed(&e.deps[nb], -1) == 1) release_first<RINGS>(e, nb);
 }
 
 // NW waves per workgroup: wave 0 runs the worker; with NW > 1 (single
@@ -1295,12 +1303,15 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
   unsigned long long nsweeps = 0, nchecks = 0;  // this wave's totals
   if constexpr (HEAP)  // the only worker: block minima of the cells queued so far
     for (int b = 0; b < ((e.ncells + 63) >> 6); ++b) heap_fix(e, b, lane);
-  // under per-problem groups a wave looks at the group of its own index first
-  const uint32_t home = e.q.ng > 1 ? blockIdx.x % e.q.ng : 0u;
+  // under per-problem groups a wave looks at the group of its own index first;
+  // a FIFO wave waits on the ring of its own index
+  const uint32_t home = e.q.ng > 1                ? blockIdx.x % e.q.ng
+                        : NW == 1 && e.q.nb == 1   ? blockIdx.x & (e.q.nring - 1u)
+                                                   : 0u;
   for (;;) {
     int ring = 0;
     const int g = HEAP            ? heap_pop(e, lane)
-                  : e.q.nb == 1   ? q_pop_ticket(e, lane)
+                  : e.q.nb == 1   ? q_pop_ticket<(NW == 1)>(e, lane, home)
                   : e.q.ng > 1    ? q_pop_groups(e, lane, home, &ring)
                                   : q_pop(e, lane, &ring);
     if (g < 0) {
@@ -1389,7 +1400,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
             if (ch) nsweeps++; else nchecks++;
           }
         tick(e, ph, kPhSweep, &t0);
-        publish<T, P, M>(e, I, B, g, tu, td, pub, is_first, lane);
+        publish<T, P, M, (NW == 1)>(e, I, B, g, tu, td, pub, is_first, lane);
         is_first = false;
         tick(e, ph, kPhPublish, &t0);
       } else {
@@ -1409,7 +1420,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
           if (ch) nsweeps++; else nchecks++;
           tick(e, ph, kPhSweep, &t0);
           if (e.eager && (ch || is_first)) {
-            publish<T, P, M>(e, I, B, g, tu, td, pub, is_first, lane);
+            publish<T, P, M, (NW == 1)>(e, I, B, g, tu, td, pub, is_first, lane);
             is_first = false;
             tick(e, ph, kPhPublish, &t0);
           }
@@ -1435,7 +1446,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
           }
         }
         if (!e.eager) {
-          publish<T, P, M>(e, I, B, g, tu, td, pub, is_first, lane);
+          publish<T, P, M, (NW == 1)>(e, I, B, g, tu, td, pub, is_first, lane);
           is_first = false;
           tick(e, ph, kPhPublish, &t0);
         }
@@ -1446,7 +1457,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
         // publish has made the boundary visible: later neighbours start
         // while the interior is written back
         if (lane < 4 && e.dag && !__builtin_amdgcn_readfirstlane(done1))  // lane 0's flag
-          release_later(e, g, I, B, ordb, lane);
+          release_later<(NW == 1)>(e, g, I, B, ordb, lane);
       }
       tile_store(I, B, g);
       order_release();
@@ -1454,7 +1465,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
       if (lane == 0) {
         if (e.dag && !done1) {
           if (M == kFmsm)
-            for (int sd = 0; sd < 4; ++sd) release_later(e, g, I, B, ordb, sd);
+            for (int sd = 0; sd < 4; ++sd) release_later<(NW == 1)>(e, g, I, B, ordb, sd);
           done1 = 1;
         }
         uint32_t exp = run_state;
@@ -1579,7 +1590,8 @@ __global__ void k_prep_cells(Engine e) {
   for (size_t k = tid; k < 4 * (size_t)ninst; k += stride) e.istat[k] = 0ull;
   if (ninst > 1)
     for (size_t k = tid; k < (size_t)ninst; k += stride) e.iact[k] = 0ull;
-  for (size_t k = tid; k < (size_t)e.q.nb * e.q.ng; k += stride) {
+  const size_t nctr = (size_t)e.q.nb * e.q.ng > e.q.nring ? (size_t)e.q.nb * e.q.ng : e.q.nring;
+  for (size_t k = tid; k < nctr; k += stride) {
     e.q.head[k * kCtrStride] = 0ull;
     e.q.tail[k * kCtrStride] = 0ull;
     e.q.inflight[k * kCtrStride] = 0ull;

@@ -152,7 +152,7 @@ struct BandSpec {
 // nullptr (no bands).
 int setup_engine(Solver& sv, std::vector<Inst>& inst, int dtype, int method, int dag, int heap,
                  const BandSpec* band, int window, int eager, uint64_t guard, uint64_t timeout,
-                 hipStream_t stream, Engine* out, DevBuf* instbuf = nullptr);
+                 hipStream_t stream, Engine* out, DevBuf* instbuf = nullptr, int rings = 1);
 eik_opts default_opts();
 int check_opts(const eik_opts& o);
 int std_cells(int n, int s);

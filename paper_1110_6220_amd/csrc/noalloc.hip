@@ -74,11 +74,16 @@ int na_init(int dev, NoAlloc** out) {
 size_t scratch_need(int64_t nodes, int64_t J, int dtype, int nbands) {
   size_t cap = 1;
   while (cap < (size_t)J + 1) cap <<= 1;
+  if (nbands == 1) {  // the FIFO's rings
+    size_t rc = 1;
+    while (rc < (size_t)(J + kFifoRings - 1) / kFifoRings + 1) rc <<= 1;
+    cap = rc * kFifoRings;
+  }
   // states, visits, values, dependency counts, order bits, heap blocks;
   // coarse speed, mask, exit cost, value, rank, h/F and Fast Marching spill
   const size_t per_cell = 4 + 4 + 8 + 4 + 1 + 1 + 8 + 1 + 8 + 8 + 4 + 8 + 24;
   return (size_t)nodes * (dtype == EIK_F64 ? 8 : 4) + (size_t)J * per_cell +
-         (size_t)nbands * cap * 8 + (size_t)nbands * 3 * 128 + 64 * 256 + (1u << 16);
+         (size_t)nbands * cap * 8 + (size_t)(nbands + kFifoRings) * 3 * 128 + 64 * 256 + (1u << 16);
 }
 
 }  // namespace

@@ -92,6 +92,22 @@ def test_batch_band_groups(eik):
         assert np.abs(g - U).max() <= 10 * np.abs(Vo - U).max() + 1e-12, w["name"]
 
 
+def test_few_workers(eik):
+    """Fewer persistent waves than the FIFO has rings: the queue uses no
+    more rings than there are waves to wait on them (every ring is served),
+    for batches and single problems, under every schedule."""
+    ws = W.batch_bumps(count=6, seed=48, n_lo=40, n_hi=150)
+    refs = [O.fmm(O.Problem.from_workload(w)) for w in ws]
+    for workers in (1, 2, 3, 5):
+        for sched in ("coarse", "fifo", "bands"):
+            got, _ = run_batched(eik, ws, workers=workers, schedule=sched, cell=16, timeout_ms=5000)
+            for w, g, U in zip(ws, got, refs):
+                assert max_rel(g, U) <= 1e-12, (workers, sched, w["name"])
+    d = to_dev(ws[0])
+    u, _ = eik.eik_solve(d["F"], d["h"], d["src"], d["q"], None, workers=3, cell=16, timeout_ms=5000)
+    assert max_rel(u.cpu().numpy(), refs[0]) <= 1e-12
+
+
 def test_fmsm_batched_bitwise(eik):
     ws = W.batch_bumps(count=8, seed=43, n_lo=40, n_hi=180)
     got, _ = run_batched(eik, ws, method="fmsm", cell=16)
