@@ -204,7 +204,10 @@ int eik_solve_batched(int32_t n, const eik_problem* probs, const eik_opts* opts,
    poll/wait reports completion.  opts.stream and opts.workers are ignored
    (each lane uses its own stream and a 1/lanes share of the device).
    Small per-launch solver state (a few bytes per cell) is held by the lanes
-   outside the budget. */
+   outside the budget.  Each lane uses two streams; create the server before
+   the process replays HIP graphs (opts.graph): measured, a server created
+   after one graph-replayed solve had twice the p99 latency (most likely two
+   lanes then share one of the runtime's hardware queues). */
 typedef struct {
   uint64_t hbm_budget_bytes;  /* device arena; 0 = 64 GiB                      */
   int32_t max_slots;          /* requests admitted at once; 0 = 1024           */
