@@ -447,9 +447,13 @@ int setup_engine(Solver& sv, std::vector<Inst>& inst, int dtype, int method, int
   return EIK_OK;
 }
 
-// Persistent waves: as many as fit on the device at once (at most one per
-// cell); a single problem is capped at 128 waves, beyond which more waves
-// only contend for the few ready cells of one front.
+// Persistent workers: as many as fit on the device at once (at most one per
+// cell).  A single problem is capped at J/16 workers, between 128 and 256:
+// beyond that more workers only contend for the few ready cells of one
+// front.  Measured (kernel us at 128 / 256 / 512 workers): 4097^2
+// checkerboard with obstacles (4225 cells) 7309 / 6799 / 6961, 2049^2 maze
+// (4225 cells) 15577 / 14311 / 14081, 2049^2 smooth speed (1089 cells)
+// 2272 / 2271 / 2302, 1025^2 (289 cells) 1146 / 1149 / 1162.
 static int default_workers(const Workspace* ws, int64_t J, int tile, int dtype, int method, int n) {
   static std::mutex mu;
   static int cache[2][3][3] = {};
@@ -462,7 +466,7 @@ static int default_workers(const Workspace* ws, int64_t J, int tile, int dtype, 
     per_cu = c;
   }
   int64_t w = std::min<int64_t>(J, (int64_t)ws->cus * per_cu);
-  if (n == 1) w = std::min<int64_t>(w, 128);
+  if (n == 1) w = std::min<int64_t>(w, std::min<int64_t>(256, std::max<int64_t>(128, J / 16)));
   return (int)std::max<int64_t>(w, 1);
 }
 
