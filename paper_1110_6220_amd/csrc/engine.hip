@@ -99,6 +99,25 @@ __device__ __forceinline__ double sqrt_pos(double x) {
   return fma(d, h, g);
 }
 
+// The same root without the last correction: within one unit in the last
+// place instead of correctly rounded, two dependent operations shorter.
+__device__ __forceinline__ double sqrt_pos_faithful(double x) {
+  const double r = __builtin_amdgcn_rsq(x);
+  double g = x * r;
+  double h = r * 0.5;
+  const double e = fma(-h, g, 0.5);
+  g = fma(g, e, g);
+  h = fma(h, e, h);
+  const double d = fma(-g, g, x);
+  return fma(d, h, g);
+}
+
+template <bool FAITHFUL>
+__device__ __forceinline__ double root_pos(double x) {
+  if constexpr (FAITHFUL) return sqrt_pos_faithful(x);
+  else return sqrt_pos(x);
+}
+
 // Local update of Section 2 from a (x-neighbour value) and b (y-neighbour
 // value): the one-sided value min(a,b) + delta when |a - b| >= delta,
 // otherwise the root >= max(a,b) of (U-a)^2 + (U-b)^2 = delta^2.  The
@@ -108,21 +127,25 @@ __device__ __forceinline__ double sqrt_pos(double x) {
 // range).  Contraction is otherwise off, so the remaining terms round as in
 // the oracle too.  a = b = +inf gives NaN, which the caller's minimum with the
 // old value turns into "no update".
+// FAITHFUL: the root within one unit in the last place (the exact method,
+// whose bar is a relative error against the oracle, not bit equality).
+template <bool FAITHFUL = false>
 __device__ __forceinline__ double local_update(double a, double b, double dl) {
   const double lo = wave::vmin(a, b);  // a and b are never NaN
   const double d = a - b;
   const double one = lo + dl;
-  const double two = fma(0.5, sqrt_pos(2.0 * dl * dl - d * d), 0.5 * (a + b));
+  const double two = fma(0.5, root_pos<FAITHFUL>(2.0 * dl * dl - d * d), 0.5 * (a + b));
   return (fabs(d) >= dl) ? one : two;
 }
 
 // FP32 storage: the branch test and the two-sided root are evaluated in FP64
 // and rounded once to FP32.
+template <bool FAITHFUL = false>
 __device__ __forceinline__ float local_update(float a, float b, float dl) {
   const float lo = wave::vmin(a, b);
   const double da = a, db = b, dd = da - db, ddl = dl;
   const float one = lo + dl;
-  const float two = (float)fma(0.5, sqrt_pos(2.0 * ddl * ddl - dd * dd), 0.5 * (da + db));
+  const float two = (float)fma(0.5, root_pos<FAITHFUL>(2.0 * ddl * ddl - dd * dd), 0.5 * (da + db));
   return (fabs(dd) >= ddl) ? one : two;
 }
 
@@ -670,8 +693,13 @@ __device__ uint32_t claim(const Engine& e, int g) {
 // also maps the NaN that a = b = +inf produces to "no update", as the
 // oracle's explicit test does.
 // STATS: also the lane's largest decrease (+inf for a node that left +inf)
-// and number of decreased nodes, into *mx and *cnt.
-template <typename T, int P, bool DIRECTIONAL, bool STATS, int dir>
+// and number of decreased nodes, into *mx and *cnt.  FAITHFUL: the update's
+// root within one unit in the last place (local_update).
+// The three result bits are kept as wave masks (lanes that decreased, and
+// that did so below an upwind neighbour), one scalar AND / OR per term and
+// step; lane 0's x-neighbour is the fixed halo, so its bit is dropped at the
+// end.
+template <typename T, int P, bool DIRECTIONAL, bool STATS, int dir, bool FAITHFUL = false>
 __device__ __forceinline__ uint32_t sweep_tile_dir(T* tu, const T* td, int w, int hgt, int lane,
                                                    double* mx, int* cnt) {
   lane = opaque_lane(lane);
@@ -692,7 +720,8 @@ __device__ __forceinline__ uint32_t sweep_tile_dir(T* tu, const T* td, int w, in
   };
   int c = idx_t(-lane);
   T prev = tu[idx_t(-1)];
-  bool changed = false, back_x = false, back_y = false;
+  unsigned long long m_dec = 0ull, m_bx = 0ull, m_by = 0ull;
+  const unsigned long long m_col = ballot(col_ok);
   // One step at d: the node's old value uo and its north value nv were read
   // before; the values of the next step are read into the *n references.
   // The lane's row index moves by one row while t + 1 lies in [0, hgt].
@@ -708,12 +737,14 @@ __device__ __forceinline__ uint32_t sweep_tile_dir(T* tu, const T* td, int w, in
     const T wv = shr1_or(prev, hw);
     const T a = DIRECTIONAL ? wv : vmin(wv, ev);
     const T b = DIRECTIONAL ? prev : vmin(prev, nv);
-    const T U = local_update(a, b, dl);
+    const T U = local_update<FAITHFUL>(a, b, dl);
     const T r = vmin(uo, U);
     const bool dec = valid && (r < uo);
-    changed |= dec;
-    back_x |= dec && lane > 0 && r < wv;
-    back_y |= dec && t > 0 && r < prev;
+    // ballot(dec), as three compare masks (no detour through a register)
+    const unsigned long long md = ballot(r < uo) & ballot((unsigned)t < (unsigned)hgt) & m_col;
+    m_dec |= md;
+    m_bx |= md & ballot(r < wv);
+    m_by |= md & ballot(r < prev) & ballot(t > 0);
     if constexpr (STATS) {
       const double chg = (double)uo - (double)r;  // +inf when uo is +inf
       smx = dec && chg > smx ? chg : smx;
@@ -741,19 +772,19 @@ __device__ __forceinline__ uint32_t sweep_tile_dir(T* tu, const T* td, int w, in
     *mx = smx;
     *cnt = scnt;
   }
-  return (ballot(changed) ? 1u : 0u) | (ballot(back_x) ? 2u : 0u) | (ballot(back_y) ? 4u : 0u);
+  return (m_dec ? 1u : 0u) | ((m_bx & ~1ull) ? 2u : 0u) | (m_by ? 4u : 0u);
 }
 
 // The sweep with its direction fixed at compile time (the neighbour offsets
 // become immediates of the LDS accesses).
-template <typename T, int P, bool DIRECTIONAL, bool STATS = false>
+template <typename T, int P, bool DIRECTIONAL, bool STATS = false, bool FAITHFUL = false>
 __device__ uint32_t sweep_tile(T* tu, const T* td, int w, int hgt, int dir, int lane,
                                double* mx = nullptr, int* cnt = nullptr) {
   switch (dir) {
-    case 0: return sweep_tile_dir<T, P, DIRECTIONAL, STATS, 0>(tu, td, w, hgt, lane, mx, cnt);
-    case 1: return sweep_tile_dir<T, P, DIRECTIONAL, STATS, 1>(tu, td, w, hgt, lane, mx, cnt);
-    case 2: return sweep_tile_dir<T, P, DIRECTIONAL, STATS, 2>(tu, td, w, hgt, lane, mx, cnt);
-    default: return sweep_tile_dir<T, P, DIRECTIONAL, STATS, 3>(tu, td, w, hgt, lane, mx, cnt);
+    case 0: return sweep_tile_dir<T, P, DIRECTIONAL, STATS, 0, FAITHFUL>(tu, td, w, hgt, lane, mx, cnt);
+    case 1: return sweep_tile_dir<T, P, DIRECTIONAL, STATS, 1, FAITHFUL>(tu, td, w, hgt, lane, mx, cnt);
+    case 2: return sweep_tile_dir<T, P, DIRECTIONAL, STATS, 2, FAITHFUL>(tu, td, w, hgt, lane, mx, cnt);
+    default: return sweep_tile_dir<T, P, DIRECTIONAL, STATS, 3, FAITHFUL>(tu, td, w, hgt, lane, mx, cnt);
   }
 }
 
@@ -1415,7 +1446,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
         int dir = pick ? __builtin_ctz(pick) : 0;
         bool flip_x_next = true;
         for (int k = 0;; ++k) {
-          const uint32_t res = sweep_tile<T, P, false>(tu, td, B.w, B.hgt, dir, lane);
+          const uint32_t res = sweep_tile<T, P, false, false, true>(tu, td, B.w, B.hgt, dir, lane);
           const bool ch = res & 1u;
           if (ch) nsweeps++; else nchecks++;
           tick(e, ph, kPhSweep, &t0);
@@ -2229,8 +2260,9 @@ __global__ void k_convert(const S* src, D* dst, int64_t n) {
 // Latency of the sweep's dependent chain: one wave alone sweeps one S x S
 // tile in LDS `sweeps` times (direction SW; exit node at the south-west
 // corner, +inf elsewhere, so every sweep runs the same branch-free steps as
-// in the solver) and reports the wall-clock ticks of the loop.  One sweep is
-// 2S - 1 anti-diagonal steps, each one dependent local update per lane.
+// in the exact method's solver) and reports the wall-clock ticks of the loop.
+// One sweep is 2S - 1 anti-diagonal steps, each one dependent local update
+// per lane.
 template <typename T, int S>
 __global__ __launch_bounds__(64) void k_probe_sweep(int sweeps, unsigned long long* ticks) {
   constexpr int P = S + 2;
@@ -2247,7 +2279,7 @@ __global__ __launch_bounds__(64) void k_probe_sweep(int sweeps, unsigned long lo
   __syncthreads();
   const unsigned long long t0 = wall_clock64();
   uint32_t acc = 0;
-  for (int r = 0; r < sweeps; ++r) acc += sweep_tile<T, P, false>(tu, td, S, S, 0, lane);
+  for (int r = 0; r < sweeps; ++r) acc += sweep_tile<T, P, false, false, true>(tu, td, S, S, 0, lane);
   const unsigned long long t1 = wall_clock64();
   if (lane == 0) ticks[0] = (t1 - t0) | ((unsigned long long)(acc & 1u) << 63);
 }
