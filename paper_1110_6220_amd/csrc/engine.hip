@@ -127,14 +127,16 @@ __device__ __forceinline__ double root_pos(double x) {
 // range).  Contraction is otherwise off, so the remaining terms round as in
 // the oracle too.  a = b = +inf gives NaN, which the caller's minimum with the
 // old value turns into "no update".
-// FAITHFUL: the root within one unit in the last place (the exact method,
-// whose bar is a relative error against the oracle, not bit equality).
+// FAITHFUL (the exact method, whose bar is a relative error against the
+// oracle, not bit equality): the discriminant as one fma and the root within
+// one unit in the last place.
 template <bool FAITHFUL = false>
 __device__ __forceinline__ double local_update(double a, double b, double dl) {
   const double lo = wave::vmin(a, b);  // a and b are never NaN
   const double d = a - b;
   const double one = lo + dl;
-  const double two = fma(0.5, root_pos<FAITHFUL>(2.0 * dl * dl - d * d), 0.5 * (a + b));
+  const double x = FAITHFUL ? fma(-d, d, 2.0 * dl * dl) : 2.0 * dl * dl - d * d;
+  const double two = fma(0.5, root_pos<FAITHFUL>(x), 0.5 * (a + b));
   return (fabs(d) >= dl) ? one : two;
 }
 
@@ -145,7 +147,8 @@ __device__ __forceinline__ float local_update(float a, float b, float dl) {
   const float lo = wave::vmin(a, b);
   const double da = a, db = b, dd = da - db, ddl = dl;
   const float one = lo + dl;
-  const float two = (float)fma(0.5, root_pos<FAITHFUL>(2.0 * ddl * ddl - dd * dd), 0.5 * (da + db));
+  const double x = FAITHFUL ? fma(-dd, dd, 2.0 * ddl * ddl) : 2.0 * ddl * ddl - dd * dd;
+  const float two = (float)fma(0.5, root_pos<FAITHFUL>(x), 0.5 * (da + db));
   return (fabs(dd) >= ddl) ? one : two;
 }
 
