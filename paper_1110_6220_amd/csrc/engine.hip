@@ -1172,8 +1172,10 @@ __device__ void publish(const Engine& e, const Inst& I, const CellBox& B, int g,
     else if (side == 2) pub[2] = np;
     else pub[3] = np;
     const bool cr = ballot(c) != 0ull;
-    int ka;
-    const double kvv = wave_max(vmax, &ka);
+    // the boundary maximum only feeds the neighbour's key (schedules other
+    // than the dependency order)
+    int ka = -1;
+    const double kvv = e.dag ? -__builtin_huge_val() : wave_max(vmax, &ka);
     const uint32_t mo = M == kFhcm ? line_monotone(v, ok && v != INF, lane) : 3u;
     if (lane == side) {
       my_crit = cr;
