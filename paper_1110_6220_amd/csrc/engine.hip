@@ -672,8 +672,9 @@ __device__ uint32_t claim(const Engine& e, int g) {
 
 // One Gauss-Seidel sweep in direction dir (0 SW, 1 NW, 2 NE, 3 SE: x and y
 // ascending for SW, x ascending / y descending for NW, ...) over the w x hgt
-// tile in LDS (pitch P, halo at row/column 0 and w+1/hgt+1; P*P + lane is a
-// per-lane dummy slot).  Returns (wave-uniform) bit 0: some node decreased;
+// tile in LDS (pitch P, halo at row/column 0 and w+1/hgt+1; the halo's h/F
+// is +inf, see halo_to_masks).  Returns (wave-uniform) bit 0: some node
+// decreased;
 // bit 1 (bit 2): some node that decreased is now below its upwind neighbour
 // in x (in y) inside the tile.  Without bits 1 and 2 the tile is converged:
 // every node was
@@ -689,12 +690,16 @@ __device__ uint32_t claim(const Engine& e, int g) {
 // of step d-1 (for lane 0 the halo value, supplied as the DPP's out-of-range
 // operand); the upwind y-neighbour is the lane's own previous result, which
 // before the lane's first row holds the halo value below it.  The step is
-// branch-free: lanes without a node at this step store into their dummy slot
-// and keep their previous result.  The old values a step needs are read one
-// step ahead (none is a location the current step writes); the node's own old
-// value is the north value read for the step before.  min is v_min_f64, which
-// also maps the NaN that a = b = +inf produces to "no update", as the
-// oracle's explicit test does.
+// branch-free, and with no select: a lane whose row lies outside the tile
+// (clamped to a halo row), or which lies past the tile's width (on the halo
+// column beside the tile), updates a halo node, whose h/F of +inf makes the
+// update "no update", so it stores back the value it read and carries that
+// halo value as its upwind value, as the lane's first row needs.  The old
+// values a step needs are read one step ahead (none is a location the
+// current step writes); the node's own old value is the north value read for
+// the step before.  min is v_min_f64, which also maps the NaN that a = b =
+// +inf (or an infinite h/F) produces to "no update", as the oracle's explicit
+// test does.
 // STATS: also the lane's largest decrease (+inf for a node that left +inf)
 // and number of decreased nodes, into *mx and *cnt.  FAITHFUL: the update's
 // root within one unit in the last place (local_update).
@@ -712,29 +717,32 @@ __device__ __forceinline__ uint32_t sweep_tile_dir(T* tu, const T* td, int w, in
   const int sy = (dir == 0 || dir == 3) ? 1 : -1;
   const int rowstep = sy * P;
   const bool col_ok = lane < w;
-  const int i = col_ok ? (sx > 0 ? lane : w - 1 - lane) : 0;
+  // lanes past the tile's width walk the halo column on the sweep's far side
+  const int i = col_ok ? (sx > 0 ? lane : w - 1 - lane) : (sx > 0 ? w : -1);
   const int j0 = sy > 0 ? 0 : hgt - 1;
-  const int dummy = P * P + lane;
   const int nsteps = __builtin_amdgcn_readfirstlane(w + hgt - 1);  // the same on every lane
   // LDS index of the lane's node at sweep-order row t, clamped to the halo rows
   auto idx_t = [&](int t) {
     const int tc = t < -1 ? -1 : (t > hgt ? hgt : t);
     return (j0 + sy * tc + 1) * P + i + 1;
   };
-  int c = idx_t(-lane);
+  int c = idx_t(-lane), c1 = idx_t(1 - lane);  // the lane's positions at steps 0 and 1
   T prev = tu[idx_t(-1)];
   unsigned long long m_dec = 0ull, m_bx = 0ull, m_by = 0ull;
   const unsigned long long m_col = ballot(col_ok);
   // One step at d: the node's old value uo and its north value nv were read
   // before; the values of the next step are read into the *n references.
-  // The lane's row index moves by one row while t + 1 lies in [0, hgt].
+  // The lane's row index moves by one row while t + 1 lies in [0, hgt].  The
+  // value read as the next step's north value is the one at the lane's
+  // position two steps on (the north neighbour wherever the lane has a node),
+  // so that it is also that step's own old value where the row is clamped.
   auto step = [&](int d, const T& ev, const T& uo, const T& nv, const T& dl, const T& hw,
                   T& evn, T& nvn, T& dln, T& hwn) {
     const int t = d - lane;
     const bool valid = col_ok && (unsigned)t < (unsigned)hgt;
-    const int c1 = c + ((unsigned)(t + 1) <= (unsigned)hgt ? rowstep : 0);
+    const int c2 = c1 + ((unsigned)(t + 2) <= (unsigned)hgt ? rowstep : 0);
     evn = tu[c1 + sx];
-    nvn = tu[c1 + rowstep];
+    nvn = tu[c2];
     dln = td[c1];
     hwn = tu[c1 - sx];
     const T wv = shr1_or(prev, hw);
@@ -753,13 +761,14 @@ __device__ __forceinline__ uint32_t sweep_tile_dir(T* tu, const T* td, int w, in
       smx = dec && chg > smx ? chg : smx;
       scnt += dec ? 1 : 0;
     }
-    tu[valid ? c : dummy] = r;
-    prev = valid ? r : prev;
+    tu[c] = r;
+    prev = r;
     c = c1;
+    c1 = c2;
   };
   // two steps per iteration (the step count is wave-uniform): the values
   // read one step ahead alternate between two register sets
-  T evA = tu[c + sx], nvA = tu[c + rowstep], uoA = tu[c], dlA = td[c], hwA = tu[c - sx];
+  T evA = tu[c + sx], nvA = tu[c1], uoA = tu[c], dlA = td[c], hwA = tu[c - sx];
   T evB, nvB, dlB, hwB;
   int d = 0;
   for (; d + 1 < nsteps; d += 2) {
@@ -788,6 +797,38 @@ __device__ uint32_t sweep_tile(T* tu, const T* td, int w, int hgt, int dir, int 
     case 1: return sweep_tile_dir<T, P, DIRECTIONAL, STATS, 1, FAITHFUL>(tu, td, w, hgt, lane, mx, cnt);
     case 2: return sweep_tile_dir<T, P, DIRECTIONAL, STATS, 2, FAITHFUL>(tu, td, w, hgt, lane, mx, cnt);
     default: return sweep_tile_dir<T, P, DIRECTIONAL, STATS, 3, FAITHFUL>(tu, td, w, hgt, lane, mx, cnt);
+  }
+}
+
+// After a tile load: records per side which outside nodes are accessible
+// (finite h/F) as a mask along the side (bit k: row k for W/E, column k for
+// S/N) in hacc[0..3] (W, E, S, N; when hacc is given), and sets the halo's
+// h/F, corners included, to +inf, which the sweep relies on (sweep_tile_dir).
+// One wave, after every part of the load has landed.
+template <typename T, int P>
+__device__ void halo_to_masks(T* td, int w, int hgt, int lane, unsigned long long* hacc) {
+  lane = opaque_lane(lane);
+  const T INF = inf_v<T>();
+  const bool rv = lane < hgt, cv = lane < w;
+  const int iw = (lane + 1) * P, ie = iw + w + 1, is = lane + 1, in = (hgt + 1) * P + lane + 1;
+  const T dW = rv ? td[iw] : INF, dE = rv ? td[ie] : INF;
+  const T dS = cv ? td[is] : INF, dN = cv ? td[in] : INF;
+  const unsigned long long mW = ballot(dW != INF), mE = ballot(dE != INF);
+  const unsigned long long mS = ballot(dS != INF), mN = ballot(dN != INF);
+  if (rv) {
+    td[iw] = INF;
+    td[ie] = INF;
+  }
+  if (cv) {
+    td[is] = INF;
+    td[in] = INF;
+  }
+  if (lane < 4) td[lane == 0 ? 0 : lane == 1 ? w + 1 : lane == 2 ? (hgt + 1) * P : (hgt + 1) * P + w + 1] = INF;
+  if (hacc && lane == 0) {
+    hacc[0] = mW;
+    hacc[1] = mE;
+    hacc[2] = mS;
+    hacc[3] = mN;
   }
 }
 
@@ -1129,7 +1170,7 @@ __device__ uint32_t line_monotone(T v, bool fin, int lane) {
 // check of Algorithm FHCM), and lowers their cell values (eq. cell_value).
 template <typename T, int P, int M, bool RINGS>
 __device__ void publish(const Engine& e, const Inst& I, const CellBox& B, int g, T* tu,
-                        const T* td, T pub[4], bool first, int lane) {
+                        const T* td, const unsigned long long* hacc, T pub[4], bool first, int lane) {
   lane = opaque_lane(lane);
   const T INF = inf_v<T>();
   T* u = static_cast<T*>(I.u);
@@ -1163,7 +1204,7 @@ __device__ void publish(const Engine& e, const Inst& I, const CellBox& B, int g,
         const int jj = vert ? B.y0 + lane : (side == 2 ? B.y0 : B.y1 - 1);
         st_coh(u + (size_t)jj * I.nx + ii, v);
       }
-      c = changed && td[idx_out] != INF && v < tu[idx_out];
+      c = changed && ((hacc[side] >> lane) & 1ull) && v < tu[idx_out];
       if (v != INF) vmax = (double)v;
     }
     const T np = ok ? v : ps;
@@ -1269,11 +1310,11 @@ __device__ void release_later(const Engine& e, int g, const Inst& I, const CellB
 // ~70-90 cycles.
 constexpr int kSolveWaves1 = 4;  // waves per worker for single problems
 
-// LDS of a tile with pitch P: one guard row, the (P x P) tile with its halo,
-// 64 per-lane dummy slots and one guard element.  The sweep reads the next
-// step's operands one step ahead, and on its last steps that read reaches one
-// row beyond the far halo row (south: row -1; north: up to P*P + P - 2); the
-// guards keep those reads, whose values are discarded, inside the array.
+// LDS of a tile with pitch P: one guard row, the (P x P) tile with its halo
+// and 65 guard elements.  The sweep reads the next step's operands one step
+// ahead, and on its last steps that read reaches one row beyond the far halo
+// row (south: row -1, down to -P; north: up to P*P + 64 for 64-node cells);
+// the guards keep those reads, whose values are discarded, inside the array.
 template <int P>
 struct TileLds {
   static constexpr int kBefore = P;
@@ -1286,9 +1327,10 @@ template <typename T, int S, int M, int NW, bool HEAP = false>
 __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
   constexpr int P = S + 2;
   __shared__ T tu_mem[TileLds<P>::kSize];
-  T* const tu = tu_mem + TileLds<P>::kBefore;  // tile + per-lane dummy slots
+  T* const tu = tu_mem + TileLds<P>::kBefore;  // the tile with its halo
   __shared__ T td[P * P];
   __shared__ TileJob job;
+  __shared__ unsigned long long hacc[4];  // accessible outside nodes per side
   const int lane = threadIdx.x & 63;
   if constexpr (NW > 1) {
     if (threadIdx.x >= 64) {  // helper wave
@@ -1320,6 +1362,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
       load_tile_v<T, P, NW>(tu, td, I, B, lane, with_interior, fresh, 0);
       __syncthreads();  // B: every part has landed
     }
+    halo_to_masks<T, P>(td, B.w, B.hgt, lane, hacc);
   };
   auto tile_store = [&](const Inst& I, const CellBox& B, int g) {
     if constexpr (NW == 1) {
@@ -1436,7 +1479,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
             if (ch) nsweeps++; else nchecks++;
           }
         tick(e, ph, kPhSweep, &t0);
-        publish<T, P, M, (NW == 1)>(e, I, B, g, tu, td, pub, is_first, lane);
+        publish<T, P, M, (NW == 1)>(e, I, B, g, tu, td, hacc, pub, is_first, lane);
         is_first = false;
         tick(e, ph, kPhPublish, &t0);
       } else {
@@ -1456,7 +1499,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
           if (ch) nsweeps++; else nchecks++;
           tick(e, ph, kPhSweep, &t0);
           if (e.eager && (ch || is_first)) {
-            publish<T, P, M, (NW == 1)>(e, I, B, g, tu, td, pub, is_first, lane);
+            publish<T, P, M, (NW == 1)>(e, I, B, g, tu, td, hacc, pub, is_first, lane);
             is_first = false;
             tick(e, ph, kPhPublish, &t0);
           }
@@ -1482,7 +1525,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
           }
         }
         if (!e.eager) {
-          publish<T, P, M, (NW == 1)>(e, I, B, g, tu, td, pub, is_first, lane);
+          publish<T, P, M, (NW == 1)>(e, I, B, g, tu, td, hacc, pub, is_first, lane);
           is_first = false;
           tick(e, ph, kPhPublish, &t0);
         }
@@ -1542,6 +1585,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve(Engine e) {
       done1 = 1;
       order_acquire();
       load_tile_v<T, P, 1, 2>(tu, td, I, B, lane, false, false, 0);  // fresh halo only
+      halo_to_masks<T, P>(td, B.w, B.hgt, lane, hacc);
     }
     if (lane == 0) {
       if (NW == 1 && e.ninst > 1) {  // per-instance statistics of a batch (visits: count_visit)
@@ -2172,6 +2216,7 @@ __global__ __launch_bounds__(64) void k_sweep_diag(Engine e, SweepArgs a) {
   }
   const CellBox B = cell_box(I, g);
   load_tile<T, P>(tu, td, I, B, lane, true);
+  halo_to_masks<T, P>(td, B.w, B.hgt, lane, nullptr);
   double mx = 0.0;
   int cnt = 0;
   sweep_tile<T, P, false, true>(tu, td, B.w, B.hgt, a.dir, lane, &mx, &cnt);
@@ -2279,6 +2324,8 @@ __global__ __launch_bounds__(64) void k_probe_sweep(int sweeps, unsigned long lo
     tu[k] = inf_v<T>();
     td[k] = (T)(1.0 / S);
   }
+  __syncthreads();
+  halo_to_masks<T, P>(td, S, S, lane, nullptr);
   __syncthreads();
   if (lane == 0) tu[P + 1] = (T)0;  // the exit node
   __syncthreads();
