@@ -477,8 +477,9 @@ static int default_workers(const Workspace* ws, int64_t J, int tile, int dtype, 
 constexpr unsigned kTraceCap = 1u << 20;  // trace records (EIK_TRACE)
 // Cell side of the cell engine when it solves a coarse grid (more than
 // kCoarseJacobiMax coarse cells) for the order of the exact method: 16-node
-// cells let several waves share the coarse front (the 64 x 64 coarse grid of
-// the 4097^2 headline: ~0.47 ms in one 64-node cell, ~0.1 ms less in 16).
+// cells let several waves share the coarse front (the 65 x 65 coarse grid of
+// the 4097^2 checkerboard, before Jacobi took grids of that size: ~0.47 ms
+// in one 64-node cell, 0.34 ms in 16-node cells, 0.07 ms more in 32 or 64).
 #ifndef EIK_COARSE_ENGINE_CELL
 #define EIK_COARSE_ENGINE_CELL 16
 #endif
@@ -745,12 +746,16 @@ int run(int n, const eik_problem* probs, const eik_opts& o, eik_stats* stats, Ru
   // orders its cells by Fast Marching on it, as the method prescribes; the
   // other methods use the order only as a schedule and take a parallel exact
   // solve: Jacobi iteration in one workgroup per problem for coarse grids of
-  // up to kCoarseJacobiMax cells, else the cell engine (coarse_engine)
+  // up to 1024 cells (a single problem: up to kCoarseJacobiMax), else the
+  // cell engine (coarse_engine).  The 65 x 65 coarse grid of the 4097^2
+  // checkerboard: 0.34 ms in the cell engine, ~0.26 ms by Jacobi; batches
+  // keep the cell engine above 1024 cells (served mazes, whose coarse paths
+  // wind, were ~3% slower by Jacobi)
   bool have_coarse = false, coarse_engine = false;
   const bool fmm = method == EIK_FMSM;
   int64_t max_coarse = 0;
   for (int k = 0; k < n; ++k) max_coarse = std::max<int64_t>(max_coarse, (int64_t)inst[k].kx * inst[k].ky);
-  const bool jacobi = !fmm && max_coarse <= kCoarseJacobiMax;
+  const bool jacobi = !fmm && max_coarse <= (n == 1 ? kCoarseJacobiMax : 1024);
   int cext = 0, fmm_lds = 0;
   FmmSpill spill{};
   if (dag) {

@@ -203,9 +203,11 @@ hipError_t launch_residual(const Engine& e, int64_t max_nodes, hipStream_t strea
 hipError_t launch_coarse_inputs(const Engine& fine, const CoarseOut* co_dev, int max_cells,
                                 hipStream_t stream);
 // Exact solve of every problem's coarse grid (values into co[k].u) when no
-// problem has more than kCoarseJacobiMax coarse cells; max_cells = the
-// largest count.
-constexpr int kCoarseJacobiMax = 1024;
+// problem has more than kCoarseJacobiMax coarse cells (one workgroup of up
+// to 1024 threads per problem, up to kCoarseJacobiPer cells per thread);
+// max_cells = the largest count.
+constexpr int kCoarseJacobiPer = 8;
+constexpr int kCoarseJacobiMax = 1024 * kCoarseJacobiPer;
 hipError_t launch_coarse_jacobi(const Engine& fine, const CoarseOut* co_dev, int max_cells,
                                 hipStream_t stream);
 // Fast Marching on the coarse grid of every problem (FMSM Part I): values

@@ -2059,64 +2059,78 @@ __device__ void coarse_fmm(const CoarseOut& C, int kx, int ky, double hc, int la
   }
 }
 
-// Exact solve of a small coarse grid (at most kCoarseJacobiMax cells) by
-// Jacobi iteration, one workgroup per problem, one cell per thread: every
-// iteration applies the local update of Section 2 to all cells at once from
-// the previous iterate (two LDS buffers, one barrier per iteration) until no
-// value decreases.  The update is causal (a new value exceeds the values it
-// is computed from), so a value is final once the chain of cells it depends
-// on is, and at most J + 1 iterations are needed.  The exact, HCM and FHCM
+// Exact solve of a coarse grid of at most kCoarseJacobiMax cells by Jacobi
+// iteration, one workgroup per problem, NPT cells per thread (1 up to 1024
+// cells, else kCoarseJacobiPer with 1024 threads): every iteration applies
+// the local update of Section 2 to all cells at once from the previous
+// iterate (two LDS buffers, one barrier per iteration) until no value
+// decreases.  The update is causal (a new value exceeds the values it is
+// computed from), so a value is final once the chain of cells it depends on
+// is, and at most J + 1 iterations are needed.  The exact, HCM and FHCM
 // methods use these values only to order the fine cells.
-__global__ __launch_bounds__(kCoarseJacobiMax) void k_coarse_jacobi(Engine e, const CoarseOut* co) {
-  __shared__ double ub[2][kCoarseJacobiMax];
+template <int NPT>
+__global__ __launch_bounds__(1024) void k_coarse_jacobi(Engine e, const CoarseOut* co) {
+  __shared__ double ub[2][1024 * NPT];
   __shared__ int dec_any[3];  // iteration it reports decreases in dec_any[it % 3]
   const int k = blockIdx.x;
   const Inst I = inst_at(e, k);
   const CoarseOut C = co[k];
   const int kx = I.kx, ky = I.ky, J = kx * ky;
   const double hc = (double)I.s * I.h;
-  const int c = threadIdx.x;
   const double inf = __builtin_huge_val();
   // dl = h^c / F^c on coarse cells that are updated: accessible and not exit cells
-  double dl = inf, u0 = inf;
-  int cx = 0, cy = 0;
-  if (c < J) {
-    cx = c % kx;
-    cy = c / kx;
-    if (C.mask[c]) {
-      u0 = C.q[c];
-      if (!(u0 < inf)) dl = hc / C.F[c];
+  double dl[NPT], u[NPT];
+  int cx[NPT], cy[NPT];
+#pragma unroll
+  for (int m = 0; m < NPT; ++m) {
+    const int c = threadIdx.x + m * (int)blockDim.x;
+    dl[m] = inf;
+    u[m] = inf;
+    cx[m] = cy[m] = 0;
+    if (c < J) {
+      cx[m] = c % kx;
+      cy[m] = c / kx;
+      if (C.mask[c]) {
+        u[m] = C.q[c];
+        if (!(u[m] < inf)) dl[m] = hc / C.F[c];
+      }
+      ub[0][c] = u[m];
     }
-    ub[0][c] = u0;
   }
-  if (c < 3) dec_any[c] = 0;
+  if (threadIdx.x < 3) dec_any[threadIdx.x] = 0;
   __syncthreads();
-  double u = u0;
-  const bool live = c < J && dl < inf;
   for (int it = 0; it <= J; ++it) {
     const double* cur = ub[it & 1];
     double* nxt = ub[(it + 1) & 1];
     bool dec = false;
-    if (live) {
-      const double l = cx > 0 ? cur[c - 1] : inf, r = cx + 1 < kx ? cur[c + 1] : inf;
-      const double d = cy > 0 ? cur[c - kx] : inf, t = cy + 1 < ky ? cur[c + kx] : inf;
-      const double a = l < r ? l : r, b = d < t ? d : t;
-      const double v = local_update(a, b, dl);
-      if (v < u) {
-        u = v;
-        dec = true;
+#pragma unroll
+    for (int m = 0; m < NPT; ++m) {
+      const int c = threadIdx.x + m * (int)blockDim.x;
+      if (c < J && dl[m] < inf) {
+        const double l = cx[m] > 0 ? cur[c - 1] : inf, r = cx[m] + 1 < kx ? cur[c + 1] : inf;
+        const double d = cy[m] > 0 ? cur[c - kx] : inf, t = cy[m] + 1 < ky ? cur[c + kx] : inf;
+        const double a = l < r ? l : r, b = d < t ? d : t;
+        const double v = local_update(a, b, dl[m]);
+        if (v < u[m]) {
+          u[m] = v;
+          dec = true;
+        }
       }
+      if (c < J) nxt[c] = u[m];
     }
-    if (c < J) nxt[c] = u;
     // the flag of iteration it + 1 was last read after the barrier of
     // iteration it - 2, which every thread has passed
     const int f = it % 3;
-    if (c == 0) dec_any[f == 2 ? 0 : f + 1] = 0;
+    if (threadIdx.x == 0) dec_any[f == 2 ? 0 : f + 1] = 0;
     if (dec) dec_any[f] = 1;
     __syncthreads();
     if (!dec_any[f]) break;
   }
-  if (c < J) C.u[c] = u;
+#pragma unroll
+  for (int m = 0; m < NPT; ++m) {
+    const int c = threadIdx.x + m * (int)blockDim.x;
+    if (c < J) C.u[c] = u[m];
+  }
 }
 
 __global__ __launch_bounds__(64) void k_coarse_fmm(Engine e, const CoarseOut* co, int lds_cells,
@@ -2481,9 +2495,14 @@ hipError_t launch_sweep_seed(const Engine& e, int nsrc, uint8_t* dirty, hipStrea
 hipError_t launch_coarse_jacobi(const Engine& fine, const CoarseOut* co_dev, int max_cells,
                                 hipStream_t stream) {
   if (max_cells < 1) return hipSuccess;
-  const int threads = (max_cells + 63) / 64 * 64;
-  if (threads > kCoarseJacobiMax) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_coarse_jacobi, dim3(fine.ninst), dim3(threads), 0, stream, fine, co_dev);
+  if (max_cells > kCoarseJacobiMax) return hipErrorInvalidValue;
+  if (max_cells <= 1024) {
+    const int threads = (max_cells + 63) / 64 * 64;
+    hipLaunchKernelGGL((k_coarse_jacobi<1>), dim3(fine.ninst), dim3(threads), 0, stream, fine, co_dev);
+  } else {
+    hipLaunchKernelGGL((k_coarse_jacobi<kCoarseJacobiPer>), dim3(fine.ninst), dim3(1024), 0, stream,
+                       fine, co_dev);
+  }
   return hipGetLastError();
 }
 
