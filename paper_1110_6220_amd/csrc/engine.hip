@@ -1755,7 +1755,9 @@ __device__ __forceinline__ int cell_of_node(const Inst& I, int i, int j) {
 }
 
 // u = +inf, or the dense exit costs (coarse problems: those nodes are frozen
-// and, without dependency ordering, their cells queued).
+// and, without dependency ordering, their cells queued).  A pass of its own
+// after k_prep_nodes: u is often the caller's output, which a problem that
+// fails validation leaves untouched.
 template <typename T>
 __global__ void k_init_u(Engine e) {
   if (get_err(e.ctl)) return;
@@ -2159,46 +2161,66 @@ __global__ __launch_bounds__(64) void k_coarse_fmm(Engine e, const CoarseOut* co
 // cells the coarse front does not reach last, by index.  Each cell counts
 // the accessible neighbours that precede it; a cell with none is queued.
 __global__ void k_dag(Engine e, const CoarseOut* co) {
-  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < e.ncells; g += gridDim.x * blockDim.x) {
-    const int k = inst_index(e, g);
-    const Inst I = inst_at(e, k);
-    const CoarseOut C = co[k];
-    const int c = g - I.cell0;
-    if (!C.mask[c]) {
-      e.ord[g] = kOrdEmpty;
-      e.st[g] = kDone1;
-      continue;
-    }
-    auto cls = [&](int x) { return C.q[x] < __builtin_huge_val() ? 0 : 1; };
-    auto val = [&](int x) { return C.q[x] < __builtin_huge_val() ? C.q[x] : C.u[x]; };
-    auto before = [&](int x, int y) {  // does cell x precede cell y?
-      if (C.rank) return C.rank[x] < C.rank[y];
-      const int cxx = cls(x), cyy = cls(y);
-      if (cxx != cyy) return cxx < cyy;
-      const double vx = val(x), vy = val(y);
-      if (vx != vy) return vx < vy;
-      return x < y;
-    };
-    const int cx = c % I.kx, cy = c / I.kx;
-    uint8_t o = (cls(c) == 0 || !(val(c) < __builtin_huge_val())) ? kOrdConverge : 0;
-    if (cls(c) == 0) o |= kOrdSource;
-    int n = 0;
-    for (int side = 0; side < 4; ++side) {
-      int nb = -1;
-      if (side == 0 && cx > 0) nb = c - 1;
-      if (side == 1 && cx + 1 < I.kx) nb = c + 1;
-      if (side == 2 && cy > 0) nb = c - I.kx;
-      if (side == 3 && cy + 1 < I.ky) nb = c + I.kx;
-      if (nb < 0 || !C.mask[nb]) continue;
-      if (before(nb, c)) {
-        o |= (uint8_t)(1u << side);
-        n++;
+  const int lane = threadIdx.x & 63;
+  // uniform trip count: every lane of a wave takes part in the aggregation
+  for (int g0 = blockIdx.x * blockDim.x; g0 < e.ncells; g0 += gridDim.x * blockDim.x) {
+    const int g = g0 + (int)threadIdx.x;
+    int k = -1, n = 0;
+    if (g < e.ncells) {
+      k = inst_index(e, g);
+      const Inst I = inst_at(e, k);
+      const CoarseOut C = co[k];
+      const int c = g - I.cell0;
+      if (!C.mask[c]) {
+        e.ord[g] = kOrdEmpty;
+        e.st[g] = kDone1;
+        k = -1;
+      } else {
+        auto cls = [&](int x) { return C.q[x] < __builtin_huge_val() ? 0 : 1; };
+        auto val = [&](int x) { return C.q[x] < __builtin_huge_val() ? C.q[x] : C.u[x]; };
+        auto before = [&](int x, int y) {  // does cell x precede cell y?
+          if (C.rank) return C.rank[x] < C.rank[y];
+          const int cxx = cls(x), cyy = cls(y);
+          if (cxx != cyy) return cxx < cyy;
+          const double vx = val(x), vy = val(y);
+          if (vx != vy) return vx < vy;
+          return x < y;
+        };
+        const int cx = c % I.kx, cy = c / I.kx;
+        uint8_t o = (cls(c) == 0 || !(val(c) < __builtin_huge_val())) ? kOrdConverge : 0;
+        if (cls(c) == 0) o |= kOrdSource;
+        for (int side = 0; side < 4; ++side) {
+          int nb = -1;
+          if (side == 0 && cx > 0) nb = c - 1;
+          if (side == 1 && cx + 1 < I.kx) nb = c + 1;
+          if (side == 2 && cy > 0) nb = c - I.kx;
+          if (side == 3 && cy + 1 < I.ky) nb = c + I.kx;
+          if (nb < 0 || !C.mask[nb]) continue;
+          if (before(nb, c)) {
+            o |= (uint8_t)(1u << side);
+            n++;
+          }
+        }
+        e.ord[g] = o;
+        e.deps[g] = n;
       }
     }
-    e.ord[g] = o;
-    e.deps[g] = n;
-    cell_active(e, g);
-    if (n == 0 && !get_err(e.ctl)) release_first(e, g);
+    // the active counts (cell_active) of the wave's accessible cells: one
+    // atomic per problem among them instead of one per cell, all before any
+    // of them is queued (the solver starts after this kernel)
+    unsigned long long todo = ballot(k >= 0);
+    while (todo) {
+      const int leader = __builtin_ctzll(todo);
+      const int kl = __shfl(k, leader, 64);
+      const unsigned long long same = ballot(k == kl);
+      if (lane == leader) {
+        const unsigned long long cnt = (unsigned long long)__builtin_popcountll(same);
+        if (e.ninst > 1) atomic_add_relaxed(&e.iact[kl], cnt);
+        else atomic_add_relaxed(&e.ctl->active, cnt);
+      }
+      todo &= ~same;
+    }
+    if (k >= 0 && n == 0 && !get_err(e.ctl)) release_first(e, g);
   }
 }
 
