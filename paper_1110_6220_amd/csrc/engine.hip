@@ -2404,7 +2404,10 @@ hipError_t launch_prepare(const Engine& e, int64_t max_nodes, hipStream_t stream
   const int gy = e.ninst;
   const int64_t cwork = (int64_t)e.ncells > (int64_t)e.q.nslot ? (int64_t)e.ncells : (int64_t)e.q.nslot;
   hipLaunchKernelGGL(k_prep_cells, dim3(grid_for(cwork, 256, 4096)), dim3(256), 0, stream, e);
-  const dim3 gn(grid_for(max_nodes, 256, gy > 1 ? 512 : 8192), gy);
+  // per problem of a batch at most 128 blocks (grid-stride): with 512 most
+  // blocks of the small problems found no node (256-instance batch:
+  // 3.65 -> 3.57 ms per batch)
+  const dim3 gn(grid_for(max_nodes, 256, gy > 1 ? 128 : 8192), gy);
   if (e.dtype == 0) hipLaunchKernelGGL(k_prep_nodes<double>, gn, dim3(256), 0, stream, e);
   else hipLaunchKernelGGL(k_prep_nodes<float>, gn, dim3(256), 0, stream, e);
   if (e.dtype == 0) hipLaunchKernelGGL(k_init_u<double>, gn, dim3(256), 0, stream, e);
